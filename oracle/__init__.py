@@ -1,0 +1,249 @@
+"""CPU oracle for VRP-RPD — TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct reference implementations of everything the
+GPU path computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  It shares no code with
+the HIP library (``paper_2602_23685_amd``) and never imports it.
+
+The C core (``oracle/*.c``) is built with gcc into ``oracle/liboracle.so`` by
+:func:`build`; these wrappers marshal numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = ["eval.c", "decode.c", "scan.c", "brkga.c", "alns.c"]
+
+BAD_COVER, LOAD, RES, DEADLOCK, BAD_KEY, BAD_TUPLE = 1, 2, 4, 8, 16, 32
+MIN_PRELOAD, FULL_START = 0, 1
+INT32_MAX = 2**31 - 1
+INT64_MAX = 2**63 - 1
+
+TUPLE_DTYPE = np.dtype([("c", "<u2"), ("vD", "u1"), ("vP", "u1"), ("pD", "<u2"), ("pP", "<u2")])
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle's C sources with gcc (plain -O2, no FP contraction)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+           "-o", tmp] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Inst(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("k", C.c_int32), ("R", C.c_int32),
+                ("load_model", C.c_int32), ("d", C.c_void_p), ("p", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _declare(L):
+    P = C.c_void_p
+    L.orc_eval.restype = C.c_uint32
+    L.orc_eval.argtypes = [P, C.c_int, P, P, P, P]
+    L.orc_eval_dag.restype = C.c_uint32
+    L.orc_eval_dag.argtypes = [P, P, P, P, P]
+    L.orc_eval_batch.restype = None
+    L.orc_eval_batch.argtypes = [P, C.c_int, C.c_int64, P, P, P, P, P, P]
+    L.orc_insert_scan.restype = None
+    L.orc_insert_scan.argtypes = [P, P, P, C.c_int64, P, C.c_int32, P, P, P, P]
+    L.orc_decode.restype = C.c_uint32
+    L.orc_decode.argtypes = [P, P, P, P, P, P, P, P]
+    L.orc_philox.restype = None
+    L.orc_philox.argtypes = [P, P, P]
+    L.orc_brkga_evolve.restype = None
+    L.orc_brkga_evolve.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_int32,
+                                   C.c_uint32, C.c_uint64, C.c_uint32, P, P, P]
+    L.orc_brkga_warm_start.restype = None
+    L.orc_brkga_warm_start.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, P, P]
+    if hasattr(L, "orc_alns_run"):
+        _declare_alns(L)
+
+
+def _declare_alns(L):
+    P = C.c_void_p
+    L.orc_alns_run.restype = C.c_int32
+    L.orc_alns_run.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, C.c_int32, P, P, P, P, P]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class OInst:
+    """Holds the instance arrays alive for the duration of oracle calls."""
+
+    def __init__(self, inst):
+        self.n, self.m, self.k, self.R = inst.n, inst.m, inst.k, inst.R
+        self.load_model = inst.load_model
+        self.d = np.ascontiguousarray(inst.d, dtype=np.int32)
+        self.p = np.ascontiguousarray(inst.p, dtype=np.int32)
+        self.s = _Inst(self.n, self.m, self.k, self.R, self.load_model,
+                       self.d.ctypes.data, self.p.ctypes.data)
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _oinst(inst):
+    return inst if isinstance(inst, OInst) else OInst(inst)
+
+
+def eval_one(inst, ops, rt_end, allow_partial=False, times=False, dag=False):
+    """Evaluate one candidate.  Returns (makespan, status) or, with times,
+    (makespan, status, op_time[L])."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    mk = np.zeros(1, dtype=np.int32)
+    L = int(rt[-1]) if len(rt) else 0
+    tt = np.full(max(L, 1), -1, dtype=np.int64) if times else None
+    if dag:
+        st = lib().orc_eval_dag(oi.ref, _ptr(ops), _ptr(rt), _ptr(mk), _ptr(tt))
+    else:
+        st = lib().orc_eval(oi.ref, int(allow_partial), _ptr(ops), _ptr(rt), _ptr(mk), _ptr(tt))
+    if times:
+        return int(mk[0]), int(st), tt[:L]
+    return int(mk[0]), int(st)
+
+
+def eval_batch(inst, ops, rt_end, op_off=None, rt_off=None, allow_partial=False):
+    """Evaluate B candidates.  ops: [B, 2n] (or flat with op_off), rt_end: [B, m]
+    (or flat with rt_off).  Returns (makespan int32[B], status uint32[B])."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    if op_off is None:
+        B = ops.shape[0] if ops.ndim == 2 else len(ops) // (2 * oi.n)
+    else:
+        op_off = np.ascontiguousarray(op_off, dtype=np.int64)
+        B = len(op_off)
+    if rt_off is not None:
+        rt_off = np.ascontiguousarray(rt_off, dtype=np.int64)
+    mk = np.zeros(B, dtype=np.int32)
+    st = np.zeros(B, dtype=np.uint32)
+    lib().orc_eval_batch(oi.ref, int(allow_partial), B, _ptr(op_off), _ptr(ops), _ptr(rt_off),
+                         _ptr(rt), _ptr(mk), _ptr(st))
+    return mk, st
+
+
+def insert_scan(inst, base_ops, base_rt, tuples, seg_off):
+    oi = _oinst(inst)
+    base_ops = np.ascontiguousarray(base_ops, dtype=np.uint16)
+    base_rt = np.ascontiguousarray(base_rt, dtype=np.uint16)
+    tuples = np.ascontiguousarray(tuples).astype(TUPLE_DTYPE, copy=False)
+    seg_off = np.ascontiguousarray(seg_off, dtype=np.int64)
+    T, S = len(tuples), len(seg_off) - 1
+    mk = np.zeros(max(T, 1), dtype=np.int32)
+    st = np.zeros(max(T, 1), dtype=np.uint32)
+    top = np.zeros((max(S, 1), 3), dtype=np.int64)
+    lib().orc_insert_scan(oi.ref, _ptr(base_ops), _ptr(base_rt), T, _ptr(tuples), S,
+                          _ptr(seg_off), _ptr(mk), _ptr(st), _ptr(top))
+    return mk[:T], st[:T], top[:S]
+
+
+def decode(inst, prio, hint=None, want_ops=False):
+    """Decode one chromosome.  Returns dict(fitness, makespan, unscheduled,
+    status[, ops, rt_end])."""
+    oi = _oinst(inst)
+    prio = np.ascontiguousarray(prio, dtype=np.float32)
+    hint = None if hint is None else np.ascontiguousarray(hint, dtype=np.float32)
+    f = np.zeros(1, dtype=np.int64)
+    mk = np.zeros(1, dtype=np.int32)
+    un = np.zeros(1, dtype=np.int32)
+    ops = np.zeros(2 * oi.n, dtype=np.uint16) if want_ops else None
+    rt = np.zeros(oi.m, dtype=np.uint16) if want_ops else None
+    st = lib().orc_decode(oi.ref, _ptr(prio), _ptr(hint), _ptr(f), _ptr(mk), _ptr(un),
+                          _ptr(ops), _ptr(rt))
+    out = dict(fitness=int(f[0]), makespan=int(mk[0]), unscheduled=int(un[0]), status=int(st))
+    if want_ops:
+        out["ops"] = ops[: int(rt[-1])] if rt[-1] else ops[:0]
+        out["rt_end"] = rt
+    return out
+
+
+def decode_batch(inst, prio, hint=None):
+    oi = _oinst(inst)
+    B = prio.shape[0]
+    f = np.zeros(B, dtype=np.int64)
+    mk = np.zeros(B, dtype=np.int32)
+    un = np.zeros(B, dtype=np.int32)
+    st = np.zeros(B, dtype=np.uint32)
+    for b in range(B):
+        r = decode(oi, prio[b], None if hint is None else hint[b])
+        f[b], mk[b], un[b], st[b] = r["fitness"], r["makespan"], r["unscheduled"], r["status"]
+    return f, mk, un, st
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def rho_threshold(rho: float) -> int:
+    """Integer threshold of the Bernoulli(rho) draw: (w >> 8) < floor(rho * 2^24)."""
+    return int(np.floor(rho * 16777216.0))
+
+
+def brkga_sizes(Np, elite_frac=0.15, mutant_frac=0.15):
+    return int(np.floor(elite_frac * Np)), int(np.floor(mutant_frac * Np))
+
+
+def brkga_evolve(prio, hint, fitness, n_elite, n_mutant, rho_thr24, seed, generation):
+    prio = np.ascontiguousarray(prio, dtype=np.float32)
+    Np, G = prio.shape
+    hint = None if hint is None else np.ascontiguousarray(hint, dtype=np.float32)
+    fitness = np.ascontiguousarray(fitness, dtype=np.int64)
+    po = np.zeros_like(prio)
+    ho = None if hint is None else np.zeros_like(hint)
+    rank = np.zeros(Np, dtype=np.int32)
+    lib().orc_brkga_evolve(Np, G, _ptr(prio), _ptr(hint), _ptr(fitness), n_elite, n_mutant,
+                           rho_thr24, seed & (2**64 - 1), generation, _ptr(po), _ptr(ho),
+                           _ptr(rank))
+    return po, ho, rank
+
+
+def brkga_warm_start(inst, ops, rt_end, Np, n_warm, n_variants, seed):
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    G = 2 * oi.n
+    po = np.zeros((Np, G), dtype=np.float32)
+    ho = np.zeros((Np, G), dtype=np.float32)
+    lib().orc_brkga_warm_start(oi.ref, _ptr(ops), _ptr(rt), Np, n_warm, n_variants,
+                               seed & (2**64 - 1), _ptr(po), _ptr(ho))
+    return po, ho
+
+
+def int32_safe(inst) -> bool:
+    """Whether every time of every schedule fits in int32: a longest path
+    has at most one incoming edge per op (travel or processing) plus the
+    return leg."""
+    dmax = int(np.max(inst.d))
+    return (2 * inst.n + 1) * dmax + int(np.sum(inst.p, dtype=np.int64)) < 2**31 - 1

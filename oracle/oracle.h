@@ -1,0 +1,80 @@
+/*
+ * CPU oracle for VRP-RPD makespan evaluation — TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded C that states what the GPU path must compute.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header, table or helper with the HIP
+ * library; the two are compared on the same seeded inputs.
+ *
+ * Problem statement and timing model: Section 3 (problem formulation) and the
+ * MILP of Section 3.1, Eq. (1)-(23).  Decoder: Section 4.4.2, Algorithm 2.
+ * Genetic operators: Section 4.4.3.  ALNS: Section 4.2, Algorithm 1.
+ */
+#ifndef VRPRPD_ORACLE_H
+#define VRPRPD_ORACLE_H
+#include <stdint.h>
+
+#define ORC_BAD_COVER 1u
+#define ORC_LOAD 2u
+#define ORC_RES 4u
+#define ORC_DEADLOCK 8u
+#define ORC_BAD_KEY 16u
+#define ORC_BAD_TUPLE 32u
+
+#define ORC_MIN_PRELOAD 0
+#define ORC_FULL_START 1
+
+typedef struct {
+    int32_t n, m, k, R, load_model;
+    const int32_t* d; /* (n+1)*(n+1) row-major travel times */
+    const int32_t* p; /* n+1 processing times, p[0] = 0 */
+} orc_inst;
+
+/* Sweep evaluator (definition).  ops: L codes (c<<1 | isPickup) grouped by
+ * vehicle; rt_end: m cumulative route ends.  op_time (nullable, L entries)
+ * receives each op's time: the drop time for D, the pickup (departure) time
+ * for P.  Returns status bits; *makespan = INT32_MAX when BAD_COVER or
+ * DEADLOCK. */
+uint32_t orc_eval(const orc_inst* I, int allow_partial, const uint16_t* ops,
+                  const uint16_t* rt_end, int32_t* makespan, int64_t* op_time);
+
+/* Independent second evaluator of the timing part only: builds the operation
+ * graph explicitly and runs Kahn's topological order with a longest-path
+ * pass.  Returns 0 or ORC_DEADLOCK (a cycle); cover must already hold. */
+uint32_t orc_eval_dag(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
+                      int32_t* makespan, int64_t* op_time);
+
+void orc_eval_batch(const orc_inst* I, int allow_partial, int64_t B, const int64_t* op_off,
+                    const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end,
+                    int32_t* makespan, uint32_t* status);
+
+typedef struct { uint16_t c; uint8_t vD, vP; uint16_t pD, pP; } orc_tuple;
+
+/* Insertion scan over one base (partial) solution: each tuple's exact
+ * makespan and status, and per segment the three smallest keys
+ * (makespan << 32 | tuple index) among feasible tuples (INT64_MAX if fewer). */
+void orc_insert_scan(const orc_inst* I, const uint16_t* base_ops, const uint16_t* base_rt,
+                     int64_t T, const orc_tuple* tuples, int32_t S, const int64_t* seg_off,
+                     int32_t* mk_out, uint32_t* st_out, int64_t* seg_top3);
+
+/* Multi-pass decoder (Algorithm 2).  prio/hint: 2n keys each, op o = 2(c-1)+isP;
+ * hint may be NULL.  Writes fitness, makespan, unscheduled count; ops_out (2n)
+ * and rt_end_out (m) if non-NULL.  Returns status (0 or ORC_BAD_KEY). */
+uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
+                    int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                    uint16_t* ops_out, uint16_t* rt_end_out);
+
+/* Philox4x32-10 (Salmon et al., SC'11). */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* One BRKGA generation (Section 4.4.3). */
+void orc_brkga_evolve(int32_t Np, int32_t genes, const float* prio, const float* hint,
+                      const int64_t* fitness, int32_t n_elite, int32_t n_mutant,
+                      uint32_t rho_thr24, uint64_t seed, uint32_t generation,
+                      float* prio_out, float* hint_out, int32_t* rank_out);
+
+/* Warm-start population from one solution (Section 4.4.4). */
+void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
+                          int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed,
+                          float* prio_out, float* hint_out);
+#endif
