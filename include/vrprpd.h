@@ -1,0 +1,258 @@
+/*
+ * vrprpd.h — C-ABI of the MI355X (gfx950) VRP-RPD evaluation library.
+ *
+ * Problem (Section 3): a depot (node 0), customers 1..n, m vehicles that each
+ * carry at most k identical resources.  Every customer needs a drop (a vehicle
+ * deploys a resource), p_c time units of autonomous processing, and a pickup
+ * (some vehicle, possibly another one, retrieves the resource).  Travel times
+ * d[i][j] are integers.  The objective is the makespan: the time the last
+ * vehicle is back at the depot (Eq. 21-23).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: VRPRPD_OK (0) or a negative error code.  The message of the
+ *    last error on the calling thread is available from vrprpd_last_error().
+ *  - Infeasibility is data, not an error: each evaluated candidate gets status
+ *    bits (VRPRPD_ST_*), status 0 meaning feasible.
+ *  - Buffers named "device" are caller-owned device memory (for instance torch
+ *    tensors).  "host" buffers are read before the call returns.  The library
+ *    keeps no pointer to a caller buffer after a call returns.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    compute call is asynchronous on it; a fault inside a kernel surfaces at the
+ *    caller's next synchronisation.  Calls that allocate (the *_create
+ *    functions) synchronise the device.
+ *  - All times are int32.  vrprpd_set_create refuses (VRPRPD_ERANGE) an
+ *    instance on which some schedule could exceed INT32_MAX - 1:
+ *    (2n + 1) * max d + sum p must stay below 2^31 - 1.
+ *  - A candidate is a list of per-vehicle operation sequences.  An operation is
+ *    the uint16 code (c << 1) | isPickup, c in [1, n].  The ops of a candidate
+ *    are stored vehicle after vehicle; rt_end[v] is the cumulative end of
+ *    vehicle v's sequence (so rt_end[m-1] is the candidate's op count).
+ *    This is the tour representation of Section 4.3 (a list of (customer, op)
+ *    per vehicle).
+ *  - Handles are not thread-safe: one host thread at a time per handle.
+ */
+#ifndef VRPRPD_H
+#define VRPRPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define VRPRPD_OK 0
+#define VRPRPD_EINVAL (-1) /* bad argument (null pointer, size out of range) */
+#define VRPRPD_ERANGE (-2) /* an instance whose times could overflow int32 */
+#define VRPRPD_ENOMEM (-3) /* device allocation failed */
+#define VRPRPD_EHIP (-4)   /* a HIP API call or kernel launch failed */
+
+/* ---- per-candidate status bits --------------------------------------------- */
+#define VRPRPD_ST_BAD_COVER 1u  /* Eq. (1) violated: missing/duplicate op, bad customer id or route ends */
+#define VRPRPD_ST_LOAD 2u       /* Eq. (13)-(18): a vehicle's load leaves [0, k] */
+#define VRPRPD_ST_RES 4u        /* the fleet needs more than R resources */
+#define VRPRPD_ST_DEADLOCK 8u   /* pickups wait on each other in a cycle: no schedule exists */
+#define VRPRPD_ST_BAD_KEY 16u   /* a random key outside [0, 1) or NaN */
+#define VRPRPD_ST_BAD_TUPLE 32u /* an insertion tuple that does not fit its base solution */
+
+/* ---- load models ------------------------------------------------------------
+ * VRPRPD_MIN_PRELOAD: each vehicle leaves the depot with the least load its
+ *   sequence needs (L_v = max over prefixes of drops - pickups); its load must
+ *   stay within [0, k] and the preloads together within R.
+ * VRPRPD_FULL_START: the MILP as printed (Eq. 13, q_0 = k): every vehicle
+ *   leaves with k resources; the fleet needs m*k <= R. */
+#define VRPRPD_MIN_PRELOAD 0
+#define VRPRPD_FULL_START 1
+
+/* ---- eval flags ------------------------------------------------------------- */
+#define VRPRPD_ALLOW_PARTIAL 1 /* customers may be absent (neither op present) */
+
+typedef struct vrprpd_set vrprpd_set;
+
+typedef struct {
+    int32_t n;          /* customers, 1 <= n <= 10000 (per-candidate state lives in LDS) */
+    int32_t m;          /* vehicles, 1 <= m <= 64 */
+    int32_t k;          /* vehicle capacity, k >= 1 */
+    int32_t R;          /* resources available to the fleet, R >= 0 */
+    int32_t load_model; /* VRPRPD_MIN_PRELOAD or VRPRPD_FULL_START */
+    const int32_t* dist; /* host, (n+1)*(n+1) row-major travel times >= 0, d[i][i] = 0 */
+    const int32_t* proc; /* host, n+1 processing times >= 0, proc[0] = 0 */
+} vrprpd_instance_desc;
+
+const char* vrprpd_last_error(void);
+
+/* Instance set: copies num_inst instances to the current device, packing the
+ * travel times as uint16 when every entry fits (else int32).  Synchronous.
+ * Errors: EINVAL (sizes, negative entries, nonzero diagonal or proc[0]),
+ * ERANGE (see above), ENOMEM, EHIP.  *out is NULL on error. */
+int vrprpd_set_create(vrprpd_set** out, int32_t num_inst, const vrprpd_instance_desc* desc);
+int vrprpd_set_destroy(vrprpd_set* set);
+/* Largest n and m over the set, and whether travel times are packed to 16 bits. */
+int vrprpd_set_info(const vrprpd_set* set, int32_t* num_inst, int32_t* n_max, int32_t* m_max,
+                    int32_t* dist16);
+
+/*
+ * vrprpd_eval — exact makespan of B candidates (Section 3, Eq. 1-23).
+ *
+ * For each candidate b:
+ *   1. cover (Eq. 1): every op code names a customer in [1, n(inst)]; each
+ *      customer has at most one drop and one pickup, a drop iff a pickup, and
+ *      (without VRPRPD_ALLOW_PARTIAL) both; route ends are non-decreasing and
+ *      at most 2n.  Else status = BAD_COVER, makespan = INT32_MAX.
+ *   2. load (Eq. 13-18) under the instance's load model -> LOAD, RES bits.
+ *   3. timing (Eq. 7-12): the earliest-start schedule of the given sequences.
+ *      Vehicles start at time 0 at the depot; a drop happens on arrival; a
+ *      pickup departs at max(arrival, drop time + p_c) whichever vehicle made
+ *      the drop (Eq. 9).  If the pickups' waits form a cycle: DEADLOCK and
+ *      makespan = INT32_MAX.
+ *   4. makespan (Eq. 21-22): the latest return time; an empty route adds 0.
+ *
+ * Arguments (all device pointers unless said otherwise):
+ *   set       instance set
+ *   B         number of candidates, B >= 0
+ *   inst      [B] int32 instance index per candidate, or NULL: all use instance 0;
+ *             an index outside [0, num_inst) gives status BAD_COVER
+ *   op_off    [B] int64 offset of candidate b's first op in ops, or NULL: b * 2 * n(0)
+ *   ops       op codes (uint16)
+ *   rt_off    [B] int64 offset of candidate b's route ends in rt_end, or NULL: b * m(0)
+ *   rt_end    m(inst) cumulative route ends per candidate (uint16)
+ *   flags     0 or VRPRPD_ALLOW_PARTIAL
+ *   makespan  [B] int32 out
+ *   status    [B] uint32 out
+ * op_off/rt_off NULL with inst non-NULL requires every instance to share n, m.
+ * Errors: EINVAL (NULL set or buffers with B > 0, B < 0, bad flags), EHIP.
+ */
+int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                int32_t* makespan, uint32_t* status, void* stream);
+
+/* One way to put a removed customer back into a partial solution
+ * (Section 4.2.3, repair operators): its drop into route vD before index pD
+ * (pD = len(vD) appends), its pickup into route vP before index pP, where pP
+ * counts positions after the drop was inserted (so on one vehicle
+ * pD + 1 <= pP <= len + 1, and pP = pD + 1 means the vehicle waits at c). */
+typedef struct {
+    uint16_t c;
+    uint8_t vD;
+    uint8_t vP;
+    uint16_t pD;
+    uint16_t pP;
+} vrprpd_tuple;
+
+/*
+ * vrprpd_insert_scan — exact makespan of insertion candidates (Section 4.2.3).
+ *
+ * The repair operators price inserting a removed customer's drop and pickup
+ * at every (vehicle, position) pair, including different vehicles for the two
+ * ops, by the resulting makespan, and keep the best options (greedy: the
+ * cheapest; regret-k: the k cheapest).  Here every tuple is evaluated exactly
+ * (cover, load and the full timing of vrprpd_eval under ALLOW_PARTIAL) on its
+ * segment's base solution with the tuple applied, and each segment reports
+ * its three smallest keys (makespan << 32 | tuple index) over tuples with
+ * status 0.
+ *
+ * A tuple is BAD_TUPLE (makespan INT32_MAX) when c is outside [1, n], c
+ * already has an op in the base, a vehicle index is >= m, or a position is
+ * outside the ranges above.  A base that breaks cover rules (even allowing
+ * absent customers) makes every valid tuple on it BAD_COVER.
+ *
+ * Arguments (device pointers unless said otherwise):
+ *   num_bases     >= 1 base (partial) solutions
+ *   base_inst     [num_bases] instance index, or NULL: all instance 0
+ *   base_op_off   [num_bases] offset of each base's ops in base_ops, or NULL: b * 2n(0)
+ *   base_ops      op codes of the bases
+ *   base_rt_off   [num_bases] offset of each base's route ends, or NULL: b * m(0)
+ *   base_rt_end   cumulative route ends of the bases
+ *   num_seg       S >= 0 segments; segment s covers tuples [seg_off[s], seg_off[s+1])
+ *   seg_off       [S+1] int64, non-decreasing, seg_off[0] = 0
+ *   seg_base      [S] base index of each segment, or NULL: all base 0
+ *   tuples        [seg_off[S]] tuples
+ *   mk_out        [seg_off[S]] int32 makespans, or NULL
+ *   st_out        [seg_off[S]] uint32 status bits, or NULL
+ *   seg_top3      [S][3] int64 out, ascending; INT64_MAX where fewer than 3 feasible tuples
+ * Errors: EINVAL, EHIP.  seg_base / base_inst values out of range make the
+ * segment's tuples BAD_TUPLE.
+ */
+int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, const int32_t* base_inst,
+                       const int64_t* base_op_off, const uint16_t* base_ops, const int64_t* base_rt_off,
+                       const uint16_t* base_rt_end, int32_t num_seg, const int64_t* seg_off,
+                       const int32_t* seg_base, const vrprpd_tuple* tuples, int32_t* mk_out,
+                       uint32_t* st_out, int64_t* seg_top3, void* stream);
+
+/*
+ * brkga_decode_eval — multi-pass decoder (Section 4.4.2, Algorithm 2) and the
+ * penalised fitness of the schedule (Section 4.4.2, infeasibility handling).
+ *
+ * Chromosome b holds 2n priority keys pi_o and (optionally) 2n vehicle hints
+ * alpha_o for the ops o = 2(c-1) + isPickup (Section 4.4.1).  The decoder
+ * visits the ops by ascending priority (equal keys: lower op index first) in
+ * passes; an op is scheduled at its turn when feasible:
+ *   drop:   some vehicle can hand out a resource (FULL_START: load > 0;
+ *           MIN_PRELOAD: load > 0, or it may take one more from the depot
+ *           within k and the fleet total R);
+ *   pickup: its drop is scheduled and some vehicle has room (load < k); the
+ *           vehicle waits for drop time + p_c (Eq. 9).
+ * SelectVehicle picks the feasible vehicle with the earliest completion time
+ * of the op (arrival for a drop, max(arrival, ready) for a pickup); ties go to
+ * the first vehicle counting cyclically from floor(m * alpha_o) (fp32
+ * product), or from vehicle 0 without hints.  Passes repeat until every op is
+ * scheduled or a pass schedules nothing (at most 2n passes).
+ * makespan = latest return of a used vehicle; unscheduled = 2n - #scheduled;
+ * fitness = makespan + 10^6 * unscheduled (lambda of the paper).
+ * Keys must lie in [0, 1) (-0.0 counts as 0.0): otherwise status BAD_KEY,
+ * fitness INT64_MAX, makespan INT32_MAX, unscheduled 2n.  Under FULL_START
+ * with m*k > R the status carries RES (the fleet as loaded needs more than R).
+ *
+ * Arguments (device pointers):
+ *   B            chromosomes; inst [B] instance index or NULL (all instance 0)
+ *   prio, hint   [B][key_stride] fp32 keys (hint may be NULL); key_stride >= 2n
+ *   fitness      [B] int64 out; makespan, unscheduled [B] int32 out; status [B] out
+ *   ops_out      [B][2 n_max] uint16 out, the decoded sequences route after
+ *                route (only the first rt_end_out[m-1] entries are written), or NULL
+ *   rt_end_out   [B][m_max] uint16 out, cumulative route ends, or NULL
+ * Limits: 2n <= 8192.  Errors: EINVAL, EHIP.
+ */
+int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
+                      const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
+                      int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
+                      void* stream);
+
+/*
+ * brkga_evolve — one BRKGA generation (Section 4.4.3): rank by (fitness,
+ * index); children [0, n_elite) copy the ranked elites; [n_elite,
+ * n_elite + n_mutant) get fresh U(0,1) genes; the rest take each gene from a
+ * uniformly chosen elite parent with probability rho_e, else from a
+ * uniformly chosen non-elite parent.  Genes are the `genes` priorities and,
+ * when hint != NULL, as many hints.  Draws: Philox4x32-10 keyed by seed,
+ * counter (gene / 4, child, generation, stream tag); uniform fp32 =
+ * (w >> 8) * 2^-24, Bernoulli = (w >> 8) < floor(rho_e * 2^24).
+ *   prio/hint      [Np][key_stride] in; prio_out/hint_out same shape, out (no aliasing)
+ *   fitness        [Np] int64 in
+ *   rank_out       [Np] int32 out: index of the individual of each rank
+ * Errors: EINVAL (sizes: n_elite + n_mutant <= Np, and n_elite >= 1 and a
+ * non-elite individual when crossover children exist), EHIP.
+ */
+int brkga_evolve(int32_t Np, int32_t genes, int64_t key_stride, const float* prio, const float* hint,
+                 const int64_t* fitness, int32_t n_elite, int32_t n_mutant, double rho_e, uint64_t seed,
+                 uint32_t generation, float* prio_out, float* hint_out, int32_t* rank_out, void* stream);
+
+/*
+ * brkga_warm_start — initial population seeded from one solution (Section
+ * 4.4.4).  Encoding: the op at 1-based position r of a route of L_v ops gets
+ * priority (r-1)/L_v (fp64 quotient rounded to fp32) and hint (v + 1/2)/m;
+ * ops absent from the solution get 0.  Slots [0, n_warm) cycle through
+ * n_variants variants (slot s takes variant s mod n_variants; variant 0 is
+ * the encoding, variant t > 0 adds U(-0.03, 0.03) to every gene in fp64 and
+ * clamps into [0, 1)); slots [n_warm, Np) are fresh U(0,1) individuals.
+ * Draws: Philox4x32-10, counter (gene / 4, variant or slot, 0, tag).
+ *   ops, rt_end   the solution of instance `inst` (device)
+ *   prio_out, hint_out   [Np][key_stride] fp32 out
+ */
+int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint16_t* ops, const uint16_t* rt_end,
+                     int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed, int64_t key_stride,
+                     float* prio_out, float* hint_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

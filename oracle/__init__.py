@@ -82,10 +82,62 @@ def _declare(L):
         _declare_alns(L)
 
 
+class AlnsParams(C.Structure):
+    """Table 2 hyper-parameters (Section 4.2.6) plus this build's repair budget."""
+    _fields_ = [("T0", C.c_double), ("alpha", C.c_double), ("reheat", C.c_double), ("gate", C.c_double),
+                ("stag_limit", C.c_int32), ("tau", C.c_int32), ("r", C.c_double),
+                ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
+                ("w_min", C.c_double), ("q_min", C.c_int32), ("q_max", C.c_int32),
+                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32)]
+
+
+def alns_params(**kw):
+    """Table 2 defaults: T0 = 0.30, alpha = 0.9998, reheat 0.50 after 2000
+    stagnant iterations (temperature gate 1% of T_init), tau = 100, r = 0.1,
+    sigma = (33, 9, 13), minimum weight 0.1, intra-GPU import every 1000."""
+    d = dict(T0=0.30, alpha=0.9998, reheat=0.50, gate=0.01, stag_limit=2000, tau=100, r=0.1,
+             sigma1=33, sigma2=9, sigma3=13, w_min=0.1, q_min=0, q_max=0, tuple_budget=0,
+             import_interval=1000, op_mask=0x0F3F)
+    d.update(kw)
+    return AlnsParams(**d)
+
+
 def _declare_alns(L):
     P = C.c_void_p
     L.orc_alns_run.restype = C.c_int32
-    L.orc_alns_run.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, C.c_int32, P, P, P, P, P]
+    L.orc_alns_run.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P]
+    L.orc_det_exp.restype = C.c_double
+    L.orc_det_exp.argtypes = [C.c_double]
+    L.orc_alns_qrange.restype = None
+    L.orc_alns_qrange.argtypes = [C.c_int, P, P]
+
+
+def det_exp(x):
+    return lib().orc_det_exp(float(x))
+
+
+def alns_qrange(n):
+    a, b = C.c_int(), C.c_int()
+    lib().orc_alns_qrange(n, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False):
+    """Run ALNS chains from one initial solution.  Returns dict(best_mk [chains],
+    best_ops [chains, 2n], best_rt [chains, m], trace [chains, iters, 4])."""
+    oi = _oinst(inst)
+    init_ops = np.ascontiguousarray(init_ops, dtype=np.uint16)
+    init_rt = np.ascontiguousarray(init_rt, dtype=np.uint16)
+    bo = np.zeros((chains, 2 * oi.n), dtype=np.uint16)
+    br = np.zeros((chains, oi.m), dtype=np.uint16)
+    bm = np.zeros(chains, dtype=np.int32)
+    tr = np.zeros((chains, iterations, 4), dtype=np.int64) if trace else None
+    lib().orc_alns_run(oi.ref, C.byref(params), chains, iterations, seed & (2**64 - 1), _ptr(init_ops),
+                       _ptr(init_rt), _ptr(bo), _ptr(br), _ptr(bm), _ptr(tr))
+    out = dict(best_mk=bm, best_ops=bo, best_rt=br)
+    if trace:
+        out["trace"] = tr
+    return out
 
 
 def _ptr(a):

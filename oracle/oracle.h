@@ -73,6 +73,25 @@ void orc_brkga_evolve(int32_t Np, int32_t genes, const float* prio, const float*
                       uint32_t rho_thr24, uint64_t seed, uint32_t generation,
                       float* prio_out, float* hint_out, int32_t* rank_out);
 
+/* ALNS parameters (Table 2 defaults in oracle/__init__.py). */
+typedef struct {
+    double T0, alpha, reheat, gate;
+    int32_t stag_limit, tau;
+    double r;
+    int32_t sigma1, sigma2, sigma3;
+    double w_min;
+    int32_t q_min, q_max;      /* 0: from n (Section 4.2.2) */
+    int32_t tuple_budget;      /* tuples per iteration; 0: every slot pair */
+    int32_t import_interval;   /* 0: never */
+    uint32_t op_mask;          /* destroy ops bits 0-5, repair ops bits 8-11 */
+} orc_alns_params;
+
+double orc_det_exp(double x);
+void orc_alns_qrange(int n, int* q_min, int* q_max);
+int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                     uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                     uint16_t* best_rt, int32_t* best_mk, int64_t* trace);
+
 /* Warm-start population from one solution (Section 4.4.4). */
 void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
                           int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed,

@@ -60,11 +60,21 @@ void orc_insert_scan(const orc_inst* I, const uint16_t* base_ops, const uint16_t
                      int32_t* mk_out, uint32_t* st_out, int64_t* seg_top3)
 {
     const int m = I->m;
-    uint16_t* ops = malloc(((size_t)base_rt[m - 1] + 2) * sizeof(uint16_t));
+    uint16_t* ops = malloc(((size_t)base_rt[m - 1] + 2 + 2 * (size_t)m) * sizeof(uint16_t));
     uint16_t* rt = malloc((size_t)m * sizeof(uint16_t));
     int32_t* mk = malloc((size_t)(T ? T : 1) * sizeof(int32_t));
     uint32_t* st = malloc((size_t)(T ? T : 1) * sizeof(uint32_t));
+    /* positions are only defined against a valid route-end table */
+    int rt_ok = 1;
+    for (int v = 0, prev = 0; v < m; prev = base_rt[v], ++v)
+        if (base_rt[v] < prev) rt_ok = 0;
+    if (base_rt[m - 1] > 2 * I->n) rt_ok = 0;
     for (int64_t i = 0; i < T; ++i) {
+        if (!rt_ok) {
+            mk[i] = INT32_MAX;
+            st[i] = ORC_BAD_COVER;
+            continue;
+        }
         if (!tuple_valid(I, base_ops, base_rt, &tuples[i])) {
             mk[i] = INT32_MAX;
             st[i] = ORC_BAD_TUPLE;

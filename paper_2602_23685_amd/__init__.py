@@ -1,0 +1,12 @@
+"""VRP-RPD batched exact makespan evaluation on MI355X (gfx950).
+
+The computation lives in ``libvrprpd.so`` (hand-written HIP kernels behind the
+C-ABI in ``include/vrprpd.h``); this package only marshals device tensors and
+streams into it.  Importing it loads nothing; the first call loads the library
+and raises if it is not built.
+"""
+from ._lib import (  # noqa: F401
+    ALLOW_PARTIAL, FULL_START, MIN_PRELOAD, SIGNATURES, ST_BAD_COVER, ST_BAD_KEY, ST_BAD_TUPLE,
+    ST_DEADLOCK, ST_LOAD, ST_RES, TUPLE_DTYPE, InstanceSet, VrpError, brkga_decode_eval, brkga_evolve, brkga_warm_start, load, vrprpd_eval,
+    vrprpd_insert_scan,
+)

@@ -1,0 +1,232 @@
+"""ctypes binding of libvrprpd.so: argument marshalling only.
+
+Every computation runs in the library's HIP kernels.  Tensors passed here must
+be device tensors; the functions hand their pointers and the current torch
+stream to the C-ABI (include/vrprpd.h) and return device tensors.  There is no
+fallback: if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvrprpd.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP = 0, -1, -2, -3, -4
+ST_BAD_COVER, ST_LOAD, ST_RES, ST_DEADLOCK, ST_BAD_KEY, ST_BAD_TUPLE = 1, 2, 4, 8, 16, 32
+MIN_PRELOAD, FULL_START = 0, 1
+ALLOW_PARTIAL = 1
+
+TUPLE_DTYPE = np.dtype([("c", "<u2"), ("vD", "u1"), ("vP", "u1"), ("pD", "<u2"), ("pP", "<u2")])
+
+
+class VrpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vrprpd error {code}: {msg}")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("k", C.c_int32), ("R", C.c_int32),
+                ("load_model", C.c_int32), ("dist", C.c_void_p), ("proc", C.c_void_p)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every symbol declared in include/vrprpd.h
+_P, _I32, _I64, _U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+SIGNATURES = {
+    "vrprpd_last_error": (C.c_char_p, []),
+    "vrprpd_set_create": (C.c_int, [C.POINTER(C.c_void_p), _I32, _P]),
+    "vrprpd_set_destroy": (C.c_int, [_P]),
+    "vrprpd_set_info": (C.c_int, [_P, _P, _P, _P, _P]),
+    "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
+                               _P, _P, _P, _P]),
+    "brkga_warm_start": (C.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _U64, _I64, _P, _P, _P]),
+}
+
+
+def load():
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2602_23685_amd/build.py "
+                              "(or __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            if hasattr(lib, name):
+                f = getattr(lib, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise VrpError(rc, load().vrprpd_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class InstanceSet:
+    """Instances copied to the current device (vrprpd_set_create)."""
+
+    def __init__(self, instances):
+        if not isinstance(instances, (list, tuple)):
+            instances = [instances]
+        lib = load()
+        self._keep = []
+        descs = (_Desc * len(instances))()
+        for i, inst in enumerate(instances):
+            d = np.ascontiguousarray(inst.d, dtype=np.int32)
+            p = np.ascontiguousarray(inst.p, dtype=np.int32)
+            self._keep += [d, p]
+            descs[i] = _Desc(inst.n, inst.m, inst.k, inst.R, inst.load_model,
+                             d.ctypes.data, p.ctypes.data)
+        h = C.c_void_p()
+        _check(lib.vrprpd_set_create(C.byref(h), len(instances), descs))
+        self.handle = h
+        self.instances = list(instances)
+        self._keep = None
+        info = [C.c_int32() for _ in range(4)]
+        _check(lib.vrprpd_set_info(h, *[C.byref(x) for x in info]))
+        self.num_inst, self.n_max, self.m_max, self.dist16 = (x.value for x in info)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().vrprpd_set_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vrprpd_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None,
+                partial=False, makespan=None, status=None, B=None, stream=None):
+    """Exact makespan and status of B candidates (see vrprpd_eval in vrprpd.h).
+
+    ops: uint16 codes (device); rt_end: uint16 route ends (device).  With
+    op_off/rt_off None the candidates are [B, 2n] and [B, m] blocks."""
+    if B is None:
+        if op_off is not None:
+            B = op_off.numel()
+        else:
+            B = rt_end.numel() // S.instances[0].m
+    dev = ops.device
+    if makespan is None:
+        makespan = torch.empty(B, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty(B, dtype=torch.int32, device=dev)
+    _check(load().vrprpd_eval(
+        S.handle, B, _dptr(inst, torch.int32, "inst"), _dptr(op_off, torch.int64, "op_off"),
+        _dptr(ops, torch.uint16, "ops"), _dptr(rt_off, torch.int64, "rt_off"),
+        _dptr(rt_end, torch.uint16, "rt_end"), ALLOW_PARTIAL if partial else 0,
+        _dptr(makespan, torch.int32, "makespan"), _dptr(status, None, "status"), _stream(stream)))
+    return makespan, status
+
+
+def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_bases=1,
+                       base_inst=None, base_op_off=None, base_rt_off=None, seg_base=None,
+                       want_each=True, stream=None):
+    """Exact makespan of insertion tuples against base partial solutions (see
+    vrprpd_insert_scan in vrprpd.h).  tuples: device uint8 tensor holding the
+    packed 8-byte tuples (TUPLE_DTYPE).  Returns (mk, status, seg_top3)."""
+    dev = base_ops.device
+    S_ = seg_off.numel() - 1
+    T = tuples.numel() // 8
+    mk = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
+    st = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
+    top = torch.empty((max(S_, 0), 3), dtype=torch.int64, device=dev)
+    _check(load().vrprpd_insert_scan(
+        S.handle, num_bases, _dptr(base_inst, torch.int32, "base_inst"),
+        _dptr(base_op_off, torch.int64, "base_op_off"), _dptr(base_ops, torch.uint16, "base_ops"),
+        _dptr(base_rt_off, torch.int64, "base_rt_off"), _dptr(base_rt, torch.uint16, "base_rt"),
+        S_, _dptr(seg_off, torch.int64, "seg_off"), _dptr(seg_base, torch.int32, "seg_base"),
+        _dptr(tuples, torch.uint8, "tuples"), _dptr(mk, torch.int32, "mk"), _dptr(st, None, "st"),
+        _dptr(top, torch.int64, "seg_top3"), _stream(stream)))
+    return mk, st, top
+
+
+def brkga_decode_eval(S: InstanceSet, prio, hint=None, inst=None, want_ops=False, out=None, stream=None):
+    """Decode B chromosomes (see brkga_decode_eval in vrprpd.h).  prio/hint:
+    [B, stride] float32 device tensors.  Returns dict of device tensors."""
+    B, stride = prio.shape
+    dev = prio.device
+    if out is None:
+        out = dict(fitness=torch.empty(B, dtype=torch.int64, device=dev),
+                   makespan=torch.empty(B, dtype=torch.int32, device=dev),
+                   unscheduled=torch.empty(B, dtype=torch.int32, device=dev),
+                   status=torch.empty(B, dtype=torch.int32, device=dev))
+        if want_ops:
+            n_max = S.n_max if inst is not None else S.instances[0].n
+            m_max = S.m_max if inst is not None else S.instances[0].m
+            out["ops"] = torch.zeros((B, 2 * n_max), dtype=torch.uint16, device=dev)
+            out["rt_end"] = torch.zeros((B, m_max), dtype=torch.uint16, device=dev)
+    _check(load().brkga_decode_eval(
+        S.handle, B, _dptr(inst, torch.int32, "inst"), _dptr(prio, torch.float32, "prio"),
+        _dptr(hint, torch.float32, "hint"), stride, _dptr(out["fitness"], torch.int64, "fitness"),
+        _dptr(out["makespan"], torch.int32, "makespan"), _dptr(out["unscheduled"], torch.int32, "unscheduled"),
+        _dptr(out["status"], None, "status"), _dptr(out.get("ops"), torch.uint16, "ops_out"),
+        _dptr(out.get("rt_end"), torch.uint16, "rt_end_out"), _stream(stream)))
+    return out
+
+
+def brkga_evolve(prio, hint, fitness, n_elite, n_mutant, rho_e, seed, generation, genes=None,
+                 prio_out=None, hint_out=None, rank_out=None, stream=None):
+    """One BRKGA generation (see brkga_evolve in vrprpd.h).  Returns
+    (prio_out, hint_out, rank_out)."""
+    Np, stride = prio.shape
+    genes = stride if genes is None else genes
+    prio_out = torch.empty_like(prio) if prio_out is None else prio_out
+    if hint is not None and hint_out is None:
+        hint_out = torch.empty_like(hint)
+    rank_out = torch.empty(Np, dtype=torch.int32, device=prio.device) if rank_out is None else rank_out
+    _check(load().brkga_evolve(
+        Np, genes, stride, _dptr(prio, torch.float32, "prio"), _dptr(hint, torch.float32, "hint"),
+        _dptr(fitness, torch.int64, "fitness"), n_elite, n_mutant, float(rho_e), seed & (2**64 - 1),
+        generation, _dptr(prio_out, torch.float32, "prio_out"), _dptr(hint_out, torch.float32, "hint_out"),
+        _dptr(rank_out, torch.int32, "rank_out"), _stream(stream)))
+    return prio_out, hint_out, rank_out
+
+
+def brkga_warm_start(S: InstanceSet, ops, rt_end, Np, n_warm, n_variants, seed, inst=0, stride=None,
+                     stream=None):
+    """Initial population seeded from a solution (see brkga_warm_start)."""
+    G = 2 * S.instances[inst].n
+    stride = G if stride is None else stride
+    po = torch.empty((Np, stride), dtype=torch.float32, device=ops.device)
+    ho = torch.empty((Np, stride), dtype=torch.float32, device=ops.device)
+    _check(load().brkga_warm_start(
+        S.handle, inst, _dptr(ops, torch.uint16, "ops"), _dptr(rt_end, torch.uint16, "rt_end"), Np, n_warm,
+        n_variants, seed & (2**64 - 1), stride, _dptr(po, torch.float32, "prio_out"),
+        _dptr(ho, torch.float32, "hint_out"), _stream(stream)))
+    return po, ho

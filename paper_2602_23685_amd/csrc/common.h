@@ -1,0 +1,116 @@
+// Internal definitions shared by the library's translation units (not part of
+// the C-ABI).  gfx950 only: 64-lane wavefronts, 160 KB LDS per CU, 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vrprpd.h"
+
+namespace vrprpd {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+constexpr int kMaxN = 10000;          // per-candidate state must fit in one CU's LDS
+constexpr int kMaxM = 64;             // one lane per vehicle
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// Per-instance description as the kernels see it.
+struct InstDev {
+    int32_t n, m, k, R, load_model, pad;
+    int64_t d_off;  // element offset of d[0][0] in the packed distance buffer
+    int64_t p_off;  // element offset of p[0] in the processing-time buffer
+};
+
+// Records a message for vrprpd_last_error() and returns code.
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+
+#define VRP_HIP(call)                                                      \
+    do {                                                                   \
+        hipError_t e_ = (call);                                            \
+        if (e_ != hipSuccess) return ::vrprpd::hip_error(e_, #call);        \
+    } while (0)
+
+// Maps a launch's block index to the tile it works on so that consecutive
+// tiles land on the same XCD: the hardware deals blocks round-robin over the
+// 8 XCDs, so tiles i and i+1 (usually the same instance and base solution)
+// would otherwise sit in different L2 caches.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Cross-lane helpers over groups of GL consecutive lanes of a wavefront.
+template <int GL>
+__device__ __forceinline__ uint64_t group_ballot(bool pred)
+{
+    const uint64_t all = __ballot(pred);
+    if constexpr (GL == 64) {
+        return all;
+    } else {
+        const int grp = (threadIdx.x & 63) / GL;
+        return (all >> (grp * GL)) & ((1ull << GL) - 1);
+    }
+}
+
+template <int GL>
+__device__ __forceinline__ int group_max(int x)
+{
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, GL));
+    return x;
+}
+
+template <int GL>
+__device__ __forceinline__ int group_sum(int x)
+{
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, GL);
+    return x;
+}
+
+template <int GL>
+__device__ __forceinline__ long long group_min64(long long x)
+{
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) {
+        long long y = __shfl_xor(x, o, GL);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// LDS loads/stores that other lanes of the same wave may have written since
+// the last access: relaxed atomics at wavefront scope compile to plain ds ops
+// but keep the compiler from caching or reordering them.
+__device__ __forceinline__ int lds_load(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void lds_store(int* p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace vrprpd
+
+struct vrprpd_set {
+    int device = 0;
+    int32_t num_inst = 0, n_max = 0, m_max = 0, dist16 = 1;
+    bool uniform_nm = true;
+    std::vector<vrprpd::InstDev> host;  // same table as d_inst, on the host
+    vrprpd::InstDev* d_inst = nullptr;
+    void* d_dist = nullptr;            // uint16_t or int32_t, per dist16
+    int32_t* d_proc = nullptr;
+};

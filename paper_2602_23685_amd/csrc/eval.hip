@@ -1,0 +1,284 @@
+// vrprpd_eval: exact makespan of explicit candidates (Section 3, Eq. 1-23).
+//
+// Mapping: a group of GL lanes (GL = 16, 32 or 64, at least m) owns one
+// candidate; 64/GL groups share a wavefront and WPB waves form a block.
+// Phase 1 streams the candidate's ops from HBM once (coalesced, route by
+// route), checks cover with an LDS bitmap, and gathers every travel time
+// d[prev][c] in parallel into LDS, so the sweep that follows never waits on
+// the L2.  Phase 2 is the lockstep timing sweep (sweep.h), lane v = vehicle v.
+#include "common.h"
+#include "sweep.h"
+
+namespace vrprpd {
+
+struct EvalArgs {
+    const InstDev* inst_tab;
+    const void* dist;
+    const int32_t* proc;
+    const int32_t* inst;
+    const int64_t* op_off;
+    const uint16_t* ops;
+    const int64_t* rt_off;
+    const uint16_t* rt_end;
+    int32_t* makespan;
+    uint32_t* status;
+    int64_t B;
+    int32_t partial;
+    int32_t nblocks;
+    int32_t n_max;
+    int32_t group_bytes;
+    int32_t num_inst;
+};
+
+// LDS carve-up of one group, shared with the host-side size computation.
+struct GroupLayout {
+    int ready_off, bits_off, ops_off, bytes;
+};
+
+__host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
+
+constexpr int kStepOps = 4;   // ops a lane may take per sweep step
+
+__host__ __device__ inline int op_capacity(int n_max) { return 2 * n_max + kStepOps; }
+
+__host__ __device__ inline GroupLayout group_layout(int n_max, int bytes_per_op)
+{
+    GroupLayout g;
+    g.ready_off = 0;
+    g.bits_off = align16(4 * (n_max + 1));
+    g.ops_off = g.bits_off + align16(4 * ((2 * (n_max + 1) + 31) / 32));
+    g.bytes = g.ops_off + align16(bytes_per_op * op_capacity(n_max));
+    return g;
+}
+
+// Validates one op code of the staged candidate and records it.
+template <typename DT>
+__device__ __forceinline__ void stage_code(OpStore<DT>& S, uint32_t* bits, int j, uint32_t cd, int n, bool& bad)
+{
+    const int c = (int)(cd >> 1);
+    if (c < 1 || c > n) {
+        bad = true;
+        cd = 0;
+    } else {
+        const int bitpos = 2 * c + (int)(cd & 1u);
+        const uint32_t mask = 1u << (bitpos & 31);
+        if (atomicOr(&bits[bitpos >> 5], mask) & mask) bad = true;   // second copy of an op
+    }
+    S.set_code(j, cd);
+}
+
+template <typename DT, int GL, int WPB>
+__global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int G = 64 / GL;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / GL, li = lane % GL;
+    const int blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t b = ((int64_t)blk * WPB + wave) * G + grp;
+    const bool live = b < a.B;
+
+    const GroupLayout L = group_layout(a.n_max, OpStore<DT>::kBytesPerOp);
+    unsigned char* gs = smem + (size_t)(wave * G + grp) * a.group_bytes;
+    int* ready = reinterpret_cast<int*>(gs + L.ready_off);
+    uint32_t* bits = reinterpret_cast<uint32_t*>(gs + L.bits_off);
+    OpStore<DT> S;
+    S.init(gs + L.ops_off, op_capacity(a.n_max));
+
+    int ii = (live && a.inst) ? a.inst[b] : 0;
+    const bool bad_inst = ii < 0 || ii >= a.num_inst;
+    if (bad_inst) ii = 0;
+    const InstDev I = a.inst_tab[ii];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    const int64_t ob = live ? (a.op_off ? a.op_off[b] : b * 2 * (int64_t)n) : 0;
+    const int64_t rb = live ? (a.rt_off ? a.rt_off[b] : b * (int64_t)m) : 0;
+    const uint16_t* ops = a.ops + ob;
+
+    // Route bounds: lane v < m holds [s, e) of route v.
+    int e = 0;
+    if (live && !bad_inst && li < m) e = a.rt_end[rb + li];
+    int s = __shfl_up(e, 1, GL);
+    if (li == 0) s = 0;
+    const int total = __shfl(e, m - 1, GL);
+    bool bad = bad_inst || (live && li < m && s > e);
+    if (total > 2 * n) bad = true;
+    bool gbad = !live || group_ballot<GL>(bad) != 0;
+
+    // ---- phase 1a: stream the ops in (16-byte loads), check cover ----------
+    const int nwords = (2 * N1 + 31) / 32;
+    for (int w = li; w < nwords; w += GL) bits[w] = 0u;
+    wave_lds_fence();
+    bool cbad = false;
+    if (!gbad) {
+        int head = (int)((8 - (((uintptr_t)ops >> 1) & 7)) & 7);
+        head = head < total ? head : total;
+        for (int j = li; j < head; j += GL) stage_code(S, bits, j, ops[j], n, cbad);
+        const int nvec = (total - head) >> 3;
+        const uint4* vec = reinterpret_cast<const uint4*>(ops + head);
+#pragma unroll 2
+        for (int q = li; q < nvec; q += GL) {
+            const uint4 x = vec[q];
+            const int j = head + 8 * q;
+            stage_code(S, bits, j + 0, x.x & 0xFFFFu, n, cbad);
+            stage_code(S, bits, j + 1, x.x >> 16, n, cbad);
+            stage_code(S, bits, j + 2, x.y & 0xFFFFu, n, cbad);
+            stage_code(S, bits, j + 3, x.y >> 16, n, cbad);
+            stage_code(S, bits, j + 4, x.z & 0xFFFFu, n, cbad);
+            stage_code(S, bits, j + 5, x.z >> 16, n, cbad);
+            stage_code(S, bits, j + 6, x.w & 0xFFFFu, n, cbad);
+            stage_code(S, bits, j + 7, x.w >> 16, n, cbad);
+        }
+        for (int j = head + 8 * nvec + li; j < total; j += GL) stage_code(S, bits, j, ops[j], n, cbad);
+    }
+    wave_lds_fence();
+    if (!gbad) {
+        for (int c = 1 + li; c <= n; c += GL) {
+            const uint32_t two = (bits[(2 * c) >> 5] >> ((2 * c) & 31)) & 3u;
+            if (!(two == 3u || (two == 0u && a.partial))) cbad = true;
+        }
+    }
+    gbad = gbad || group_ballot<GL>(cbad) != 0;
+
+    // ---- phase 1b: every travel time d[prev][c] and every drop's p_c, -------
+    // gathered in batches so that many loads are in flight per lane.  Legs
+    // first assume the previous op of the flat list is the previous stop; the
+    // first op of each route is then re-pointed at the depot.  ready[c] starts
+    // as ~p_c: "not dropped yet", and the drop reads p_c back from it.
+    if (!gbad) {
+        constexpr int U = 8;
+        for (int j0 = li; j0 < total; j0 += U * GL) {
+            int idx[U], cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * GL;
+                const int jj = j < total ? j : 0;
+                const uint32_t cd = S.code(jj);
+                cc[u] = (cd & 1u) ? 0 : (int)(cd >> 1);
+                const int pc = jj > 0 ? (int)(S.code(jj - 1) >> 1) : 0;
+                idx[u] = pc * N1 + (int)(cd >> 1);
+            }
+            int lg[U], pv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                lg[u] = (int)D[idx[u]];
+                pv[u] = P[cc[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * GL;
+                if (j < total) {
+                    S.set_leg(j, lg[u]);
+                    if (cc[u]) ready[cc[u]] = ~pv[u];
+                }
+            }
+        }
+        wave_lds_fence();
+        if (li < m && s < e) S.set_leg(s, (int)D[(int)(S.code(s) >> 1)]);
+        wave_lds_fence();
+    }
+
+    // ---- phase 2: timing sweep ----------------------------------------------
+    const bool veh = li < m;
+    SweepOut o{0, 0, 0, 0, false};
+    if (!gbad) o = sweep_group<GL, kStepOps, DT>(S, ready, veh ? s : 0, veh ? e : 0);
+
+    uint32_t st = 0;
+    int z = 0;
+    if (!gbad) {
+        st = load_status<GL>(o, veh, m, I.k, I.R, I.load_model);
+        int ret = 0;
+        if (veh && e > s) ret = o.t + (int)D[(int64_t)(S.code(e - 1) >> 1) * N1];
+        z = group_max<GL>(ret);
+        if (o.dead) st |= VRPRPD_ST_DEADLOCK;
+    }
+    if (live && li == 0) {
+        if (gbad) {
+            a.makespan[b] = INT32_MAX;
+            a.status[b] = VRPRPD_ST_BAD_COVER;
+        } else {
+            a.makespan[b] = o.dead ? INT32_MAX : z;
+            a.status[b] = st;
+        }
+    }
+}
+
+struct LaunchShape {
+    int gl, wpb, group_bytes, lds;
+};
+
+static LaunchShape eval_shape(int n_max, int m_max, int dist16)
+{
+    LaunchShape sh;
+    sh.gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
+    sh.group_bytes = group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
+    const int per_wave = (64 / sh.gl) * sh.group_bytes;
+    sh.wpb = 4;
+    while (sh.wpb > 1 && (size_t)sh.wpb * per_wave > 64 * 1024) sh.wpb >>= 1;
+    sh.lds = sh.wpb * per_wave;
+    return sh;
+}
+
+template <typename DT, int GL, int WPB>
+static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
+{
+    auto* k = eval_kernel<DT, GL, WPB>;
+    if (lds > 64 * 1024)
+        VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(64 * WPB), lds, stream, a);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+template <typename DT, int GL>
+static int dispatch_wpb(const EvalArgs& a, int wpb, int lds, hipStream_t st)
+{
+    switch (wpb) {
+    case 4: return launch_eval<DT, GL, 4>(a, lds, st);
+    case 2: return launch_eval<DT, GL, 2>(a, lds, st);
+    default: return launch_eval<DT, GL, 1>(a, lds, st);
+    }
+}
+
+template <typename DT>
+static int dispatch_gl(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
+{
+    switch (sh.gl) {
+    case 16: return dispatch_wpb<DT, 16>(a, sh.wpb, sh.lds, st);
+    case 32: return dispatch_wpb<DT, 32>(a, sh.wpb, sh.lds, st);
+    default: return dispatch_wpb<DT, 64>(a, sh.wpb, sh.lds, st);
+    }
+}
+
+}  // namespace vrprpd
+
+using namespace vrprpd;
+
+extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                           const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                           int32_t* makespan, uint32_t* status, void* stream)
+{
+    if (!set) return set_error(VRPRPD_EINVAL, "vrprpd_eval: set is NULL");
+    if (B < 0) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B < 0");
+    if (flags & ~VRPRPD_ALLOW_PARTIAL) return set_error(VRPRPD_EINVAL, "vrprpd_eval: unknown flags 0x%x", flags);
+    if (B == 0) return VRPRPD_OK;
+    if (!ops || !rt_end || !makespan || !status)
+        return set_error(VRPRPD_EINVAL, "vrprpd_eval: ops, rt_end, makespan and status are required");
+    if (inst && (!op_off || !rt_off) && !set->uniform_nm)
+        return set_error(VRPRPD_EINVAL, "vrprpd_eval: instances differ in n or m; pass op_off and rt_off");
+    const int n_lds = inst ? set->n_max : set->host[0].n;
+    const int m_max = inst ? set->m_max : set->host[0].m;
+    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16);
+    if ((size_t)sh.lds > kLdsPerCu)
+        return set_error(VRPRPD_EINVAL, "vrprpd_eval: n=%d needs %d B of LDS per candidate", n_lds, sh.lds);
+    const int64_t per_block = (int64_t)sh.wpb * (64 / sh.gl);
+    const int64_t nb = (B + per_block - 1) / per_block;
+    if (nb > INT32_MAX) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B too large");
+    EvalArgs a{set->d_inst, set->d_dist, set->d_proc, inst, op_off, ops, rt_off, rt_end, makespan, status,
+               B, (flags & VRPRPD_ALLOW_PARTIAL) ? 1 : 0, (int32_t)nb, n_lds, sh.group_bytes,
+               set->num_inst};
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return set->dist16 ? dispatch_gl<uint16_t>(a, sh, st) : dispatch_gl<int32_t>(a, sh, st);
+}

@@ -122,40 +122,57 @@ def instance_from_matrix(d, p, m, k, R, load_model=MIN_PRELOAD) -> Instance:
 
 
 def random_candidates(inst: Instance, B: int, seed: int, respect_load: bool = True,
-                      chunk: int = 8192):
+                      chunk: int = 8192, outstanding_frac: float = 0.5):
     """B candidate solutions as per-vehicle drop/pickup sequences.
 
     Each candidate is a random linear extension of the drop-before-pickup
-    order (drop keys u1, pickup keys u1 + u2, all ops sorted by key), so the
-    sequences never contain a precedence cycle.  Each op then goes to a random
-    vehicle; with ``respect_load`` the vehicle is drawn among those whose
-    running drop-minus-pickup window stays within k and whose summed peaks
-    stay within R (a sampling filter that keeps most candidates load-feasible,
-    not a check the tests rely on).
+    order: at every step the next op is a drop of a not-yet-dropped customer
+    (customers in a random order) or the pickup of a random dropped one, so
+    the sequences never contain a precedence cycle.  At most
+    ``outstanding_frac * R`` resources are out at any time.  Each op then goes
+    to a random vehicle; with ``respect_load`` the vehicle is drawn among those
+    whose running drop-minus-pickup window stays within k and whose summed
+    peaks stay within R (a sampling filter that keeps most candidates
+    load-feasible; nothing in the tests relies on it).
 
     Returns (ops [B, 2n] uint16 with code = (c << 1) | isPickup, grouped by
     vehicle; rt_end [B, m] uint16 cumulative route ends).
     """
     n, m, k, R = inst.n, inst.m, inst.k, inst.R
     g = rng(seed)
+    lim = max(1, int(outstanding_frac * R)) if R > 0 else 1
     ops_all = np.empty((B, 2 * n), dtype=np.uint16)
     rt_all = np.empty((B, m), dtype=np.uint16)
     for s in range(0, B, chunk):
         b = min(chunk, B - s)
-        u1 = g.random((b, n))
-        u2 = g.random((b, n))
-        keys = np.empty((b, 2 * n))
-        keys[:, 0::2] = u1
-        keys[:, 1::2] = u1 + u2
-        order = np.argsort(keys, axis=1, kind="stable")       # op index o = 2(c-1)+isP
+        rows = np.arange(b)
+        dorder = np.argsort(g.random((b, n)), axis=1) + 1          # drop order of customers
+        dptr = np.zeros(b, dtype=np.int64)
+        out = np.zeros((b, n), dtype=np.int64)                      # dropped, not picked up
+        cnt = np.zeros(b, dtype=np.int64)
+        code = np.empty((b, 2 * n), dtype=np.int64)
         veh = np.empty((b, 2 * n), dtype=np.int64)
         w = np.zeros((b, m), dtype=np.int64)
         wmax = np.zeros((b, m), dtype=np.int64)
         wmin = np.zeros((b, m), dtype=np.int64)
-        rows = np.arange(b)
         for step in range(2 * n):
-            o = order[:, step]
-            delta = np.where(o & 1, -1, 1)[:, None]
+            can_d = (dptr < n) & (cnt < lim)
+            can_p = cnt > 0
+            coin = g.random(b)
+            is_d = can_d & (~can_p | (coin < 0.5))
+            c = np.where(is_d, dorder[rows, np.minimum(dptr, n - 1)], 0)
+            pick = (g.random(b) * np.maximum(cnt, 1)).astype(np.int64)
+            pc = out[rows, pick]
+            last = out[rows, np.maximum(cnt - 1, 0)]
+            # pickups: swap-remove the chosen customer from the outstanding list
+            out[rows, pick] = np.where(is_d, out[rows, pick], last)
+            cnt = np.where(is_d, cnt, cnt - 1)
+            c = np.where(is_d, c, pc)
+            out[rows, cnt] = np.where(is_d, c, out[rows, cnt])
+            cnt = np.where(is_d, cnt + 1, cnt)
+            dptr = np.where(is_d, dptr + 1, dptr)
+            code[:, step] = (c << 1) | (~is_d).astype(np.int64)
+            delta = np.where(is_d, 1, -1)[:, None]
             score = g.random((b, m))
             if respect_load:
                 w2 = w + delta
@@ -172,9 +189,7 @@ def random_candidates(inst: Instance, B: int, seed: int, respect_load: bool = Tr
             wmin[rows, v] = np.minimum(wmin[rows, v], w[rows, v])
         # group by vehicle, keeping the global order inside each route
         pos = np.argsort(veh * (2 * n) + np.arange(2 * n)[None, :], axis=1, kind="stable")
-        sorted_ops = np.take_along_axis(order, pos, axis=1)
-        code = ((sorted_ops >> 1) + 1) << 1 | (sorted_ops & 1)
-        ops_all[s:s + b] = code.astype(np.uint16)
+        ops_all[s:s + b] = np.take_along_axis(code, pos, axis=1).astype(np.uint16)
         counts = np.stack([(veh == v).sum(axis=1) for v in range(m)], axis=1)
         rt_all[s:s + b] = np.cumsum(counts, axis=1).astype(np.uint16)
     return ops_all, rt_all
@@ -282,3 +297,27 @@ def random_keys(B, n, seed, special=False):
         prio[B - 1, 0] = np.nan
         hint[B - 1, 1] = 1.0
     return prio, hint
+
+
+def relabel_candidates(ops, rt_end, n, B, seed):
+    """B candidates made from a pool by renaming customers: candidate i takes
+    pool row i % len(pool) and applies a fresh random permutation sigma of
+    1..n to every op (c -> sigma(c), op type kept).  Route shapes, op types
+    and the drop-before-pickup structure are kept, so load feasibility and
+    freedom from wait cycles carry over, while the visited customers (and so
+    the travel times and the makespan) change."""
+    g = rng(seed)
+    P = ops.shape[0]
+    out = np.empty((B, ops.shape[1]), dtype=np.uint16)
+    rt = np.empty((B, rt_end.shape[1]), dtype=np.uint16)
+    step = 4096
+    for s in range(0, B, step):
+        b = min(step, B - s)
+        src = (np.arange(s, s + b) % P)
+        sigma = np.argsort(g.random((b, n)), axis=1) + 1          # sigma[c-1] in 1..n
+        sigma = np.concatenate([np.zeros((b, 1), np.int64), sigma], axis=1)
+        o = ops[src].astype(np.int64)
+        c = np.take_along_axis(sigma, o >> 1, axis=1)
+        out[s:s + b] = ((c << 1) | (o & 1)).astype(np.uint16)
+        rt[s:s + b] = rt_end[src]
+    return out, rt

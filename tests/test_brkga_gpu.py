@@ -1,0 +1,112 @@
+"""Parity: BRKGA decode, generation and warm start on the GPU vs the oracle."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_23685_amd as P
+    P.load()
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+DECODE_CASES = [
+    # n, m, k, R, rule, load_model, B
+    (16, 2, 2, 4, "base", 0, 1024),
+    (100, 4, 5, 20, "2x", 0, 256),
+    (100, 4, 5, 20, "2x", 1, 128),
+    (1000, 10, 10, 100, "1R20d10", 0, 24),
+    (500, 10, 8, 50, "base", 0, 24),
+    (30, 3, 2, 2, "5x", 0, 256),           # scarce resources: many passes, unscheduled ops
+    (1, 1, 1, 1, "base", 0, 16),
+    (20, 40, 1, 10, "1R10", 0, 64),        # more vehicles than customers
+]
+
+
+@pytest.mark.parametrize("case", DECODE_CASES, ids=lambda c: f"n{c[0]}m{c[1]}lm{c[5]}")
+def test_decode_parity(orc, P, case):
+    n, m, k, R, rule, lm, B = case
+    inst = synth.make_instance(n, m, k, R, rule, seed=7000 + n, load_model=lm)
+    prio, hint = synth.random_keys(B, n, seed=n + m, special=B >= 8)
+    S = P.InstanceSet([inst])
+    for use_hint in (True, False):
+        out = P.brkga_decode_eval(S, dev(prio), dev(hint) if use_hint else None, want_ops=True)
+        torch.cuda.synchronize()
+        f = out["fitness"].cpu().numpy()
+        mk = out["makespan"].cpu().numpy()
+        un = out["unscheduled"].cpu().numpy()
+        st = out["status"].cpu().numpy().view(np.uint32)
+        ops = out["ops"].cpu().numpy()
+        rt = out["rt_end"].cpu().numpy()
+        for b in range(B):
+            r = orc.decode(inst, prio[b], hint[b] if use_hint else None, want_ops=True)
+            assert (f[b], mk[b], un[b], st[b]) == (r["fitness"], r["makespan"], r["unscheduled"],
+                                                     r["status"]), (b, use_hint)
+            if r["status"] & 16:
+                assert np.all(rt[b] == 0)
+            else:
+                assert np.array_equal(rt[b], r["rt_end"]), b
+                L = int(rt[b][-1])
+                assert np.array_equal(ops[b][:L], r["ops"]), b
+
+
+def test_evolve_parity(orc, P):
+    n, Np = 100, 1024
+    ne, nm = orc.brkga_sizes(Np)
+    prio, hint = synth.random_keys(Np, n, seed=3)
+    fit = synth.rng(4).integers(0, 10**6, size=Np).astype(np.int64)
+    fit[::7] = fit[0]                                       # ties resolved by index
+    fit[5] = 2**63 - 1
+    for gen in (0, 17):
+        po, ho, rank = P.brkga_evolve(dev(prio), dev(hint), dev(fit), ne, nm, 0.7, 0xC0FFEE, gen)
+        torch.cuda.synchronize()
+        opo, oho, orank = orc.brkga_evolve(prio, hint, fit, ne, nm, orc.rho_threshold(0.7), 0xC0FFEE, gen)
+        assert np.array_equal(rank.cpu().numpy(), orank)
+        assert np.array_equal(po.cpu().numpy().view(np.uint32), opo.view(np.uint32))
+        assert np.array_equal(ho.cpu().numpy().view(np.uint32), oho.view(np.uint32))
+    # without hints (priorities only); genes not a multiple of 4
+    prio2 = prio[:, :198].copy()
+    po, ho, rank = P.brkga_evolve(dev(prio2), None, dev(fit), ne, nm, 0.7, 5, 1)
+    opo, _, orank = orc.brkga_evolve(prio2, None, fit, ne, nm, orc.rho_threshold(0.7), 5, 1)
+    assert np.array_equal(po.cpu().numpy().view(np.uint32), opo.view(np.uint32))
+
+
+def test_warm_start_parity(orc, P):
+    inst = synth.make_instance(100, 4, 5, 20, "2x", seed=9)
+    ops, rt = synth.random_candidates(inst, 1, 10)
+    S = P.InstanceSet([inst])
+    po, ho = P.brkga_warm_start(S, dev(ops[0]), dev(rt[0]), 300, 45, 20, seed=99)
+    torch.cuda.synchronize()
+    opo, oho = orc.brkga_warm_start(inst, ops[0], rt[0], 300, 45, 20, 99)
+    assert np.array_equal(po.cpu().numpy().view(np.uint32), opo.view(np.uint32))
+    assert np.array_equal(ho.cpu().numpy().view(np.uint32), oho.view(np.uint32))
+
+
+def test_generation_loop_matches_oracle(orc, P):
+    """Warm start, then decode + evolve for a few generations entirely on the
+    GPU; the oracle replays the same generations from the same inputs."""
+    inst = synth.make_instance(40, 3, 4, 12, "5x", seed=21)
+    ops, rt = synth.random_candidates(inst, 1, 22)
+    S = P.InstanceSet([inst])
+    Np, G = 256, 80
+    ne, nm = orc.brkga_sizes(Np)
+    gp, gh = P.brkga_warm_start(S, dev(ops[0]), dev(rt[0]), Np, int(0.15 * Np), 20, seed=5)
+    op_, oh_ = orc.brkga_warm_start(inst, ops[0], rt[0], Np, int(0.15 * Np), 20, 5)
+    for gen in range(4):
+        out = P.brkga_decode_eval(S, gp, gh)
+        of = orc.decode_batch(inst, op_, oh_)[0]
+        assert np.array_equal(out["fitness"].cpu().numpy(), of)
+        gp, gh, _ = P.brkga_evolve(gp, gh, out["fitness"], ne, nm, 0.7, 77, gen)
+        op_, oh_, _ = orc.brkga_evolve(op_, oh_, of, ne, nm, orc.rho_threshold(0.7), 77, gen)
+        assert np.array_equal(gp.cpu().numpy().view(np.uint32), op_.view(np.uint32))

@@ -1,0 +1,166 @@
+"""Parity: vrprpd_eval on the GPU vs the CPU oracle, element by element.
+
+Makespans are integers and must match bit for bit, status bits too."""
+import numpy as np
+import pytest
+
+import synth
+from cases import destroy, flat, mutate
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_23685_amd as P
+    P.load()
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_eval(P, S, ops, rt, **kw):
+    kw2 = {k: (dev(v) if isinstance(v, np.ndarray) else v) for k, v in kw.items()}
+    mk, st = P.vrprpd_eval(S, dev(ops), dev(rt), **kw2)
+    torch.cuda.synchronize()
+    return mk.cpu().numpy(), st.cpu().numpy().view(np.uint32)
+
+
+def check(orc, P, inst, ops, rt, label, partial=False, op_off=None):
+    S = P.InstanceSet([inst])
+    if op_off is None:
+        mk, st = gpu_eval(P, S, ops, rt, partial=partial)
+        omk, ost = orc.eval_batch(inst, ops, rt, allow_partial=partial)
+    else:
+        rt_off = np.arange(len(op_off), dtype=np.int64) * inst.m
+        mk, st = gpu_eval(P, S, ops, rt.reshape(-1), op_off=op_off, rt_off=rt_off, partial=partial)
+        omk, ost = orc.eval_batch(inst, ops, rt.reshape(-1), op_off=op_off, rt_off=rt_off,
+                                  allow_partial=partial)
+    bad = np.nonzero((mk != omk) | (st != ost))[0]
+    assert bad.size == 0, (f"{label}: {bad.size} mismatches, first b={bad[0]} gpu=({mk[bad[0]]},"
+                           f"{st[bad[0]]}) oracle=({omk[bad[0]]},{ost[bad[0]]})")
+    return omk, ost
+
+
+CONFIGS = [
+    # (n, m, k, R, rule, load_model, B)
+    (16, 2, 2, 4, "base", 0, 4096),        # depot + 16 customers, 2 vehicles (small parity case)
+    (100, 4, 5, 20, "2x", 0, 2048),        # 100 customers, 4 vehicles
+    (1000, 10, 10, 100, "1R20d10", 0, 256),  # full scale, 1000 customers, 10 vehicles
+    (240, 4, 7, 24, "5x", 1, 512),
+    (37, 17, 3, 30, "1R10", 0, 512),       # 17 vehicles -> 32-lane groups
+    (50, 40, 2, 80, "base", 0, 256),       # 40 vehicles -> full-wave groups
+    (1, 1, 1, 1, "base", 0, 8),
+    (3, 64, 1, 64, "base", 0, 64),         # most vehicles empty
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"n{c[0]}m{c[1]}")
+def test_eval_parity_random_feasible(orc, P, cfg):
+    n, m, k, R, rule, lm, B = cfg
+    inst = synth.make_instance(n, m, k, R, rule, seed=1000 + n, load_model=lm)
+    ops, rt = synth.random_candidates(inst, B, seed=n + m)
+    omk, ost = check(orc, P, inst, ops, rt, f"feasible n={n}")
+    assert (ost == 0).mean() > 0.5 or lm == 1 or n == 1
+
+
+@pytest.mark.parametrize("cfg", CONFIGS[:6], ids=lambda c: f"n{c[0]}m{c[1]}")
+def test_eval_parity_adversarial(orc, P, cfg):
+    n, m, k, R, rule, lm, B = cfg
+    inst = synth.make_instance(n, m, k, R, rule, seed=2000 + n, load_model=lm)
+    ops, rt = synth.random_candidates(inst, 64, seed=n)
+    mops, mrt = mutate(inst, ops, rt, seed=n, count=min(B, 1024))
+    omk, ost = check(orc, P, inst, mops, mrt, f"adversarial n={n}")
+    assert (ost & 8).any() and (ost & 1).any()
+
+
+@pytest.mark.parametrize("cfg", CONFIGS[:3], ids=lambda c: f"n{c[0]}m{c[1]}")
+def test_eval_parity_partial(orc, P, cfg):
+    n, m, k, R, rule, lm, B = cfg
+    inst = synth.make_instance(n, m, k, R, rule, seed=3000 + n, load_model=lm)
+    ops, rt = synth.random_candidates(inst, min(B, 256), seed=n + 1)
+    fops, off, frt = destroy(inst, ops, rt, seed=n, q=max(1, n // 20))
+    check(orc, P, inst, fops, frt, "partial", partial=True, op_off=off)
+    # the same partial solutions without ALLOW_PARTIAL are cover errors
+    _, ost = check(orc, P, inst, fops, frt, "partial-strict", partial=False, op_off=off)
+    assert np.all(ost == 1)
+
+
+def test_eval_parity_wide_distances(orc, P):
+    """Travel times above 65535 keep the int32 distance layout."""
+    inst = synth.make_instance(60, 4, 5, 20, "base", seed=4)
+    inst.d = (inst.d.astype(np.int64) * 500).astype(np.int32)
+    inst.p = (inst.p.astype(np.int64) * 500).astype(np.int32)
+    S = P.InstanceSet([inst])
+    assert S.dist16 == 0
+    ops, rt = synth.random_candidates(inst, 512, seed=5)
+    check(orc, P, inst, ops, rt, "int32 distances")
+
+
+def test_eval_parity_mixed_instances(orc, P):
+    """Instances of uneven size in one launch (per-candidate instance index)."""
+    g = synth.rng(77)
+    insts, chunks = [], []
+    for i in range(12):
+        n = int(np.exp(g.uniform(np.log(17), np.log(400))))
+        m = int(np.ceil(n / 100)) + 1
+        inst = synth.make_instance(n, m, int(g.integers(5, 11)), max(1, n // 10),
+                                   ["base", "2x", "5x", "1R10", "1R20"][i % 5], seed=i)
+        insts.append(inst)
+        chunks.append(synth.random_candidates(inst, 40, seed=100 + i))
+    S = P.InstanceSet(insts)
+    ops, op_off, rt, rt_off, idx = [], [], [], [], []
+    co = cr = 0
+    order = g.permutation(sum(len(c[0]) for c in chunks))
+    flat_list = [(i, b) for i, c in enumerate(chunks) for b in range(len(c[0]))]
+    for t in order:
+        i, b = flat_list[t]
+        o, r = chunks[i][0][b], chunks[i][1][b]
+        ops.append(o); rt.append(r); idx.append(i)
+        op_off.append(co); rt_off.append(cr)
+        co += len(o); cr += len(r)
+    ops = np.concatenate(ops); rt = np.concatenate(rt)
+    op_off = np.array(op_off, np.int64); rt_off = np.array(rt_off, np.int64)
+    idx = np.array(idx, np.int32)
+    mk, st = gpu_eval(P, S, ops, rt, inst=idx, op_off=op_off, rt_off=rt_off)
+    for t in range(len(idx)):
+        inst = insts[idx[t]]
+        ref = orc.eval_one(inst, ops[op_off[t]:op_off[t] + 2 * inst.n], rt[rt_off[t]:rt_off[t] + inst.m])
+        assert (mk[t], st[t]) == ref, t
+
+
+def test_eval_full_scale_sampled(orc, P):
+    """The benchmark's launch: 65,536 candidates at n = 1000, m = 10; the oracle
+    re-evaluates a seeded sample of 200 of them."""
+    inst = synth.make_instance(1000, 10, 10, 100, "1R20d10", seed=3003)
+    base_ops, base_rt = synth.random_candidates(inst, 2048, seed=3)
+    reps = 32
+    perm = synth.rng(5).permutation(2048 * reps)
+    ops = np.tile(base_ops, (reps, 1))[perm]
+    rt = np.tile(base_rt, (reps, 1))[perm]
+    S = P.InstanceSet([inst])
+    mk, st = gpu_eval(P, S, ops, rt)
+    pick = synth.rng(6).choice(len(ops), size=200, replace=False)
+    omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
+    assert np.array_equal(mk[pick], omk) and np.array_equal(st[pick], ost)
+    # copies of one candidate agree wherever they sit in the batch
+    src = perm % 2048
+    first = np.full(2048, -1)
+    for i, s_ in enumerate(src):
+        if first[s_] < 0:
+            first[s_] = i
+    assert np.array_equal(mk, mk[first[src]])
+
+
+def test_eval_empty_batch(P):
+    inst = synth.make_instance(5, 2, 2, 4, seed=1)
+    S = P.InstanceSet([inst])
+    e16 = torch.empty(0, dtype=torch.uint16, device="cuda")
+    mk, st = P.vrprpd_eval(S, e16, e16, B=0)
+    assert mk.numel() == 0
