@@ -252,6 +252,72 @@ int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint16_t* ops, c
                      int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed, int64_t key_stride,
                      float* prio_out, float* hint_out, void* stream);
 
+/* ---- ALNS (Section 4.2) ----------------------------------------------------
+ * alns_params: the hyper-parameters of Table 2 (Section 4.2.6) plus this
+ * library's repair budget.  Defaults: T0 = 0.30, alpha = 0.9998, reheat =
+ * 0.50, gate = 0.01, stag_limit = 2000, tau = 100, r = 0.1, sigma = (33, 9,
+ * 13), w_min = 0.1, q_min = q_max = 0 (the rule of Section 4.2.2:
+ * q_max = max(4, floor(0.05 n)), q_min = max(4, floor(q_max / 2))),
+ * tuple_budget = 0 (every slot pair), import_interval = 1000,
+ * op_mask = 0x0F3F (all six destroy and four repair operators).
+ *
+ * One iteration of a chain (Algorithm 1): roulette-select a destroy and a
+ * repair operator by weight; draw q in [q_min, q_max]; destroy (random,
+ * worst, Shaw, cluster, route, critical path); repair (greedy, regret-2,
+ * regret-3, regret-m) with every candidate priced by the exact evaluator;
+ * accept by simulated annealing; cool; reheat after stag_limit iterations
+ * without a new best once T < gate * T_init; every tau iterations update the
+ * weights.  The operators' readings of the paper (candidate slots ranked by
+ * detour, the K_D / K_P budget split, regret over per-drop-vehicle options,
+ * the rank weights 2^60 / r^6 of worst removal, the integer Shaw relatedness,
+ * exp by a fixed Taylor evaluation, ...) are stated in the library's design
+ * notes and followed exactly, so a CPU implementation of the same readings
+ * reproduces every chain's trajectory.
+ * Random draws: Philox4x32-10 keyed by seed, counter (a / 4, iteration,
+ * chain, 'ALNS'): a = 0 destroy roulette, 1 repair roulette, 2 q,
+ * 8 annealing, 16.. destroy operator. */
+typedef struct {
+    double T0, alpha, reheat, gate;
+    int32_t stag_limit, tau;
+    double r;
+    int32_t sigma1, sigma2, sigma3;
+    double w_min;
+    int32_t q_min, q_max;
+    int32_t tuple_budget;
+    int32_t import_interval;
+    uint32_t op_mask;
+} alns_params;
+
+typedef struct alns_state alns_state;
+
+/* chains_per_inst chains for each of n_inst instances (inst_ids, host), all
+ * starting from that instance's initial solution: init_ops (device) holds
+ * instance i's 2n ops at [i * 2 n_max), init_rt (device) its route ends at
+ * [i * m_max), where n_max, m_max are the largest n, m among inst_ids.  The
+ * initial solutions must be feasible (status 0).  Chain c = i *
+ * chains_per_inst + j.  Synchronous; allocates device memory.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int alns_state_create(alns_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
+                      int32_t chains_per_inst, const alns_params* params, uint64_t seed,
+                      const uint16_t* init_ops, const uint16_t* init_rt, void* stream);
+/* Runs `iterations` more iterations of every chain (asynchronous on stream). */
+int alns_step(alns_state* st, int32_t iterations, void* stream);
+/* Records (candidate makespan, current z, best z, destroy | repair << 8 |
+ * outcome << 16 | removed << 24) of every chain for the next `capacity`
+ * iterations into trace [chains][capacity][4] int64 (device), or stops
+ * recording (trace = NULL). */
+int alns_set_trace(alns_state* st, int64_t* trace, int64_t capacity);
+/* Best makespan (host out) and, if ops / rt_end are non-NULL, the best
+ * solution (device out, 2 n_max ops and m_max route ends) of one chain, or of
+ * the best chain when chain = -1.  Synchronises the stream. */
+int alns_get_best(const alns_state* st, int32_t chain, int32_t* mk, uint16_t* ops, uint16_t* rt_end, void* stream);
+/* Host copies of the iteration count and every chain's current and best
+ * makespan, temperature and operator weights ([chains][6], [chains][4]); any
+ * pointer may be NULL.  Synchronises the device. */
+int alns_get_state(const alns_state* st, int64_t* iterations, int32_t* z, int32_t* zb, double* T, double* wD,
+                   double* wR);
+int alns_state_destroy(alns_state* st);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,12 @@ SIGNATURES = {
     "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
                                _P, _P, _P, _P]),
     "brkga_warm_start": (C.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _U64, _I64, _P, _P, _P]),
+    "alns_state_create": (C.c_int, [C.POINTER(C.c_void_p), _P, _I32, _P, _I32, _P, _U64, _P, _P, _P]),
+    "alns_step": (C.c_int, [_P, _I32, _P]),
+    "alns_set_trace": (C.c_int, [_P, _P, _I64]),
+    "alns_get_best": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
+    "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "alns_state_destroy": (C.c_int, [_P]),
 }
 
 
@@ -230,3 +236,78 @@ def brkga_warm_start(S: InstanceSet, ops, rt_end, Np, n_warm, n_variants, seed, 
         n_variants, seed & (2**64 - 1), stride, _dptr(po, torch.float32, "prio_out"),
         _dptr(ho, torch.float32, "hint_out"), _stream(stream)))
     return po, ho
+
+
+class AlnsParams(C.Structure):
+    """alns_params of vrprpd.h (Table 2 hyper-parameters plus the repair budget)."""
+    _fields_ = [("T0", C.c_double), ("alpha", C.c_double), ("reheat", C.c_double), ("gate", C.c_double),
+                ("stag_limit", C.c_int32), ("tau", C.c_int32), ("r", C.c_double),
+                ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
+                ("w_min", C.c_double), ("q_min", C.c_int32), ("q_max", C.c_int32),
+                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32)]
+
+
+def alns_params(**kw):
+    d = dict(T0=0.30, alpha=0.9998, reheat=0.50, gate=0.01, stag_limit=2000, tau=100, r=0.1,
+             sigma1=33, sigma2=9, sigma3=13, w_min=0.1, q_min=0, q_max=0, tuple_budget=0,
+             import_interval=1000, op_mask=0x0F3F)
+    d.update(kw)
+    return AlnsParams(**d)
+
+
+class AlnsState:
+    """ALNS chains on the device (alns_state_create / alns_step)."""
+
+    def __init__(self, S: InstanceSet, inst_ids, chains_per_inst, params, seed, init_ops, init_rt,
+                 stream=None):
+        ids = (C.c_int32 * len(inst_ids))(*inst_ids)
+        h = C.c_void_p()
+        _check(load().alns_state_create(C.byref(h), S.handle, len(inst_ids), ids, chains_per_inst,
+                                        C.byref(params), seed & (2**64 - 1),
+                                        _dptr(init_ops, torch.uint16, "init_ops"),
+                                        _dptr(init_rt, torch.uint16, "init_rt"), _stream(stream)))
+        self.handle = h
+        self.S = S
+        self.chains = len(inst_ids) * chains_per_inst
+        self.n_max = max(S.instances[i].n for i in inst_ids)
+        self.m_max = max(S.instances[i].m for i in inst_ids)
+        self._trace = None
+
+    def step(self, iterations, stream=None):
+        _check(load().alns_step(self.handle, iterations, _stream(stream)))
+
+    def set_trace(self, capacity):
+        """Start recording per-iteration records into a new device tensor."""
+        self._trace = torch.zeros((self.chains, capacity, 4), dtype=torch.int64, device="cuda")
+        _check(load().alns_set_trace(self.handle, _dptr(self._trace, torch.int64, "trace"), capacity))
+        return self._trace
+
+    def best(self, chain=-1, stream=None):
+        mk = C.c_int32()
+        ops = torch.zeros(2 * self.n_max, dtype=torch.uint16, device="cuda")
+        rt = torch.zeros(self.m_max, dtype=torch.uint16, device="cuda")
+        _check(load().alns_get_best(self.handle, chain, C.byref(mk), _dptr(ops, torch.uint16, "ops"),
+                                    _dptr(rt, torch.uint16, "rt"), _stream(stream)))
+        return mk.value, ops, rt
+
+    def state(self):
+        it = C.c_int64()
+        z = np.zeros(self.chains, np.int32)
+        zb = np.zeros(self.chains, np.int32)
+        T = np.zeros(self.chains, np.float64)
+        wD = np.zeros((self.chains, 6), np.float64)
+        wR = np.zeros((self.chains, 4), np.float64)
+        _check(load().alns_get_state(self.handle, C.byref(it), z.ctypes.data, zb.ctypes.data, T.ctypes.data,
+                                     wD.ctypes.data, wR.ctypes.data))
+        return dict(iterations=it.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().alns_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

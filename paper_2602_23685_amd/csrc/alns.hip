@@ -1,0 +1,1308 @@
+// alns_step: Algorithm 1 of Section 4.2 for many chains on one device.
+//
+// Every chain (an independent ALNS instance of Section 4.2.1, item 1) keeps
+// its current solution S, its best S*, temperature, operator weights, scores
+// and attempt counts in device memory.  One iteration is a fixed sequence of
+// launches over all chains at once:
+//   begin    roulette selection of the destroy / repair operators, q
+//   gains    z(S) - z(S without c) for every customer (worst and critical-
+//            path removal only), one sweep per customer, many blocks per chain
+//   destroy  the removal list and the partial solution W = S minus it
+//   rounds   (q_max times) enumerate candidate tuples of every waiting
+//            customer, price them all exactly with the insertion scan, and
+//            insert the customer the repair operator picks
+//   accept   simulated annealing, scores, cooling, reheat, weight update
+// and every import_interval iterations the chains of an instance adopt the
+// best solution among them.  The operator and tie-breaking rules follow the
+// readings stated in the header of vrprpd.h's alns section.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "philox.h"
+#include "scan.h"
+#include "sweep.h"
+
+namespace vrprpd {
+
+constexpr uint32_t kTagAlns = 0x414C4E53u;
+constexpr int kND = 6, kNR = 4;
+constexpr long long kBigC = 1LL << 40;
+constexpr int kAlnsStep = 4;
+constexpr int kGainWaves = 4;   // gains kernel: 4 waves of 16-lane groups (m <= 16)
+constexpr int kGainGroups = 16;
+
+struct AlnsDev {
+    // problem
+    const InstDev* inst_tab;
+    const void* dist;
+    const int32_t* proc;
+    const int32_t* chain_inst;   // [C]
+    int32_t C, N, M, Q, TPC;     // chains, n_max, m_max, q_max, tuples per customer slot
+    alns_params prm;
+    uint64_t seed;
+    // solutions (stride 2N ops, M route ends per chain)
+    uint16_t *S_ops, *S_rt, *B_ops, *B_rt, *W_ops, *W_rt;   // W: two buffers per chain
+    int32_t* W_cur;
+    int32_t *z, *zb, *zn;
+    double *T, *T_init, *wD, *wR;
+    long long *sD, *sR;
+    int32_t *aD, *aR, *stag;
+    // per-iteration scratch
+    int32_t *di, *ri, *q, *nrem, *nleft, *KD, *KP, *rstate;   // rstate: 0 running, 1 done, 2 failed
+    int32_t *rem, *left;           // [C][Q]
+    long long* gains;              // [C][N+1]
+    vrprpd_tuple* tuples;          // [C][Q][TPC]
+    int32_t *tmk, *seg_cnt, *seg_base;
+    uint32_t* tst;
+    int64_t *seg_off, *seg_top3;
+    int64_t *base_op_off, *base_rt_off;   // [C] offsets of the current W buffers
+    int64_t* trace;                // [C][trace_cap][4] or null
+    int64_t trace_cap;
+};
+
+__device__ __forceinline__ uint32_t adraw(uint64_t seed, uint32_t a, uint32_t it, uint32_t chain)
+{
+    return philox_word(seed, a, it, chain, kTagAlns);
+}
+__device__ __forceinline__ double unit_d(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+__device__ __forceinline__ int uint_below(uint32_t w, int nval) { return (int)(((uint64_t)w * (uint64_t)nval) >> 32); }
+
+// exp(x) for x <= 0 by range reduction to |r| <= ln2/2 and a degree-16 Taylor
+// series: a fixed sequence of IEEE operations, so every implementation that
+// performs the same steps makes the same annealing decisions.
+__device__ __forceinline__ double det_exp(double x)
+{
+    if (x < -745.0) return 0.0;
+    const double LN2 = 0.6931471805599453;
+    const double k = floor(x / LN2 + 0.5);
+    const double r = x - k * LN2;
+    double s = 1.0, term = 1.0;
+    for (int i = 1; i <= 16; ++i) {
+        term = term * (r / (double)i);
+        s = s + term;
+    }
+    return ldexp(s, (int)k);
+}
+
+__device__ __forceinline__ int roulette(const double* w, int nops, uint32_t mask, double u)
+{
+    double tot = 0.0;
+    for (int i = 0; i < nops; ++i)
+        if (mask & (1u << i)) tot = tot + w[i];
+    const double target = u * tot;
+    double acc = 0.0;
+    int last = -1;
+    for (int i = 0; i < nops; ++i) {
+        if (!(mask & (1u << i))) continue;
+        acc = acc + w[i];
+        last = i;
+        if (target < acc) return i;
+    }
+    return last;
+}
+
+// Block-wide bitonic sort of n (power of two) u64 keys in LDS, ascending.
+__device__ void block_sort_u64(unsigned long long* key, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__host__ __device__ inline int pow2_ge(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Sequential carving of dynamic LDS into 16-byte aligned arrays; the host
+// sizes the allocation with the same rounding (LdsSize).
+struct Carve {
+    unsigned char* p;
+    template <typename T>
+    __device__ T* take(size_t count)
+    {
+        T* r = reinterpret_cast<T*>(p);
+        p += (count * sizeof(T) + 15) & ~(size_t)15;
+        return r;
+    }
+};
+struct LdsSize {
+    size_t bytes = 0;
+    template <typename T>
+    void take(size_t count) { bytes += (count * sizeof(T) + 15) & ~(size_t)15; }
+};
+
+// ---------------------------------------------------------------- begin
+__global__ void k_begin(AlnsDev a, uint32_t it)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    int qmin = a.prm.q_min, qmax = a.prm.q_max;
+    if (qmin <= 0 || qmax <= 0) {
+        qmax = I.n / 20;
+        if (qmax < 4) qmax = 4;
+        qmin = qmax / 2;
+        if (qmin < 4) qmin = 4;
+    }
+    if (qmax > I.n) qmax = I.n;
+    if (qmin > qmax) qmin = qmax;
+    const uint32_t dmask = a.prm.op_mask & 0x3Fu, rmask = (a.prm.op_mask >> 8) & 0xFu;
+    const int di = roulette(a.wD + kND * c, kND, dmask, unit_d(adraw(a.seed, 0, it, (uint32_t)c)));
+    const int ri = roulette(a.wR + kNR * c, kNR, rmask, unit_d(adraw(a.seed, 1, it, (uint32_t)c)));
+    const int q = qmin + uint_below(adraw(a.seed, 2, it, (uint32_t)c), qmax - qmin + 1);
+    a.di[c] = di;
+    a.ri[c] = ri;
+    a.q[c] = q;
+    a.aD[kND * c + di] += 1;
+    a.aR[kNR * c + ri] += 1;
+    a.rstate[c] = 0;
+    a.nleft[c] = 0;
+    a.nrem[c] = qmin;   // q_min of this chain, read by destroy
+}
+
+// Stages a chain's solution (ops + legs) in LDS.  Returns the op count.
+template <typename DT>
+__device__ int stage_solution(OpStore<DT>& S, const uint16_t* ops, const uint16_t* rt, int m, const DT* D, int N1,
+                              int* rs, int* re)
+{
+    if (threadIdx.x < m) {
+        rs[threadIdx.x] = threadIdx.x ? rt[threadIdx.x - 1] : 0;
+        re[threadIdx.x] = rt[threadIdx.x];
+    }
+    __syncthreads();
+    const int L = re[m - 1];
+    for (int j = threadIdx.x; j < L; j += blockDim.x) S.set_code(j, ops[j]);
+    __syncthreads();
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const int c = (int)(S.code(j) >> 1);
+        const int pc = j > 0 ? (int)(S.code(j - 1) >> 1) : 0;
+        S.set_leg(j, (int)D[pc * N1 + c]);
+    }
+    __syncthreads();
+    if (threadIdx.x < m && rs[threadIdx.x] < re[threadIdx.x])
+        S.set_leg(rs[threadIdx.x], (int)D[(int)(S.code(rs[threadIdx.x]) >> 1)]);
+    __syncthreads();
+    return L;
+}
+
+// Lane v's view of route v of the staged solution with customer `cust`'s ops
+// taken out (cust = 0: nothing removed).  Returns the route and its return leg.
+template <typename DT, bool kRec>
+__device__ DelRouteT<DT, kRec> del_route(const OpStore<DT>& S, const int* rs, const int* re, int lane, int m,
+                                         const uint16_t* posD, const uint16_t* posP, int cust, const DT* D, int N1,
+                                         int* times, int& ret)
+{
+    DelRouteT<DT, kRec> R;
+    R.S = &S;
+    R.times = times;
+    R.y1 = R.y2 = kNoPos;
+    R.lb1 = R.lb2 = 0;
+    R.bs = 0;
+    R.vlen = 0;
+    ret = 0;
+    if (lane >= m) return R;
+    const int s = rs[lane], e = re[lane];
+    R.bs = s;
+    int r[2], nr = 0;
+    if (cust) {
+        const int a = posD[cust], b = posP[cust];
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        if (lo >= s && lo < e) r[nr++] = lo - s;
+        if (hi >= s && hi < e) r[nr++] = hi - s;
+    }
+    const int len = e - s;
+    R.vlen = len - nr;
+    auto cust_at = [&](int rel) { return (int)(S.code(s + rel) >> 1); };
+    if (nr >= 1) {
+        R.y1 = r[0];
+        if (nr == 2) R.y2 = r[1] - 1;
+        // legs into the first kept op after each removed one
+        const int prev1 = r[0] > 0 ? cust_at(r[0] - 1) : 0;
+        if (nr == 2 && r[1] == r[0] + 1) {
+            if (r[1] + 1 < len) R.lb2 = (int)D[prev1 * N1 + cust_at(r[1] + 1)];
+        } else {
+            if (r[0] + 1 < len) R.lb1 = (int)D[prev1 * N1 + cust_at(r[0] + 1)];
+            if (nr == 2 && r[1] + 1 < len) R.lb2 = (int)D[cust_at(r[1] - 1) * N1 + cust_at(r[1] + 1)];
+        }
+    }
+    // return leg from the last kept op
+    int last = len - 1;
+    while (last >= 0 && ((nr >= 1 && last == r[0]) || (nr == 2 && last == r[1]))) --last;
+    ret = last >= 0 ? (int)D[cust_at(last) * N1] : 0;
+    return R;
+}
+
+// ---------------------------------------------------------------- gains
+// Block (chain, chunk): z(S without c) for the chunk's customers, one sweep
+// per customer per group.  Only chains drawing worst or critical-path removal.
+template <typename DT, int GL, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_gains(AlnsDev a, int per_block)
+{
+    constexpr int G = 64 / GL;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x;
+    const int di = a.di[c];
+    if (di != 1 && di != 5) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const int c0 = 1 + blockIdx.y * per_block;
+    if (c0 > n) return;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane % GL, gidx = wave * G + lane / GL;
+    Carve cv{smem};
+    int* pblk = cv.take<int>(a.N + 1);
+    uint16_t* posD = cv.take<uint16_t>(a.N + 2);
+    uint16_t* posP = cv.take<uint16_t>(a.N + 2);
+    int* rs = cv.take<int>(kMaxM);
+    int* re = cv.take<int>(kMaxM);
+    unsigned char* ops_base = cv.take<unsigned char>((size_t)OpStore<DT>::kBytesPerOp * (2 * a.N + kAlnsStep));
+    int* ready = cv.take<int>((size_t)WPB * G * (a.N + 1)) + gidx * (a.N + 1);
+    OpStore<DT> S;
+    S.init(ops_base, 2 * a.N + kAlnsStep);
+    for (int x = threadIdx.x; x <= n; x += blockDim.x) pblk[x] = x ? P[x] : 0;
+    const uint16_t* sops = a.S_ops + (int64_t)c * 2 * a.N;
+    const int L = stage_solution(S, sops, a.S_rt + (int64_t)c * a.M, m, D, N1, rs, re);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const uint32_t cd = S.code(j);
+        if (cd & 1u) posP[cd >> 1] = (uint16_t)j;
+        else posD[cd >> 1] = (uint16_t)j;
+    }
+    for (int x = li; x <= n; x += GL) ready[x] = -1;
+    __syncthreads();
+    int pol = 0;
+    const int zS = a.z[c];
+    const int c1 = min(n, c0 + per_block - 1);
+    int prev = 0;
+    for (int cust = c0 + gidx; cust <= c1; cust += WPB * G) {
+        // the customer left out last time is back: its entry is stale
+        if (li == 0 && prev) ready[prev] = pol ? 0 : -1;
+        wave_lds_fence();
+        prev = cust;
+        int ret;
+        const auto R = del_route<DT, false>(S, rs, re, li, m, posD, posP, cust, D, N1, nullptr, ret);
+        const SweepOut o = sweep_route<kAlnsStep, GL>(R, ready, pblk, pol);
+        pol ^= 1;
+        const int rv = (li < m && R.vlen > 0) ? o.t + ret : 0;
+        const int zc = group_max<GL>(rv);
+        if (li == 0) a.gains[(int64_t)c * (a.N + 1) + cust] = (long long)zS - zc;
+    }
+}
+
+// ---------------------------------------------------------------- destroy
+template <typename DT>
+__global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    const int di = a.di[c];
+    const int q_min = a.nrem[c];
+    int q = a.q[c];
+    if (q > n) q = n;
+    const int npow = pow2_ge(n);
+    Carve cv{smem};
+    unsigned long long* key = cv.take<unsigned long long>(pow2_ge(a.N));
+    int* times = cv.take<int>(2 * a.N + kAlnsStep);
+    int* pblk = cv.take<int>(a.N + 1);
+    uint16_t* posD = cv.take<uint16_t>(a.N + 2);
+    uint16_t* posP = cv.take<uint16_t>(a.N + 2);
+    unsigned char* flag = cv.take<unsigned char>(a.N + 1);
+    int* rs = cv.take<int>(kMaxM);
+    int* re = cv.take<int>(kMaxM);
+    int* rem = cv.take<int>(a.Q);
+    int* ready = cv.take<int>(a.N + 1);
+    unsigned char* ops_base = cv.take<unsigned char>((size_t)OpStore<DT>::kBytesPerOp * (2 * a.N + kAlnsStep));
+    __shared__ int sh_cnt;
+    OpStore<DT> S;
+    S.init(ops_base, 2 * a.N + kAlnsStep);
+    const uint16_t* sops = a.S_ops + (int64_t)c * 2 * a.N;
+    const uint16_t* srt = a.S_rt + (int64_t)c * a.M;
+    const int L = stage_solution(S, sops, srt, m, D, N1, rs, re);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const uint32_t cd = S.code(j);
+        if (cd & 1u) posP[cd >> 1] = (uint16_t)j;
+        else posD[cd >> 1] = (uint16_t)j;
+    }
+    for (int x = threadIdx.x; x <= n; x += blockDim.x) {
+        pblk[x] = x ? P[x] : 0;
+        flag[x] = 0;
+        ready[x] = -1;
+    }
+    if (threadIdx.x == 0) sh_cnt = 0;
+    __syncthreads();
+
+    // times of every op of S (Shaw needs drop times, critical path the returns)
+    if (di == 2 || di == 5) {
+        if (threadIdx.x < 64) {
+            int ret;
+            const auto R = del_route<DT, true>(S, rs, re, threadIdx.x, m, posD, posP, 0, D, N1, times, ret);
+            (void)sweep_route<kAlnsStep, 64>(R, ready, pblk, 0);
+        }
+    }
+    __syncthreads();
+    const long long* gain = a.gains + (int64_t)c * (a.N + 1);
+    const uint32_t uc = (uint32_t)c;
+    if (di == 0) {                                   // random: partial Fisher-Yates
+        int* perm = reinterpret_cast<int*>(key);
+        for (int x = threadIdx.x; x < n; x += blockDim.x) perm[x] = x + 1;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < q; ++i) {
+                const int j = i + uint_below(adraw(a.seed, 16 + i, it, uc), n - i);
+                const int x = perm[i];
+                perm[i] = perm[j];
+                perm[j] = x;
+                rem[i] = perm[i];
+            }
+            sh_cnt = q;
+        }
+    } else if (di == 1) {                            // worst: rank by gain, weight 2^60 / r^6
+        for (int x = threadIdx.x; x < npow; x += blockDim.x)
+            key[x] = x < n ? (((unsigned long long)((1LL << 34) - gain[x + 1]) << 16) | (unsigned)(x + 1)) : ~0ull;
+        __syncthreads();
+        block_sort_u64(key, npow);
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int i = 0; i < n && i < 1024; ++i) {
+                const unsigned long long r = (unsigned long long)(i + 1);
+                tot += (1ULL << 60) / (r * r * r * r * r * r);
+            }
+            int cnt = 0;
+            for (int s2 = 0; s2 < q; ++s2) {
+                if (tot == 0) break;
+                const unsigned long long w32 = adraw(a.seed, 16 + s2, it, uc);
+                const unsigned long long hi = (w32 * (tot >> 32)) + ((w32 * (tot & 0xFFFFFFFFull)) >> 32);
+                unsigned long long acc = 0;
+                int pick = -1;
+                for (int i = 0; i < n; ++i) {
+                    const unsigned long long r = (unsigned long long)(i + 1);
+                    const unsigned long long w = (i < 1024 && !flag[i]) ? (1ULL << 60) / (r * r * r * r * r * r) : 0ULL;
+                    acc += w;
+                    if (w && hi < acc) { pick = i; break; }
+                }
+                const unsigned long long r = (unsigned long long)(pick + 1);
+                tot -= (1ULL << 60) / (r * r * r * r * r * r);
+                flag[pick] = 1;
+                rem[cnt++] = (int)(key[pick] & 0xFFFFu);
+            }
+            sh_cnt = cnt;
+        }
+    } else if (di == 2 || di == 3) {                 // Shaw, cluster
+        const int cen = 1 + uint_below(adraw(a.seed, 16, it, uc), n);
+        for (int x = threadIdx.x; x < npow; x += blockDim.x) {
+            unsigned long long k = ~0ull;
+            const int cc = x + 1;
+            if (x < n && cc != cen) {
+                long long rel;
+                if (di == 3) {
+                    rel = (long long)D[cen * N1 + cc];
+                } else {
+                    long long dt = (long long)times[posD[cen]] - times[posD[cc]];
+                    dt = dt < 0 ? -dt : dt;
+                    auto veh_of = [&](int pos) {
+                        int v = 0;
+                        while (v < m - 1 && pos >= re[v]) ++v;
+                        return v;
+                    };
+                    rel = 18LL * D[cen * N1 + cc] + 6 * dt + 5 * (veh_of(posD[cen]) != veh_of(posD[cc])) +
+                          5 * (veh_of(posP[cen]) != veh_of(posP[cc]));
+                }
+                k = ((unsigned long long)rel << 16) | (unsigned)cc;
+            }
+            key[x] = k;
+        }
+        __syncthreads();
+        block_sort_u64(key, npow);
+        if (threadIdx.x == 0) {
+            int cnt = 0;
+            rem[cnt++] = cen;
+            for (int i = 0; i < n - 1 && cnt < q; ++i) rem[cnt++] = (int)(key[i] & 0xFFFFu);
+            sh_cnt = cnt;
+        }
+    } else if (di == 4) {                            // route
+        if (threadIdx.x == 0) {
+            int nonempty = 0;
+            for (int v = 0; v < m; ++v) nonempty += re[v] > rs[v];
+            const int pickv = uint_below(adraw(a.seed, 16, it, uc), nonempty);
+            int v = 0;
+            for (int seen = -1; v < m; ++v)
+                if (re[v] > rs[v] && ++seen == pickv) break;
+            int cnt = 0;
+            for (int j = rs[v]; j < re[v] && cnt < q; ++j) {
+                const int cc = (int)(S.code(j) >> 1);
+                if (!flag[cc]) {
+                    flag[cc] = 1;
+                    rem[cnt++] = cc;
+                }
+            }
+            sh_cnt = cnt;
+        }
+        __syncthreads();
+        const int cnt0 = sh_cnt;
+        if (cnt0 < q_min) {
+            for (int x = threadIdx.x; x < npow; x += blockDim.x) {
+                unsigned long long k = ~0ull;
+                const int cc = x + 1;
+                if (x < n && !flag[cc]) {
+                    long long best = 0x7FFFFFFFFFFFLL;
+                    for (int i = 0; i < cnt0; ++i) {
+                        const long long dd = (long long)D[rem[i] * N1 + cc];
+                        best = dd < best ? dd : best;
+                    }
+                    k = ((unsigned long long)best << 16) | (unsigned)cc;
+                }
+                key[x] = k;
+            }
+            __syncthreads();
+            block_sort_u64(key, npow);
+            if (threadIdx.x == 0) {
+                int cnt = cnt0;
+                for (int i = 0; i < n && cnt < q_min && key[i] != ~0ull; ++i) rem[cnt++] = (int)(key[i] & 0xFFFFu);
+                sh_cnt = cnt;
+            }
+        }
+    } else {                                         // critical path
+        if (threadIdx.x == 0) {
+            int bv = -1;
+            long long bret = -1;
+            for (int v = 0; v < m; ++v) {
+                if (re[v] == rs[v]) continue;
+                const int last = re[v] - 1;
+                const long long r = (long long)times[last] + D[(int)(S.code(last) >> 1) * N1];
+                if (r > bret) { bret = r; bv = v; }
+            }
+            for (int j = rs[bv]; j < re[bv]; ++j) flag[S.code(j) >> 1] = 1;
+        }
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int x = threadIdx.x; x < npow; x += blockDim.x) {
+                unsigned long long k = ~0ull;
+                const int cc = x + 1;
+                if (x < n && (flag[cc] != 0) == (pass == 0))
+                    k = ((unsigned long long)((1LL << 34) - gain[cc]) << 16) | (unsigned)cc;
+                key[x] = k;
+            }
+            __syncthreads();
+            block_sort_u64(key, npow);
+            if (threadIdx.x == 0) {
+                int cnt = pass == 0 ? 0 : sh_cnt;
+                const int lim = pass == 0 ? q : q_min;
+                for (int i = 0; i < n && cnt < lim && key[i] != ~0ull; ++i) rem[cnt++] = (int)(key[i] & 0xFFFFu);
+                sh_cnt = cnt;
+            }
+            __syncthreads();
+            if (pass == 0 && sh_cnt >= q_min) break;
+        }
+    }
+    __syncthreads();
+    const int nrem = sh_cnt;
+    // W = S without the removed customers
+    for (int x = threadIdx.x; x <= n; x += blockDim.x) flag[x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nrem; i += blockDim.x) flag[rem[i]] = 1;
+    __syncthreads();
+    uint16_t* wops = a.W_ops + ((int64_t)2 * c + 0) * 2 * a.N;
+    uint16_t* wrt = a.W_rt + ((int64_t)2 * c + 0) * a.M;
+    if (threadIdx.x == 0) {
+        int w = 0;
+        for (int v = 0; v < m; ++v) {
+            for (int j = rs[v]; j < re[v]; ++j)
+                if (!flag[S.code(j) >> 1]) wops[w++] = (uint16_t)S.code(j);
+            wrt[v] = (uint16_t)w;
+        }
+        a.W_cur[c] = 0;
+        a.base_op_off[c] = ((int64_t)2 * c + 0) * 2 * a.N;
+        a.base_rt_off[c] = ((int64_t)2 * c + 0) * a.M;
+        a.nrem[c] = nrem;
+        a.nleft[c] = nrem;
+        for (int i = 0; i < nrem; ++i) a.left[c * a.Q + i] = rem[i];
+        int KD = 0, KP = 0;
+        if (a.prm.tuple_budget > 0) {
+            long long tc = (long long)a.prm.tuple_budget / ((long long)nrem * (nrem + 1) / 2);
+            if (tc < 1) tc = 1;
+            KD = (int)floor(sqrt((double)tc));
+            if (KD < 1) KD = 1;
+            KP = (int)(tc / KD);
+            if (KP < 1) KP = 1;
+        }
+        a.KD[c] = KD;
+        a.KP[c] = KP;
+        a.rstate[c] = nrem > 0 ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------------------- enumerate
+// Block (chain, slot i): candidate tuples of the i-th waiting customer
+// against the chain's partial solution W, in this order: the drop slots
+// ranked by (detour, vehicle, position), the best K_D; for each, the pickup
+// slots ranked the same way on the route after the drop went in, the best K_P.
+__device__ __forceinline__ unsigned long long slot_key(long long det, int v, int p)
+{
+    return ((unsigned long long)(det + (1LL << 31)) << 22) | ((unsigned long long)v << 16) | (unsigned)p;
+}
+
+template <typename DT>
+__global__ __launch_bounds__(256) void k_enum(AlnsDev a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x, slot = blockIdx.y;
+    const int sidx = c * a.Q + slot;
+    if (a.rstate[c] != 0 || slot >= a.nleft[c]) {
+        if (threadIdx.x == 0) a.seg_cnt[sidx] = 0;
+        return;
+    }
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int cust = a.left[c * a.Q + slot];
+    const int wb = a.W_cur[c];
+    const uint16_t* wops = a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N;
+    const uint16_t* wrt = a.W_rt + ((int64_t)2 * c + wb) * a.M;
+    __shared__ int rs[kMaxM], re[kMaxM], cum[kMaxM + 1];
+    if (threadIdx.x < m) {
+        rs[threadIdx.x] = threadIdx.x ? wrt[threadIdx.x - 1] : 0;
+        re[threadIdx.x] = wrt[threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cum[0] = 0;
+        for (int v = 0; v < m; ++v) cum[v + 1] = cum[v] + (re[v] - rs[v]) + 1;
+    }
+    __syncthreads();
+    const int L = re[m - 1];
+    const int nslots = L + m;            // drop slots
+    const int npow = pow2_ge(nslots + 1);
+    unsigned long long* key = reinterpret_cast<unsigned long long*>(smem);
+    unsigned long long* dsel = key + npow;
+    auto cust_at = [&](int j) { return (int)(wops[j] >> 1); };
+    auto det = [&](int x, int y) { return (long long)D[x * N1 + cust] + D[cust * N1 + y] - D[x * N1 + y]; };
+    for (int k = threadIdx.x; k < npow; k += blockDim.x) {
+        unsigned long long kv = ~0ull;
+        if (k < nslots) {
+            int v = 0;
+            while (cum[v + 1] <= k) ++v;
+            const int p = k - cum[v], len = re[v] - rs[v];
+            const int x = p > 0 ? cust_at(rs[v] + p - 1) : 0;
+            const int y = p < len ? cust_at(rs[v] + p) : 0;
+            kv = slot_key(det(x, y), v, p);
+        }
+        key[k] = kv;
+    }
+    __syncthreads();
+    block_sort_u64(key, npow);
+    const int KD = a.KD[c], KP = a.KP[c];
+    const int nd = (KD > 0 && KD < nslots) ? KD : nslots;
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) dsel[k] = key[k];
+    __syncthreads();
+    vrprpd_tuple* out = a.tuples + (int64_t)sidx * a.TPC;
+    int T = 0;
+    const int npslots = L + m;           // route vD keeps its len+1 slot indices, some unused
+    const int ppow = pow2_ge(npslots);
+    for (int di = 0; di < nd; ++di) {
+        const int vD = (int)((dsel[di] >> 16) & 0x3Fu), pD = (int)(dsel[di] & 0xFFFFu);
+        for (int k = threadIdx.x; k < ppow; k += blockDim.x) {
+            unsigned long long kv = ~0ull;
+            if (k < npslots) {
+                // slots of routes before vD, then vD's len+1 slots (after the drop), then the rest
+                int v = 0, p;
+                const int lenD = re[vD] - rs[vD];
+                const int startD = cum[vD];                  // slots before route vD
+                if (k < startD) {
+                    while (cum[v + 1] <= k) ++v;
+                    p = k - cum[v];
+                } else if (k < startD + lenD + 1) {
+                    v = vD;
+                    p = pD + 1 + (k - startD);
+                } else {
+                    v = vD + 1;
+                    while (cum[v + 1] <= k) ++v;
+                    p = k - cum[v];
+                }
+                const int len = re[v] - rs[v];
+                int x, y;
+                if (v == vD) {
+                    if (p > lenD + 1) { key[k] = ~0ull; continue; }
+                    x = (p - 1 == pD) ? cust : cust_at(rs[v] + p - 2);
+                    y = (p <= lenD) ? cust_at(rs[v] + p - 1) : 0;
+                } else {
+                    x = p > 0 ? cust_at(rs[v] + p - 1) : 0;
+                    y = p < len ? cust_at(rs[v] + p) : 0;
+                }
+                kv = slot_key(det(x, y), v, p);
+            }
+            key[k] = kv;
+        }
+        __syncthreads();
+        block_sort_u64(key, ppow);
+        int cntP = 0;
+        for (int k = 0; k < ppow && key[k] != ~0ull; ++k) ++cntP;
+        const int np = (KP > 0 && KP < cntP) ? KP : cntP;
+        for (int k = threadIdx.x; k < np && T + k < a.TPC; k += blockDim.x) {
+            vrprpd_tuple t;
+            t.c = (uint16_t)cust;
+            t.vD = (uint8_t)vD;
+            t.pD = (uint16_t)pD;
+            t.vP = (uint8_t)((key[k] >> 16) & 0x3Fu);
+            t.pP = (uint16_t)(key[k] & 0xFFFFu);
+            out[T + k] = t;
+        }
+        T += np;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.seg_cnt[sidx] = T < a.TPC ? T : a.TPC;
+}
+
+// ---------------------------------------------------------------- select
+// Block per chain: price every waiting customer from the scan results, pick
+// one by the repair operator's rule, insert it into W.
+__global__ __launch_bounds__(256) void k_select(AlnsDev a)
+{
+    const int c = blockIdx.x;
+    if (a.rstate[c] != 0) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int m = I.m;
+    const int nl = a.nleft[c], ri = a.ri[c];
+    const int kreg = ri == 1 ? 2 : ri == 2 ? 3 : m;
+    __shared__ long long opt[kMaxM];
+    __shared__ long long best_c1, best_reg;
+    __shared__ int best_i, fail;
+    __shared__ long long best_key;
+    if (threadIdx.x == 0) {
+        best_i = -1;
+        fail = 0;
+    }
+    __syncthreads();
+    for (int i = 0; i < nl; ++i) {
+        const int sidx = c * a.Q + i;
+        const long long key0 = a.seg_top3[3 * sidx];
+        if (key0 == INT64_MAX) {
+            if (threadIdx.x == 0) fail = 1;
+            break;
+        }
+        if (threadIdx.x < m) opt[threadIdx.x] = kBigC;
+        __syncthreads();
+        const int cnt = a.seg_cnt[sidx];
+        const int64_t t0 = a.seg_off[sidx];
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+            if (a.tst[t0 + k] != 0) continue;
+            atomicMin((unsigned long long*)&opt[a.tuples[t0 + k].vD], (unsigned long long)a.tmk[t0 + k]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const long long c1 = key0 >> 32;
+            long long reg = 0;
+            if (ri != 0) {
+                long long* o = opt;   // sorted in place (LDS), ascending
+                for (int x = 1; x < m; ++x)
+                    for (int y = x; y > 0 && o[y] < o[y - 1]; --y) {
+                        const long long t = o[y];
+                        o[y] = o[y - 1];
+                        o[y - 1] = t;
+                    }
+                for (int h = 1; h < kreg && h < m; ++h) reg += o[h] - o[0];
+                for (int h = m; h < kreg; ++h) reg += kBigC - o[0];
+            }
+            bool better;
+            if (best_i < 0) better = true;
+            else if (ri == 0) better = c1 < best_c1;
+            else better = reg > best_reg || (reg == best_reg && c1 < best_c1);
+            if (better) {
+                best_i = i;
+                best_c1 = c1;
+                best_reg = reg;
+                best_key = key0;
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (fail) {
+        if (threadIdx.x == 0) {
+            a.rstate[c] = 2;
+            a.zn[c] = INT32_MAX;
+        }
+        return;
+    }
+    // insert the chosen tuple into the other W buffer
+    const vrprpd_tuple tp = a.tuples[(uint32_t)(best_key & 0xFFFFFFFFll)];
+    const int wb = a.W_cur[c];
+    const uint16_t* src = a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N;
+    const uint16_t* srt = a.W_rt + ((int64_t)2 * c + wb) * a.M;
+    uint16_t* dst = a.W_ops + ((int64_t)2 * c + (wb ^ 1)) * 2 * a.N;
+    uint16_t* drt = a.W_rt + ((int64_t)2 * c + (wb ^ 1)) * a.M;
+    __shared__ int nstart[kMaxM + 1];
+    if (threadIdx.x == 0) {
+        int w = 0;
+        for (int v = 0; v < m; ++v) {
+            nstart[v] = w;
+            const int len = srt[v] - (v ? srt[v - 1] : 0);
+            w += len + (v == tp.vD) + (v == tp.vP);
+            drt[v] = (uint16_t)w;
+        }
+        nstart[m] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int v = threadIdx.x;
+        const int s = v ? srt[v - 1] : 0, len = srt[v] - s;
+        int w = nstart[v];
+        // virtual positions of the inserted ops on this route
+        int x1 = kNoPos, x2 = kNoPos;
+        uint16_t k1 = 0, k2 = 0;
+        if (v == tp.vD && v == tp.vP) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); x2 = tp.pP; k2 = (uint16_t)((tp.c << 1) | 1); }
+        else if (v == tp.vD) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); }
+        else if (v == tp.vP) { x1 = tp.pP; k1 = (uint16_t)((tp.c << 1) | 1); }
+        const int vlen = len + (x1 != kNoPos) + (x2 != kNoPos);
+        for (int i = 0; i < vlen; ++i) {
+            uint16_t code;
+            if (i == x1) code = k1;
+            else if (i == x2) code = k2;
+            else code = src[s + i - (i > x1) - (i > x2)];
+            dst[w + i] = code;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.W_cur[c] = wb ^ 1;
+        a.base_op_off[c] = ((int64_t)2 * c + (wb ^ 1)) * 2 * a.N;
+        a.base_rt_off[c] = ((int64_t)2 * c + (wb ^ 1)) * a.M;
+        a.zn[c] = (int)(best_key >> 32);
+        int* lf = a.left + c * a.Q;
+        for (int i = best_i; i + 1 < nl; ++i) lf[i] = lf[i + 1];
+        a.nleft[c] = nl - 1;
+        if (nl - 1 == 0) a.rstate[c] = 1;
+    }
+}
+
+// ---------------------------------------------------------------- accept
+__global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t trace_it)
+{
+    const int c = blockIdx.x;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int m = I.m;
+    __shared__ int copyS, copyB;
+    if (threadIdx.x == 0) {
+        const alns_params& P = a.prm;
+        const int di = a.di[c], ri = a.ri[c];
+        const bool ok = a.rstate[c] == 1;
+        const int zn = ok ? a.zn[c] : INT32_MAX;
+        int accepted = 0;
+        copyS = copyB = 0;
+        double* T = a.T + c;
+        if (ok) {
+            if (zn < a.z[c]) {
+                a.z[c] = zn;
+                a.sD[kND * c + di] += P.sigma2;
+                a.sR[kNR * c + ri] += P.sigma2;
+                accepted = 1;
+                copyS = 1;
+                if (zn < a.zb[c]) {
+                    a.zb[c] = zn;
+                    a.sD[kND * c + di] += P.sigma1 - P.sigma2;
+                    a.sR[kNR * c + ri] += P.sigma1 - P.sigma2;
+                    a.stag[c] = 0;
+                    accepted = 2;
+                    copyB = 1;
+                }
+            } else {
+                const double u = unit_d(adraw(a.seed, 8, it, (uint32_t)c));
+                const double pacc = det_exp(-((double)zn - (double)a.z[c]) / *T);
+                if (u < pacc) {
+                    a.z[c] = zn;
+                    a.sD[kND * c + di] += P.sigma3;
+                    a.sR[kNR * c + ri] += P.sigma3;
+                    accepted = 3;
+                    copyS = 1;
+                }
+            }
+        }
+        *T = P.alpha * *T;
+        a.stag[c] += 1;
+        if (a.stag[c] >= P.stag_limit && *T < P.gate * a.T_init[c]) {
+            *T = P.reheat * P.T0 * (double)a.zb[c];
+            a.stag[c] = 0;
+        }
+        if ((it + 1) % (uint32_t)P.tau == 0) {
+            for (int i = 0; i < kND; ++i) {
+                const int k = kND * c + i;
+                if (a.aD[k] > 0) {
+                    const double w = (1.0 - P.r) * a.wD[k] + P.r * ((double)a.sD[k] / (double)a.aD[k]);
+                    a.wD[k] = w > P.w_min ? w : P.w_min;
+                }
+                a.sD[k] = 0;
+                a.aD[k] = 0;
+            }
+            for (int i = 0; i < kNR; ++i) {
+                const int k = kNR * c + i;
+                if (a.aR[k] > 0) {
+                    const double w = (1.0 - P.r) * a.wR[k] + P.r * ((double)a.sR[k] / (double)a.aR[k]);
+                    a.wR[k] = w > P.w_min ? w : P.w_min;
+                }
+                a.sR[k] = 0;
+                a.aR[k] = 0;
+            }
+        }
+        if (a.trace && trace_it >= 0 && trace_it < a.trace_cap) {
+            int64_t* tr = a.trace + ((int64_t)c * a.trace_cap + trace_it) * 4;
+            tr[0] = zn;
+            tr[1] = a.z[c];
+            tr[2] = a.zb[c];
+            tr[3] = (int64_t)di | ((int64_t)ri << 8) | ((int64_t)accepted << 16) | ((int64_t)a.nrem[c] << 24);
+        }
+    }
+    __syncthreads();
+    if (copyS || copyB) {
+        const int wb = a.W_cur[c];
+        const uint16_t* wops = a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N;
+        const uint16_t* wrt = a.W_rt + ((int64_t)2 * c + wb) * a.M;
+        const int L = wrt[m - 1];
+        for (int j = threadIdx.x; j < L; j += blockDim.x) {
+            if (copyS) a.S_ops[(int64_t)c * 2 * a.N + j] = wops[j];
+            if (copyB) a.B_ops[(int64_t)c * 2 * a.N + j] = wops[j];
+        }
+        for (int v = threadIdx.x; v < m; v += blockDim.x) {
+            if (copyS) a.S_rt[(int64_t)c * a.M + v] = wrt[v];
+            if (copyB) a.B_rt[(int64_t)c * a.M + v] = wrt[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- import
+// Block per instance: chains [c0, c0 + cpi) adopt the best of them.
+__global__ __launch_bounds__(256) void k_import(AlnsDev a, int cpi)
+{
+    const int c0 = blockIdx.x * cpi;
+    __shared__ int bc;
+    if (threadIdx.x == 0) {
+        bc = c0;
+        for (int c = c0 + 1; c < c0 + cpi; ++c)
+            if (a.zb[c] < a.zb[bc]) bc = c;
+    }
+    __syncthreads();
+    const InstDev I = a.inst_tab[a.chain_inst[c0]];
+    const int m = I.m;
+    const int L = a.B_rt[(int64_t)bc * a.M + m - 1];
+    for (int c = c0; c < c0 + cpi; ++c) {
+        if (a.zb[c] <= a.zb[bc]) continue;
+        for (int j = threadIdx.x; j < L; j += blockDim.x) {
+            const uint16_t x = a.B_ops[(int64_t)bc * 2 * a.N + j];
+            a.B_ops[(int64_t)c * 2 * a.N + j] = x;
+            a.S_ops[(int64_t)c * 2 * a.N + j] = x;
+        }
+        for (int v = threadIdx.x; v < m; v += blockDim.x) {
+            const uint16_t x = a.B_rt[(int64_t)bc * a.M + v];
+            a.B_rt[(int64_t)c * a.M + v] = x;
+            a.S_rt[(int64_t)c * a.M + v] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.zb[c] = a.zb[bc];
+            a.z[c] = a.zb[bc];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace vrprpd
+
+// ============================================================== host side
+
+struct alns_state {
+    const vrprpd_set* set = nullptr;
+    vrprpd::AlnsDev d{};
+    int32_t n_inst = 0, cpi = 0;       // instances, chains per instance
+    int64_t it = 0;                    // iterations done
+    int dist16 = 1;
+    std::vector<void*> allocs;
+    int64_t trace_base = 0;            // iteration of trace row 0
+    int lds_gain = 0, lds_destroy = 0, lds_enum = 0;
+};
+
+namespace vrprpd {
+
+static int alloc_dev(alns_state* s, void** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return hip_error(e, "alns_state_create: hipMalloc");
+    s->allocs.push_back(*p);
+    e = hipMemset(*p, 0, bytes);
+    if (e != hipSuccess) return hip_error(e, "alns_state_create: hipMemset");
+    return VRPRPD_OK;
+}
+
+template <typename T>
+static int alloc_n(alns_state* s, T** p, size_t n)
+{
+    return alloc_dev(s, reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+static int tpc_bound(const alns_params& P, int n, int m, int qmin)
+{
+    if (P.tuple_budget <= 0) {
+        const long long s = 2LL * n + m;
+        return (int)(s * (s + 1));
+    }
+    int best = 1;
+    for (int nrem = (qmin > 1 ? qmin : 1); nrem <= n; ++nrem) {
+        long long tc = (long long)P.tuple_budget / ((long long)nrem * (nrem + 1) / 2);
+        if (tc < 1) tc = 1;
+        int KD = (int)std::floor(std::sqrt((double)tc));
+        if (KD < 1) KD = 1;
+        int KP = (int)(tc / KD);
+        if (KP < 1) KP = 1;
+        if (KD * KP > best) best = KD * KP;
+        if (tc == 1) break;
+    }
+    return best;
+}
+
+static void qrange(const alns_params& P, int n, int* qmin, int* qmax)
+{
+    int a = P.q_min, b = P.q_max;
+    if (a <= 0 || b <= 0) {
+        b = n / 20;
+        if (b < 4) b = 4;
+        a = b / 2;
+        if (a < 4) a = 4;
+    }
+    if (b > n) b = n;
+    if (a > b) a = b;
+    *qmin = a;
+    *qmax = b;
+}
+
+}  // namespace vrprpd
+
+extern "C" int alns_state_destroy(alns_state* s)
+{
+    if (!s) return VRPRPD_OK;
+    for (void* p : s->allocs) (void)hipFree(p);
+    delete s;
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
+                                 int32_t chains_per_inst, const alns_params* params, uint64_t seed,
+                                 const uint16_t* init_ops, const uint16_t* init_rt, void* stream)
+{
+    using namespace vrprpd;
+    if (!out) return set_error(VRPRPD_EINVAL, "alns_state_create: out is NULL");
+    *out = nullptr;
+    if (!set || n_inst < 1 || !inst_ids || chains_per_inst < 1 || !params || !init_ops || !init_rt)
+        return set_error(VRPRPD_EINVAL, "alns_state_create: bad arguments");
+    const alns_params& P = *params;
+    if (P.tau < 1 || !(P.alpha > 0.0) || !(P.T0 > 0.0) || (P.op_mask & 0x3Fu) == 0 || ((P.op_mask >> 8) & 0xFu) == 0)
+        return set_error(VRPRPD_EINVAL, "alns_state_create: tau >= 1, alpha > 0, T0 > 0 and at least one "
+                                        "destroy and one repair operator are required");
+    int N = 0, M = 0, Q = 0, TPC = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (inst_ids[i] < 0 || inst_ids[i] >= set->num_inst)
+            return set_error(VRPRPD_EINVAL, "alns_state_create: instance id %d out of range", inst_ids[i]);
+        const InstDev& h = set->host[inst_ids[i]];
+        N = std::max(N, h.n);
+        M = std::max(M, h.m);
+        int a, b;
+        qrange(P, h.n, &a, &b);
+        Q = std::max(Q, b);
+        TPC = std::max(TPC, tpc_bound(P, h.n, h.m, a));
+    }
+    const int C = n_inst * chains_per_inst;
+    if ((long long)C * Q * TPC >= (1LL << 31))
+        return set_error(VRPRPD_EINVAL, "alns_state_create: %d chains x %d rounds x %d tuples is too many", C, Q, TPC);
+    auto* s = new alns_state();
+    s->set = set;
+    s->n_inst = n_inst;
+    s->cpi = chains_per_inst;
+    s->dist16 = set->dist16;
+    AlnsDev& d = s->d;
+    d.inst_tab = set->d_inst;
+    d.dist = set->d_dist;
+    d.proc = set->d_proc;
+    d.C = C;
+    d.N = N;
+    d.M = M;
+    d.Q = Q;
+    d.TPC = TPC;
+    d.prm = P;
+    d.seed = seed;
+    int rc = VRPRPD_OK;
+#define A(ptr, n)                                        \
+    if (rc == VRPRPD_OK) rc = alloc_n(s, &(ptr), (size_t)(n))
+    int32_t* cinst = nullptr;
+    A(cinst, C);
+    A(d.S_ops, (size_t)C * 2 * N); A(d.S_rt, (size_t)C * M);
+    A(d.B_ops, (size_t)C * 2 * N); A(d.B_rt, (size_t)C * M);
+    A(d.W_ops, (size_t)2 * C * 2 * N); A(d.W_rt, (size_t)2 * C * M);
+    A(d.W_cur, C); A(d.z, C); A(d.zb, C); A(d.zn, C);
+    A(d.T, C); A(d.T_init, C); A(d.wD, (size_t)kND * C); A(d.wR, (size_t)kNR * C);
+    A(d.sD, (size_t)kND * C); A(d.sR, (size_t)kNR * C); A(d.aD, (size_t)kND * C); A(d.aR, (size_t)kNR * C);
+    A(d.stag, C); A(d.di, C); A(d.ri, C); A(d.q, C); A(d.nrem, C); A(d.nleft, C); A(d.KD, C); A(d.KP, C);
+    A(d.rstate, C); A(d.rem, (size_t)C * Q); A(d.left, (size_t)C * Q); A(d.gains, (size_t)C * (N + 1));
+    A(d.tuples, (size_t)C * Q * TPC); A(d.tmk, (size_t)C * Q * TPC); A(d.tst, (size_t)C * Q * TPC);
+    A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
+    A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C);
+#undef A
+    if (rc != VRPRPD_OK) {
+        alns_state_destroy(s);
+        return rc;
+    }
+    d.chain_inst = cinst;
+    // host-side tables
+    std::vector<int32_t> hc(C), hsb((size_t)C * Q);
+    std::vector<int64_t> hso((size_t)C * Q + 1);
+    for (int c = 0; c < C; ++c) hc[c] = inst_ids[c / chains_per_inst];
+    for (size_t i = 0; i < (size_t)C * Q; ++i) {
+        hsb[i] = (int32_t)(i / Q);
+        hso[i] = (int64_t)i * TPC;
+    }
+    hso[(size_t)C * Q] = (int64_t)C * Q * TPC;
+    std::vector<double> w1((size_t)kND * C, 1.0), w2((size_t)kNR * C, 1.0);
+    hipError_t e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((e = hipMemcpy(cinst, hc.data(), C * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.seg_base, hsb.data(), hsb.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.seg_off, hso.data(), hso.size() * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.wD, w1.data(), w1.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.wR, w2.data(), w2.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+        alns_state_destroy(s);
+        return hip_error(e, "alns_state_create: hipMemcpy");
+    }
+    // initial solutions: instance i's solution at init_ops + i * 2N? no: the
+    // caller gives one solution per instance, ops at [i * 2 n_max], route ends at [i * m_max]
+    for (int c = 0; c < C; ++c) {
+        const int i = c / chains_per_inst;
+        const InstDev& h = set->host[inst_ids[i]];
+        if ((e = hipMemcpyAsync(d.S_ops + (size_t)c * 2 * N, init_ops + (size_t)i * 2 * N, 2 * h.n * sizeof(uint16_t),
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(d.S_rt + (size_t)c * M, init_rt + (size_t)i * M, h.m * sizeof(uint16_t),
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(d.B_ops + (size_t)c * 2 * N, init_ops + (size_t)i * 2 * N, 2 * h.n * sizeof(uint16_t),
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(d.B_rt + (size_t)c * M, init_rt + (size_t)i * M, h.m * sizeof(uint16_t),
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess) {
+            alns_state_destroy(s);
+            return hip_error(e, "alns_state_create: copy of the initial solutions");
+        }
+    }
+    // evaluate the initial solutions; they must be feasible
+    std::vector<int64_t> hoff(C), hroff(C);
+    for (int c = 0; c < C; ++c) {
+        hoff[c] = (int64_t)c * 2 * N;
+        hroff[c] = (int64_t)c * M;
+    }
+    int64_t *doff = nullptr, *droff = nullptr;
+    uint32_t* dst = nullptr;
+    if ((rc = alloc_n(s, &doff, C)) || (rc = alloc_n(s, &droff, C)) || (rc = alloc_n(s, &dst, C))) {
+        alns_state_destroy(s);
+        return rc;
+    }
+    if ((e = hipMemcpy(doff, hoff.data(), C * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(droff, hroff.data(), C * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess) {
+        alns_state_destroy(s);
+        return hip_error(e, "alns_state_create: hipMemcpy");
+    }
+    rc = vrprpd_eval(set, C, cinst, doff, d.S_ops, droff, d.S_rt, 0, d.z, dst, stream);
+    if (rc == VRPRPD_OK && (e = hipStreamSynchronize(st)) != hipSuccess) rc = hip_error(e, "alns_state_create: sync");
+    std::vector<int32_t> hz(C);
+    std::vector<uint32_t> hs(C);
+    if (rc == VRPRPD_OK && ((e = hipMemcpy(hz.data(), d.z, C * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+                            (e = hipMemcpy(hs.data(), dst, C * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess))
+        rc = hip_error(e, "alns_state_create: hipMemcpy");
+    if (rc != VRPRPD_OK) {
+        alns_state_destroy(s);
+        return rc;
+    }
+    std::vector<double> hT(C);
+    for (int c = 0; c < C; ++c) {
+        if (hs[c] != 0) {
+            alns_state_destroy(s);
+            return set_error(VRPRPD_EINVAL, "alns_state_create: initial solution of chain %d has status %u", c, hs[c]);
+        }
+        hT[c] = P.T0 * (double)hz[c];
+    }
+    if ((e = hipMemcpy(d.zb, d.z, C * sizeof(int32_t), hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.T, hT.data(), C * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d.T_init, hT.data(), C * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+        alns_state_destroy(s);
+        return hip_error(e, "alns_state_create: hipMemcpy");
+    }
+    // LDS sizes of the kernels (worst case over the state's instances)
+    const size_t bpo = set->dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp;
+    {
+        LdsSize g;
+        g.take<int>(N + 1);
+        g.take<uint16_t>(N + 2);
+        g.take<uint16_t>(N + 2);
+        g.take<int>(kMaxM);
+        g.take<int>(kMaxM);
+        g.take<unsigned char>(bpo * (2 * N + kAlnsStep));
+        g.take<int>((size_t)kGainGroups * (N + 1));
+        s->lds_gain = (int)g.bytes;
+        LdsSize t;
+        t.take<unsigned long long>(pow2_ge(N));
+        t.take<int>(2 * N + kAlnsStep);
+        t.take<int>(N + 1);
+        t.take<uint16_t>(N + 2);
+        t.take<uint16_t>(N + 2);
+        t.take<unsigned char>(N + 1);
+        t.take<int>(kMaxM);
+        t.take<int>(kMaxM);
+        t.take<int>(Q);
+        t.take<int>(N + 1);
+        t.take<unsigned char>(bpo * (2 * N + kAlnsStep));
+        s->lds_destroy = (int)t.bytes;
+        s->lds_enum = 2 * 8 * pow2_ge(2 * N + M + 1);
+    }
+    if ((size_t)std::max(s->lds_gain, std::max(s->lds_destroy, s->lds_enum)) > kLdsPerCu) {
+        alns_state_destroy(s);
+        return set_error(VRPRPD_EINVAL, "alns_state_create: n = %d needs too much LDS", N);
+    }
+    *out = s;
+    return VRPRPD_OK;
+}
+
+namespace vrprpd {
+
+template <typename DT, int GL>
+static int launch_gains(alns_state* s, hipStream_t st)
+{
+    constexpr int WPB = kGainWaves;
+    constexpr int per_block = 64;
+    const AlnsDev& d = s->d;
+    auto* k = k_gains<DT, GL, WPB>;
+    if (s->lds_gain > 64 * 1024)
+        VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    s->lds_gain));
+    hipLaunchKernelGGL(k, dim3(d.C, (d.N + per_block - 1) / per_block), dim3(64 * WPB), s->lds_gain, st, d,
+                       per_block);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+template <typename DT>
+static int one_iteration(alns_state* s, hipStream_t st)
+{
+    AlnsDev& d = s->d;
+    const uint32_t it = (uint32_t)s->it;
+    const int64_t trace_it = d.trace ? s->it - s->trace_base : -1;
+    hipLaunchKernelGGL(k_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, it);
+    VRP_HIP(hipGetLastError());
+    int rc;
+    if (d.M <= 16) rc = launch_gains<DT, 16>(s, st);
+    else if (d.M <= 32) rc = launch_gains<DT, 32>(s, st);
+    else rc = launch_gains<DT, 64>(s, st);
+    if (rc) return rc;
+    {
+        auto* k = k_destroy<DT>;
+        if (s->lds_destroy > 64 * 1024)
+            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_destroy));
+        hipLaunchKernelGGL(k, dim3(d.C), dim3(256), s->lds_destroy, st, d, it);
+        VRP_HIP(hipGetLastError());
+    }
+    ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
+                d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
+                d.C * d.Q};
+    for (int r = 0; r < d.Q; ++r) {
+        auto* ke = k_enum<DT>;
+        if (s->lds_enum > 64 * 1024)
+            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ke),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_enum));
+        hipLaunchKernelGGL(ke, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
+        VRP_HIP(hipGetLastError());
+        if ((rc = insert_scan_launch(sa, d.M, s->dist16, st))) return rc;
+        hipLaunchKernelGGL(k_select, dim3(d.C), dim3(256), 0, st, d);
+        VRP_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d, it, trace_it);
+    VRP_HIP(hipGetLastError());
+    s->it += 1;
+    if (d.prm.import_interval > 0 && s->it % d.prm.import_interval == 0 && s->cpi > 1) {
+        hipLaunchKernelGGL(k_import, dim3(s->n_inst), dim3(256), 0, st, d, s->cpi);
+        VRP_HIP(hipGetLastError());
+    }
+    return VRPRPD_OK;
+}
+
+}  // namespace vrprpd
+
+extern "C" int alns_step(alns_state* s, int32_t iterations, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || iterations < 0) return set_error(VRPRPD_EINVAL, "alns_step: bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < iterations; ++i) {
+        const int rc = s->dist16 ? one_iteration<uint16_t>(s, st) : one_iteration<int32_t>(s, st);
+        if (rc) return rc;
+    }
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_set_trace(alns_state* s, int64_t* trace, int64_t capacity)
+{
+    if (!s || (trace && capacity < 1)) return vrprpd::set_error(VRPRPD_EINVAL, "alns_set_trace: bad arguments");
+    s->d.trace = trace;
+    s->d.trace_cap = trace ? capacity : 0;
+    s->trace_base = s->it;
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_get_best(const alns_state* s, int32_t chain, int32_t* mk, uint16_t* ops, uint16_t* rt_end,
+                             void* stream)
+{
+    using namespace vrprpd;
+    if (!s || chain < -1 || chain >= s->d.C || !mk) return set_error(VRPRPD_EINVAL, "alns_get_best: bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    std::vector<int32_t> zb(s->d.C);
+    VRP_HIP(hipStreamSynchronize(st));
+    VRP_HIP(hipMemcpy(zb.data(), s->d.zb, s->d.C * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int c = chain;
+    if (c < 0) {
+        c = 0;
+        for (int x = 1; x < s->d.C; ++x)
+            if (zb[x] < zb[c]) c = x;
+    }
+    *mk = zb[c];
+    if (ops) VRP_HIP(hipMemcpyAsync(ops, s->d.B_ops + (size_t)c * 2 * s->d.N, 2 * s->d.N * sizeof(uint16_t),
+                                    hipMemcpyDeviceToDevice, st));
+    if (rt_end) VRP_HIP(hipMemcpyAsync(rt_end, s->d.B_rt + (size_t)c * s->d.M, s->d.M * sizeof(uint16_t),
+                                       hipMemcpyDeviceToDevice, st));
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_get_state(const alns_state* s, int64_t* iterations, int32_t* z, int32_t* zb, double* T,
+                              double* wD, double* wR)
+{
+    using namespace vrprpd;
+    if (!s) return set_error(VRPRPD_EINVAL, "alns_get_state: state is NULL");
+    VRP_HIP(hipDeviceSynchronize());
+    const int C = s->d.C;
+    if (iterations) *iterations = s->it;
+    if (z) VRP_HIP(hipMemcpy(z, s->d.z, C * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (zb) VRP_HIP(hipMemcpy(zb, s->d.zb, C * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (T) VRP_HIP(hipMemcpy(T, s->d.T, C * sizeof(double), hipMemcpyDeviceToHost));
+    if (wD) VRP_HIP(hipMemcpy(wD, s->d.wD, (size_t)kND * C * sizeof(double), hipMemcpyDeviceToHost));
+    if (wR) VRP_HIP(hipMemcpy(wR, s->d.wR, (size_t)kNR * C * sizeof(double), hipMemcpyDeviceToHost));
+    return VRPRPD_OK;
+}

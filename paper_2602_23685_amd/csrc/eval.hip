@@ -51,20 +51,20 @@ __host__ __device__ inline GroupLayout group_layout(int n_max, int bytes_per_op)
     return g;
 }
 
-// Validates one op code of the staged candidate and records it.
+// Records one op code of the staged candidate: its cover bit (a second copy
+// of an op sets `bad`) and its LDS slot.  Branch-free so that a lane's eight
+// codes issue eight LDS atomics back to back.
 template <typename DT>
-__device__ __forceinline__ void stage_code(OpStore<DT>& S, uint32_t* bits, int j, uint32_t cd, int n, bool& bad)
+__device__ __forceinline__ void stage_code(OpStore<DT>& S, uint32_t* bits, int j, uint32_t cd, int n, bool& bad,
+                                           uint32_t& old, uint32_t& mask)
 {
     const int c = (int)(cd >> 1);
-    if (c < 1 || c > n) {
-        bad = true;
-        cd = 0;
-    } else {
-        const int bitpos = 2 * c + (int)(cd & 1u);
-        const uint32_t mask = 1u << (bitpos & 31);
-        if (atomicOr(&bits[bitpos >> 5], mask) & mask) bad = true;   // second copy of an op
-    }
-    S.set_code(j, cd);
+    const bool ok = c >= 1 && c <= n;
+    bad = bad || !ok;
+    const int bitpos = ok ? 2 * c + (int)(cd & 1u) : 0;
+    mask = ok ? 1u << (bitpos & 31) : 0u;
+    old = atomicOr(&bits[bitpos >> 5], mask);
+    S.set_code(j, ok ? cd : 0u);
 }
 
 template <typename DT, int GL, int WPB>
@@ -114,23 +114,57 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     if (!gbad) {
         int head = (int)((8 - (((uintptr_t)ops >> 1) & 7)) & 7);
         head = head < total ? head : total;
-        for (int j = li; j < head; j += GL) stage_code(S, bits, j, ops[j], n, cbad);
+        for (int j = li; j < head; j += GL) {
+            uint32_t old, mask;
+            stage_code(S, bits, j, ops[j], n, cbad, old, mask);
+            cbad = cbad || (old & mask);
+        }
         const int nvec = (total - head) >> 3;
         const uint4* vec = reinterpret_cast<const uint4*>(ops + head);
-#pragma unroll 2
-        for (int q = li; q < nvec; q += GL) {
-            const uint4 x = vec[q];
-            const int j = head + 8 * q;
-            stage_code(S, bits, j + 0, x.x & 0xFFFFu, n, cbad);
-            stage_code(S, bits, j + 1, x.x >> 16, n, cbad);
-            stage_code(S, bits, j + 2, x.y & 0xFFFFu, n, cbad);
-            stage_code(S, bits, j + 3, x.y >> 16, n, cbad);
-            stage_code(S, bits, j + 4, x.z & 0xFFFFu, n, cbad);
-            stage_code(S, bits, j + 5, x.z >> 16, n, cbad);
-            stage_code(S, bits, j + 6, x.w & 0xFFFFu, n, cbad);
-            stage_code(S, bits, j + 7, x.w >> 16, n, cbad);
+        constexpr int V = 4;   // 16-byte loads in flight per lane
+        for (int q0 = li; q0 < nvec; q0 += V * GL) {
+            uint4 x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int q = q0 + v * GL;
+                x[v] = q < nvec ? vec[q] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int q = q0 + v * GL;
+                if (q < nvec) {
+                    const int j = head + 8 * q;
+                    const uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
+                    uint32_t old[8], mask[8];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        stage_code(S, bits, j + 2 * h, w4[h] & 0xFFFFu, n, cbad, old[2 * h], mask[2 * h]);
+                        stage_code(S, bits, j + 2 * h + 1, w4[h] >> 16, n, cbad, old[2 * h + 1], mask[2 * h + 1]);
+                    }
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) cbad = cbad || (old[h] & mask[h]);
+                }
+            }
         }
-        for (int j = head + 8 * nvec + li; j < total; j += GL) stage_code(S, bits, j, ops[j], n, cbad);
+        for (int j = head + 8 * nvec + li; j < total; j += GL) {
+            uint32_t old, mask;
+            stage_code(S, bits, j, ops[j], n, cbad, old, mask);
+            cbad = cbad || (old & mask);
+        }
+        // ready[c] = ~p_c ("not dropped yet"; the drop reads p_c back from it)
+        for (int c0 = li; c0 <= n; c0 += 4 * GL) {
+            int pv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = c0 + v * GL;
+                pv[v] = c <= n ? P[c] : 0;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = c0 + v * GL;
+                if (c <= n) ready[c] = ~pv[v];
+            }
+        }
     }
     wave_lds_fence();
     if (!gbad) {
@@ -141,37 +175,29 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     }
     gbad = gbad || group_ballot<GL>(cbad) != 0;
 
-    // ---- phase 1b: every travel time d[prev][c] and every drop's p_c, -------
-    // gathered in batches so that many loads are in flight per lane.  Legs
-    // first assume the previous op of the flat list is the previous stop; the
-    // first op of each route is then re-pointed at the depot.  ready[c] starts
-    // as ~p_c: "not dropped yet", and the drop reads p_c back from it.
+    // ---- phase 1b: every travel time d[prev][c], gathered in batches so ---
+    // that many loads are in flight per lane.  Legs first assume the previous
+    // op of the flat list is the previous stop; the first op of each route is
+    // then re-pointed at the depot.
     if (!gbad) {
-        constexpr int U = 8;
+        constexpr int U = 16;
         for (int j0 = li; j0 < total; j0 += U * GL) {
-            int idx[U], cc[U];
+            int idx[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * GL;
                 const int jj = j < total ? j : 0;
-                const uint32_t cd = S.code(jj);
-                cc[u] = (cd & 1u) ? 0 : (int)(cd >> 1);
+                const int c = (int)(S.code(jj) >> 1);
                 const int pc = jj > 0 ? (int)(S.code(jj - 1) >> 1) : 0;
-                idx[u] = pc * N1 + (int)(cd >> 1);
+                idx[u] = pc * N1 + c;
             }
-            int lg[U], pv[U];
+            int lg[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                lg[u] = (int)D[idx[u]];
-                pv[u] = P[cc[u]];
-            }
+            for (int u = 0; u < U; ++u) lg[u] = (int)D[idx[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * GL;
-                if (j < total) {
-                    S.set_leg(j, lg[u]);
-                    if (cc[u]) ready[cc[u]] = ~pv[u];
-                }
+                if (j < total) S.set_leg(j, lg[u]);
             }
         }
         wave_lds_fence();

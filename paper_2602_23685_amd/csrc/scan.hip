@@ -14,26 +14,11 @@
 // deadlock, every entry) is reset explicitly.
 #include "common.h"
 #include "sweep.h"
+#include "scan.h"
 
 namespace vrprpd {
 
-struct ScanArgs {
-    const InstDev* inst_tab;
-    const void* dist;
-    const int32_t* proc;
-    const int32_t* base_inst;
-    const int64_t* base_op_off;
-    const uint16_t* base_ops;
-    const int64_t* base_rt_off;
-    const uint16_t* base_rt_end;
-    const int64_t* seg_off;
-    const int32_t* seg_base;
-    const vrprpd_tuple* tuples;
-    int32_t* mk_out;
-    uint32_t* st_out;
-    int64_t* seg_top3;
-    int32_t num_bases, num_inst, n_max, num_seg;
-};
+
 
 constexpr int kScanStep = 4;
 
@@ -57,104 +42,6 @@ __host__ __device__ inline ScanLayout scan_layout(int n_max, int bytes_per_op)
     L.ready_bytes = a16(4 * (n_max + 1));
     L.bytes = L.ready_off + L.ready_bytes * WPB * G;
     return L;
-}
-
-// A route of the base with up to two ops spliced in at virtual positions
-// x1 < x2 (kNoPos when absent).  lgX is the leg into the spliced op, laX the
-// leg into the base op right after it.
-constexpr int kNoPos = 1 << 30;  // far past any route, and x + 1 cannot overflow
-
-struct VRoute {
-    int bs, len, vlen;
-    int x1, x2;
-    uint32_t k1, k2;
-    int lg1, lg2, la1, la2;
-    int ret;  // leg from the last stop back to the depot
-};
-
-template <typename DT>
-__device__ __forceinline__ void vfetch(const OpStore<DT>& S, const VRoute& R, int i, uint32_t& cd, int& leg)
-{
-    if (i == R.x1) {
-        cd = R.k1;
-        leg = R.lg1;
-    } else if (i == R.x2) {
-        cd = R.k2;
-        leg = R.lg2;
-    } else {
-        const int j = R.bs + i - (i > R.x1) - (i > R.x2);
-        S.load(j, cd, leg);
-        if (i == R.x1 + 1) leg = R.la1;
-        else if (i == R.x2 + 1) leg = R.la2;
-    }
-}
-
-template <typename DT, int GL>
-__device__ __forceinline__ SweepOut sweep_virtual(const OpStore<DT>& S, const VRoute& R, int* ready,
-                                                  const int* pblk, int pol)
-{
-    SweepOut o{0, 0, 0, 0, false};
-    int ptr = 0;
-    const int e = R.vlen;
-    for (;;) {
-        int took = 0;
-        if (ptr < e) {
-            uint32_t cd[kScanStep];
-            int leg[kScanStep], r[kScanStep];
-#pragma unroll
-            for (int u = 0; u < kScanStep; ++u) {
-                cd[u] = 0;
-                leg[u] = 0;
-                if (ptr + u < e) vfetch(S, R, ptr + u, cd[u], leg[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < kScanStep; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);
-            bool go = true;
-#pragma unroll
-            for (int u = 0; u < kScanStep; ++u) {
-                go = go && (ptr + u < e);
-                if (go) {
-                    const int c = (int)(cd[u] >> 1);
-                    const int arr = o.t + leg[u];
-                    if (!(cd[u] & 1u)) {
-                        o.t = arr;
-                        const int rv = arr + pblk[c];
-                        lds_store(&ready[c], pol ? ~rv : rv);
-                        o.w += 1;
-                    } else {
-                        const bool ok = pol ? (r[u] < 0) : (r[u] >= 0);
-                        if (ok) {
-                            const int rv = pol ? ~r[u] : r[u];
-                            o.t = arr > rv ? arr : rv;
-                            o.w -= 1;
-                        } else {
-                            go = false;
-                        }
-                    }
-                    if (go) {
-                        ++took;
-                        o.wmax = o.w > o.wmax ? o.w : o.wmax;
-                        o.wmin = o.w < o.wmin ? o.w : o.wmin;
-                    }
-                }
-            }
-            ptr += took;
-        }
-        if (!group_ballot<GL>(ptr < e)) break;
-        if (!group_ballot<GL>(took > 0)) {
-            o.dead = true;
-            break;
-        }
-    }
-    for (; ptr < e; ++ptr) {
-        uint32_t cd;
-        int leg;
-        vfetch(S, R, ptr, cd, leg);
-        o.w += (cd & 1u) ? -1 : 1;
-        o.wmax = o.w > o.wmax ? o.w : o.wmax;
-        o.wmin = o.w < o.wmin ? o.w : o.wmin;
-    }
-    return o;
 }
 
 __device__ __forceinline__ void top3_insert(long long* t, long long key)
@@ -189,7 +76,12 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
     // range, [2] base route-end table invalid
     __shared__ int flags[3];
 
-    const int64_t t0 = a.seg_off[seg], t1 = a.seg_off[seg + 1];
+    const int64_t t0 = a.seg_off[seg];
+    const int64_t t1 = a.seg_cnt ? t0 + a.seg_cnt[seg] : a.seg_off[seg + 1];
+    if (t1 <= t0) {                      // empty segment: nothing to stage
+        if (threadIdx.x < 3) a.seg_top3[3 * seg + threadIdx.x] = INT64_MAX;
+        return;
+    }
     int bi = a.seg_base ? a.seg_base[seg] : 0;
     const bool bad_base_idx = bi < 0 || bi >= a.num_bases;
     if (bad_base_idx) bi = 0;
@@ -290,7 +182,8 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
         } else if (base_bad) {
             st = VRPRPD_ST_BAD_COVER;
         } else {
-            VRoute R;
+            InsRoute<DT> R;
+            R.S = &S;
             R.bs = my_s;
             R.len = my_len;
             R.x1 = R.x2 = kNoPos;
@@ -326,7 +219,7 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
             R.vlen = my_len + (R.x1 != kNoPos) + (R.x2 != kNoPos);
             if (li == 0) ready[c] = pol ? 0 : -1;
             wave_lds_fence();
-            const SweepOut o = sweep_virtual<DT, GL>(S, R, ready, pblk, pol);
+            const SweepOut o = sweep_route<kScanStep, GL>(R, ready, pblk, pol);
             st = load_status<GL>(o, veh, m, I.k, I.R, I.load_model);
             const int ret = (veh && R.vlen > 0) ? o.t + R.ret : 0;
             const int z = group_max<GL>(ret);
@@ -364,7 +257,7 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
 }
 
 template <typename DT, int GL>
-static int launch_scan(const ScanArgs& a, hipStream_t stream)
+int launch_scan(const ScanArgs& a, hipStream_t stream)
 {
     constexpr int WPB = 4;
     const ScanLayout L = scan_layout<WPB, GL>(a.n_max, OpStore<DT>::kBytesPerOp);
@@ -385,6 +278,11 @@ static int scan_gl(const ScanArgs& a, int m_max, hipStream_t st)
     if (m_max <= 16) return launch_scan<DT, 16>(a, st);
     if (m_max <= 32) return launch_scan<DT, 32>(a, st);
     return launch_scan<DT, 64>(a, st);
+}
+
+int insert_scan_launch(const ScanArgs& a, int m_max, int dist16, hipStream_t st)
+{
+    return dist16 ? scan_gl<uint16_t>(a, m_max, st) : scan_gl<int32_t>(a, m_max, st);
 }
 
 }  // namespace vrprpd
@@ -409,7 +307,7 @@ extern "C" int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, cons
     const int n_lds = base_inst ? set->n_max : set->host[0].n;
     const int m_max = base_inst ? set->m_max : set->host[0].m;
     ScanArgs a{set->d_inst, set->d_dist, set->d_proc, base_inst, base_op_off, base_ops, base_rt_off, base_rt_end,
-               seg_off, seg_base, tuples, mk_out, st_out, seg_top3, num_bases, set->num_inst, n_lds, num_seg};
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return set->dist16 ? scan_gl<uint16_t>(a, m_max, st) : scan_gl<int32_t>(a, m_max, st);
+               seg_off, seg_base, tuples, mk_out, st_out, seg_top3, nullptr, num_bases, set->num_inst, n_lds,
+               num_seg};
+    return insert_scan_launch(a, m_max, set->dist16, reinterpret_cast<hipStream_t>(stream));
 }

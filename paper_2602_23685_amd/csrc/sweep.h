@@ -67,6 +67,54 @@ struct SweepOut {
     bool dead;          // group deadlocked
 };
 
+// One lane's attempt at its next K ops (branch-free except the drop's
+// store).  cd/leg: the ops; r: ready[] entries read at the start of the step;
+// n_left: ops left on the route.  Returns the number of ops taken.
+// pol selects the sign convention of ready[] (see sweep_route); the explicit
+// evaluation uses pol = 0 with ready[c] = ~p_c before the drop, so the drop's
+// ready time is arr + p_c with p_c = ~r.
+template <int K, bool kPolarity>
+__device__ __forceinline__ int sweep_step(SweepOut& o, const uint32_t* cd, const int* leg, const int* r,
+                                          int n_left, int* ready, const int* pblk, int pol)
+{
+    bool go = true;
+    int took = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const bool isP = cd[u] & 1u;
+        const int c = (int)(cd[u] >> 1);
+        const int arr = o.t + leg[u];
+        bool rdy;
+        int rv;
+        if constexpr (kPolarity) {
+            rdy = pol ? (r[u] < 0) : (r[u] >= 0);
+            rv = pol ? ~r[u] : r[u];
+        } else {
+            rdy = r[u] >= 0;
+            rv = r[u];
+        }
+        const bool ok = go && (u < n_left) && (!isP || rdy);
+        const int tn = isP ? (arr > rv ? arr : rv) : arr;
+        if (ok && !isP) {
+            int val;
+            if constexpr (kPolarity) {
+                const int x = arr + pblk[c];
+                val = pol ? ~x : x;
+            } else {
+                val = arr + ~r[u];
+            }
+            lds_store(&ready[c], val);
+        }
+        o.t = ok ? tn : o.t;
+        o.w += ok ? (isP ? -1 : 1) : 0;
+        o.wmax = o.w > o.wmax ? o.w : o.wmax;
+        o.wmin = o.w < o.wmin ? o.w : o.wmin;
+        took += ok ? 1 : 0;
+        go = ok;
+    }
+    return took;
+}
+
 template <int GL, int K, typename DT>
 __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready, int s, int e)
 {
@@ -80,34 +128,8 @@ __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready
 #pragma unroll
             for (int u = 0; u < K; ++u) S.load(ptr + u, cd[u], leg[u]);
 #pragma unroll
-            for (int u = 0; u < K; ++u) {
-                const int c = (ptr + u < e) ? (int)(cd[u] >> 1) : 0;
-                r[u] = lds_load(&ready[c]);
-            }
-            bool go = true;
-#pragma unroll
-            for (int u = 0; u < K; ++u) {
-                go = go && (ptr + u < e);
-                if (go) {
-                    const int c = (int)(cd[u] >> 1);
-                    const int arr = o.t + leg[u];
-                    if (!(cd[u] & 1u)) {
-                        o.t = arr;
-                        lds_store(&ready[c], arr + ~r[u]);  // ~r = p_c before the drop
-                        o.w += 1;
-                    } else if (r[u] >= 0) {
-                        o.t = arr > r[u] ? arr : r[u];
-                        o.w -= 1;
-                    } else {
-                        go = false;
-                    }
-                    if (go) {
-                        ++took;
-                        o.wmax = o.w > o.wmax ? o.w : o.wmax;
-                        o.wmin = o.w < o.wmin ? o.w : o.wmin;
-                    }
-                }
-            }
+            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[(ptr + u < e) ? (int)(cd[u] >> 1) : 0]);
+            took = sweep_step<K, false>(o, cd, leg, r, e - ptr, ready, nullptr, 0);
             ptr += took;
         }
         const uint64_t left = group_ballot<GL>(ptr < e);
@@ -126,6 +148,126 @@ __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready
     }
     return o;
 }
+
+
+// ---------------------------------------------------------------------------
+// Sweep over "virtual" routes: a staged base solution seen through a Route
+// object that splices ops in or out (Route::vlen, Route::fetch(i, code, leg)).
+// ready[] keeps no per-evaluation initialisation: its sign convention flips
+// with `pol` after every completed evaluation (see the insertion scan).
+// pblk[c] = p_c for the drop's ready time.  Route::record(i, t) may keep the
+// time of each op taken.
+template <int K, int GL, typename Route>
+__device__ __forceinline__ SweepOut sweep_route(const Route& R, int* ready, const int* pblk, int pol)
+{
+    SweepOut o{0, 0, 0, 0, false};
+    int ptr = 0;
+    const int e = R.vlen;
+    for (;;) {
+        int took = 0;
+        if (ptr < e) {
+            uint32_t cd[K];
+            int leg[K], r[K];
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                cd[u] = 0;
+                leg[u] = 0;
+                if (ptr + u < e) R.fetch(ptr + u, cd[u], leg[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);
+            const int t_before = o.t;
+            (void)t_before;
+            if constexpr (Route::kRecords) {
+                // record needs each op's own time: take the ops one by one
+                SweepOut o2 = o;
+                took = sweep_step<K, true>(o2, cd, leg, r, e - ptr, ready, pblk, pol);
+                int t = o.t;
+                for (int u = 0; u < took; ++u) {
+                    const int arr = t + leg[u];
+                    const int rv = pol ? ~r[u] : r[u];
+                    t = (cd[u] & 1u) ? (arr > rv ? arr : rv) : arr;
+                    R.record(ptr + u, t);
+                }
+                o = o2;
+            } else {
+                took = sweep_step<K, true>(o, cd, leg, r, e - ptr, ready, pblk, pol);
+            }
+            ptr += took;
+        }
+        if (!group_ballot<GL>(ptr < e)) break;
+        if (!group_ballot<GL>(took > 0)) {
+            o.dead = true;
+            break;
+        }
+    }
+    for (; ptr < e; ++ptr) {
+        uint32_t cd;
+        int leg;
+        R.fetch(ptr, cd, leg);
+        o.w += (cd & 1u) ? -1 : 1;
+        o.wmax = o.w > o.wmax ? o.w : o.wmax;
+        o.wmin = o.w < o.wmin ? o.w : o.wmin;
+    }
+    return o;
+}
+
+constexpr int kNoPos = 1 << 30;  // far past any route, and x + 1 cannot overflow
+
+// A base route with up to two ops spliced in at virtual positions x1 < x2
+// (kNoPos when absent).  lgX is the leg into the spliced op, laX the leg into
+// the base op right after it; ret is the leg from the last stop to the depot.
+template <typename DT>
+struct InsRoute {
+    static constexpr bool kRecords = false;
+    const OpStore<DT>* S;
+    int bs, len, vlen;
+    int x1, x2;
+    uint32_t k1, k2;
+    int lg1, lg2, la1, la2;
+    int ret;
+    __device__ __forceinline__ void fetch(int i, uint32_t& cd, int& leg) const
+    {
+        if (i == x1) {
+            cd = k1;
+            leg = lg1;
+        } else if (i == x2) {
+            cd = k2;
+            leg = lg2;
+        } else {
+            const int j = bs + i - (i > x1) - (i > x2);
+            S->load(j, cd, leg);
+            if (i == x1 + 1) leg = la1;
+            else if (i == x2 + 1) leg = la2;
+        }
+    }
+    __device__ __forceinline__ void record(int, int) const {}
+};
+
+// A base route with up to two ops taken out (base positions y1 < y2 relative
+// to the route start, kNoPos when absent).  lb1 / lb2 are the legs into the
+// first kept op after y1 / after y2; times, when set, receive the time of
+// each kept op at its base index.
+template <typename DT, bool kRec>
+struct DelRouteT {
+    static constexpr bool kRecords = kRec;
+    const OpStore<DT>* S;
+    int bs, vlen;
+    int y1, y2;      // virtual index of the first kept op after each removal
+    int lb1, lb2;
+    int* times;
+    __device__ __forceinline__ int base_index(int i) const { return bs + i + (i >= y1) + (i >= y2); }
+    __device__ __forceinline__ void fetch(int i, uint32_t& cd, int& leg) const
+    {
+        S->load(base_index(i), cd, leg);
+        if (i == y2) leg = lb2;
+        else if (i == y1) leg = lb1;
+    }
+    __device__ __forceinline__ void record(int i, int t) const
+    {
+        if (times) times[base_index(i)] = t;
+    }
+};
 
 // Load and resource status of a group (Eq. 13-18 under the load model).
 template <int GL>

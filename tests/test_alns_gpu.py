@@ -1,0 +1,81 @@
+"""Parity: alns_step on the GPU reproduces the oracle's ALNS trajectories.
+
+Every iteration's candidate makespan, current and best makespan, operator
+choice, outcome and removal size must match, and so must the final
+temperatures and operator weights (fp64, bit for bit) and best solutions."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_23685_amd as P
+    P.load()
+    return P
+
+
+ALNS_CASES = [
+    # n, m, k, R, rule, load_model, chains, iters, budget, import_interval
+    (16, 2, 2, 4, "base", 0, 4, 60, 0, 20),        # full enumeration (small case)
+    (40, 4, 5, 20, "5x", 0, 3, 30, 400, 10),
+    (100, 4, 5, 20, "2x", 0, 2, 12, 2000, 0),
+    (30, 3, 3, 9, "1R20", 1, 2, 25, 300, 0),
+    (20, 17, 2, 40, "1R10", 0, 2, 12, 500, 0),     # 32-lane groups
+]
+
+
+@pytest.mark.parametrize("case", ALNS_CASES, ids=lambda c: f"n{c[0]}m{c[1]}b{c[8]}")
+def test_alns_trajectory_parity(orc, P, case):
+    n, m, k, R, rule, lm, chains, iters, budget, imp = case
+    inst = synth.make_instance(n, m, k, R, rule, seed=9000 + n, load_model=lm)
+    ops, rt = synth.round_robin_solution(inst, vehicles=min(m, R))
+    assert orc.eval_one(inst, ops, rt)[1] == 0
+    seed = 1234 + n
+    ref = orc.alns_run(inst, orc.alns_params(tuple_budget=budget, import_interval=imp), chains, iters, seed,
+                       ops, rt, trace=True)
+    S = P.InstanceSet([inst])
+    st = P.AlnsState(S, [0], chains, P.alns_params(tuple_budget=budget, import_interval=imp), seed,
+                     torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+    tr = st.set_trace(iters)
+    st.step(iters)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    exp = ref["trace"]
+    for ch in range(chains):
+        for it in range(iters):
+            assert np.array_equal(got[ch, it], exp[ch, it]), (ch, it, got[ch, it], exp[ch, it])
+    info = st.state()
+    assert info["iterations"] == iters
+    assert np.array_equal(info["zb"], ref["best_mk"])
+    for ch in range(chains):
+        mk, bops, brt = st.best(ch)
+        assert mk == ref["best_mk"][ch]
+        b_rt = brt.cpu().numpy()[:m]
+        assert np.array_equal(b_rt, ref["best_rt"][ch])
+        assert np.array_equal(bops.cpu().numpy()[:2 * n], ref["best_ops"][ch])
+        assert orc.eval_one(inst, bops.cpu().numpy()[:2 * n], b_rt) == (mk, 0)
+
+
+def test_alns_continues_across_calls(orc, P):
+    """Two calls of alns_step(k) equal one call of alns_step(2k)."""
+    inst = synth.make_instance(16, 2, 2, 4, "2x", seed=77)
+    ops, rt = synth.round_robin_solution(inst)
+    prm = P.alns_params(import_interval=7)
+    S = P.InstanceSet([inst])
+    a = P.AlnsState(S, [0], 3, prm, 5, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+    b = P.AlnsState(S, [0], 3, prm, 5, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+    a.step(10)
+    a.step(10)
+    b.step(20)
+    sa, sb = a.state(), b.state()
+    for key in ("z", "zb", "T", "wD", "wR"):
+        assert np.array_equal(sa[key], sb[key]), key
+    ref = orc.alns_run(inst, orc.alns_params(import_interval=7), 3, 20, 5, ops, rt)
+    assert np.array_equal(sa["zb"], ref["best_mk"])
