@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
-"""Throughput of exact VRP-RPD makespan evaluation on one MI355X.
+"""Exact VRP-RPD makespan evaluation on one MI355X: throughput of the whole
+hot path at n = 1000.
 
 Workload (the full-scale configuration): one instance with n = 1000 customers,
 m = 10 vehicles, capacity k = 10, R = 100 resources, processing times
 U_int[1,20] * floor(mean depot distance / 10); synthetic TSPLIB-shaped points
-(integer, uniform in [0,1000]^2, EUC_2D rounding).  A step evaluates a batch of
-65,536 explicit candidate solutions (random drop-before-pickup linear
-extensions spread over the vehicles, then renamed customers so that all
-65,536 are distinct), all resident in HBM before the timed region.
+(integer, uniform in [0,1000]^2, EUC_2D rounding).  One step runs every stage
+of the path once on inputs already resident in HBM:
+  1. vrprpd_eval         65,536 explicit candidate solutions
+  2. vrprpd_insert_scan  16,384 insertion tuples (one ALNS iteration's budget)
+                         for 37 removed customers of a destroyed solution
+  3. brkga_decode_eval   a population of 4,096 chromosomes (2n keys + 2n hints)
+     brkga_evolve        one generation (614 elites, 614 mutants, rho_e = 0.7)
+  4. alns_step           one ALNS iteration of 32 chains (budget 16,384 tuples)
+`value` counts every exact schedule evaluation of the step (explicit
+candidates, tuples, decoded chromosomes and the ALNS iteration's tuples and
+removal gains) per second of step wall time.
 
-Prints one JSON line.  The CPU baseline is the oracle (single-threaded C)
-timed on a bounded sample of the same candidates.
+Also reported: the wall time for GPU ALNS to reach the best makespan the CPU
+oracle's ALNS finds in 2000 iterations on the depot + 16 customer instance,
+and the CPU baseline (the oracle, single-threaded, on a bounded sample).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -33,12 +43,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(B, seed=3003):
+def make_workload(seed=3003, B=65536, T=16384, Np=4096):
     import synth
     inst = synth.make_instance(1000, 10, 10, 100, "1R20d10", seed=seed)
     pool_ops, pool_rt = synth.random_candidates(inst, 1024, seed=seed + 1)
     ops, rt = synth.relabel_candidates(pool_ops, pool_rt, inst.n, B, seed=seed + 2)
-    return inst, ops, rt
+    # a destroyed solution: 37 customers removed from a feasible candidate
+    g = synth.rng(seed + 3)
+    removed = sorted(int(c) for c in g.choice(np.arange(1, inst.n + 1), size=37, replace=False))
+    gone = set(removed)
+    base_routes = [[x for x in r if x[0] not in gone] for r in synth.unpack_candidate(pool_ops[0], pool_rt[0])]
+    bops, _, brt = synth.pack_candidates([base_routes], inst.m)
+    tuples = synth.random_tuples(bops, brt[0], inst.n, inst.m, T, seed=seed + 4, absent=removed)
+    order = np.argsort(tuples["c"], kind="stable")
+    tuples = tuples[order]
+    cs = tuples["c"].astype(np.int64)
+    seg_off = np.concatenate([[0], np.nonzero(np.diff(cs))[0] + 1, [T]]).astype(np.int64)
+    prio, hint = synth.random_keys(Np, inst.n, seed=seed + 5)
+    return dict(inst=inst, ops=ops, rt=rt, bops=bops, brt=brt[0], tuples=tuples, seg_off=seg_off,
+                prio=prio, hint=hint, pool_ops=pool_ops, pool_rt=pool_rt)
 
 
 def cpu_baseline(inst, ops, rt, seconds):
@@ -52,21 +75,53 @@ def cpu_baseline(inst, ops, rt, seconds):
         i += chunk
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of the {len(ops)} candidates, single-threaded C oracle, {dt:.1f} s"}
+            "sample": f"first {done} of the 65,536 explicit candidates at n=1000, "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
+
+def time_to_oracle_best(P, torch, iters_oracle=2000, chains=32, budget_iters=4000):
+    """Small-instance race: the oracle's ALNS (one chain, 2000 iterations,
+    every slot pair priced) sets the target; GPU ALNS with 32 chains runs
+    until its best reaches it."""
+    import oracle
+    import synth
+    inst = synth.make_instance(16, 2, 2, 4, "base", seed=1001)
+    ops, rt = synth.round_robin_solution(inst)
+    t0 = time.perf_counter()
+    ref = oracle.alns_run(inst, oracle.alns_params(), 1, iters_oracle, 2024, ops, rt)
+    t_oracle = time.perf_counter() - t0
+    z_target = int(ref["best_mk"][0])
+    S = P.InstanceSet([inst])
+    st = P.AlnsState(S, [0], chains, P.alns_params(), 99, torch.from_numpy(ops).cuda(),
+                     torch.from_numpy(rt).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, best, chunk = 0, None, 25
+    while done < budget_iters:
+        st.step(chunk)
+        done += chunk
+        best = int(st.state()["zb"].min())
+        if best <= z_target:
+            break
+    t_gpu = time.perf_counter() - t0
+    return {"config": "n=16 customers, m=2, k=2, R=4, base rule", "z_oracle": z_target,
+            "oracle_seconds": t_oracle, "oracle_iterations": iters_oracle, "oracle_chains": 1,
+            "gpu_seconds": t_gpu, "gpu_iterations": done, "gpu_chains": chains, "gpu_best": best,
+            "reached": bool(best is not None and best <= z_target)}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-race", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -76,39 +131,75 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P.load()
-    B, K, W = args.batch, args.steps, args.warmup
-    log(f"generating workload B={B}")
-    inst, ops, rt = make_workload(B)
+    K, W = args.steps, args.warmup
+    log("generating workload")
+    w = make_workload()
+    inst = w["inst"]
     S = P.InstanceSet([inst])
-    d_ops = torch.from_numpy(ops).cuda()
-    d_rt = torch.from_numpy(rt).cuda()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d_ops, d_rt = dev(w["ops"]), dev(w["rt"])
+    B = d_rt.shape[0]
     mk = torch.empty(B, dtype=torch.int32, device="cuda")
     st = torch.empty(B, dtype=torch.int32, device="cuda")
+    d_bops, d_brt, d_seg = dev(w["bops"]), dev(w["brt"]), dev(w["seg_off"])
+    d_tup = dev(w["tuples"].view(np.uint8))
+    T = len(w["tuples"])
+    d_prio, d_hint = dev(w["prio"]), dev(w["hint"])
+    Np = d_prio.shape[0]
+    ne, nm = int(0.15 * Np), int(0.15 * Np)
+    dec_out = P.brkga_decode_eval(S, d_prio, d_hint)
+    p_next, h_next = torch.empty_like(d_prio), torch.empty_like(d_hint)
+    rank = torch.empty(Np, dtype=torch.int32, device="cuda")
+    chains = 32
+    init_ops = dev(w["pool_ops"][0])
+    init_rt = dev(w["pool_rt"][0])
+    alns = P.AlnsState(S, [0], chains, P.alns_params(tuple_budget=16384), 7, init_ops, init_rt)
     stream = torch.cuda.current_stream()
+    names = ["vrprpd_eval", "vrprpd_insert_scan", "brkga_decode_eval+evolve", "alns_step"]
+    ev = {nm_: [] for nm_ in names}
 
-    def step():
+    def step(gen, record):
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record:
+            marks[0].record(stream)
         P.vrprpd_eval(S, d_ops, d_rt, makespan=mk, status=st, stream=stream)
+        if record:
+            marks[1].record(stream)
+        P.vrprpd_insert_scan(S, d_bops, d_brt, d_seg, d_tup, stream=stream)
+        if record:
+            marks[2].record(stream)
+        P.brkga_decode_eval(S, d_prio, d_hint, out=dec_out, stream=stream)
+        P.brkga_evolve(d_prio, d_hint, dec_out["fitness"], ne, nm, 0.7, 11, gen, prio_out=p_next,
+                       hint_out=h_next, rank_out=rank, stream=stream)
+        if record:
+            marks[3].record(stream)
+        alns.step(1, stream=stream)
+        if record:
+            marks[4].record(stream)
+            for i, nm_ in enumerate(names):
+                ev[nm_].append((marks[i], marks[i + 1]))
 
     log(f"warmup {W}")
-    for _ in range(W):
-        step()
+    for i in range(W):
+        step(i, False)
     torch.cuda.synchronize()
-    feasible = float((st == 0).float().mean().item())
-
+    ev0 = alns.state()
     log(f"timing {K} steps")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        ev[i][0].record(stream)
-        step()
-        ev[i][1].record(stream)
+        step(W + i, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    value = B * K / wall
+    ev1 = alns.state()
+    comp_ms = {nm_: float(np.mean([a.elapsed_time(b) for a, b in ev[nm_]])) for nm_ in names}
+    alns_evals = (ev1["evals"] - ev0["evals"]) / K
+    evals_per_step = B + T + Np + alns_evals
+    value = evals_per_step * K / wall
     bytes_per_eval = 2 * 2 * inst.n + 2 * inst.m + 4 + 4
-    achieved = bytes_per_eval * B / (kern_ms * 1e-3)
+    eval_ms = comp_ms["vrprpd_eval"]
+    achieved = bytes_per_eval * B / (eval_ms * 1e-3)
+    feasible = float((st == 0).float().mean().item())
 
     out = {
         "metric": METRIC,
@@ -124,21 +215,33 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "vrprpd_eval, n=1000 customers, m=10 vehicles, k=10, R=100, "
-                        "p=U_int[1,20]*floor(dbar/10), 65,536 explicit candidates per step",
-            "n": inst.n, "m": inst.m, "k": inst.k, "R": inst.R, "batch": B,
-            "feasible_fraction": feasible,
+            "workload": "n=1000 customers, m=10 vehicles, k=10, R=100, p=U_int[1,20]*floor(dbar/10); "
+                        "per step: 65,536 explicit candidates, 16,384 insertion tuples, BRKGA 4,096 "
+                        "decode+evolve, one ALNS iteration of 32 chains (16,384-tuple budget)",
+            "n": inst.n, "m": inst.m, "k": inst.k, "R": inst.R,
+            "explicit_candidates": B, "tuples": T, "population": Np, "alns_chains": chains,
+            "evals_per_step": evals_per_step, "feasible_fraction": feasible,
+        },
+        "components_ms": comp_ms,
+        "component_evals_per_s": {
+            "vrprpd_eval": B / (comp_ms["vrprpd_eval"] * 1e-3),
+            "vrprpd_insert_scan": T / (comp_ms["vrprpd_insert_scan"] * 1e-3),
+            "brkga_decode_eval+evolve": Np / (comp_ms["brkga_decode_eval+evolve"] * 1e-3),
+            "alns_step": alns_evals / (comp_ms["alns_step"] * 1e-3),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": None,
-            "kernel": "eval_kernel", "kernel_ms": kern_ms,
-            "bytes_per_eval": bytes_per_eval,
+            "kernel": "eval_kernel", "kernel_ms": eval_ms, "bytes_per_unit": bytes_per_eval,
+            "units_per_launch": B,
         },
     }
+    if not args.no_race:
+        log("time to oracle-best (n=16)")
+        out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(inst, ops, rt, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -170,6 +170,9 @@ typedef struct {
  *   mk_out        [seg_off[S]] int32 makespans, or NULL
  *   st_out        [seg_off[S]] uint32 status bits, or NULL
  *   seg_top3      [S][3] int64 out, ascending; INT64_MAX where fewer than 3 feasible tuples
+ *   blocks_per_seg  (host) workgroups sharing each segment's tuples, 0 or 1
+ *                 for one; more spreads long segments over the GPU (each
+ *                 workgroup stages the base once)
  * Errors: EINVAL, EHIP.  seg_base / base_inst values out of range make the
  * segment's tuples BAD_TUPLE.
  */
@@ -177,7 +180,7 @@ int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, const int32_t* 
                        const int64_t* base_op_off, const uint16_t* base_ops, const int64_t* base_rt_off,
                        const uint16_t* base_rt_end, int32_t num_seg, const int64_t* seg_off,
                        const int32_t* seg_base, const vrprpd_tuple* tuples, int32_t* mk_out,
-                       uint32_t* st_out, int64_t* seg_top3, void* stream);
+                       uint32_t* st_out, int64_t* seg_top3, int32_t blocks_per_seg, void* stream);
 
 /*
  * brkga_decode_eval — multi-pass decoder (Section 4.4.2, Algorithm 2) and the
@@ -311,11 +314,12 @@ int alns_set_trace(alns_state* st, int64_t* trace, int64_t capacity);
  * solution (device out, 2 n_max ops and m_max route ends) of one chain, or of
  * the best chain when chain = -1.  Synchronises the stream. */
 int alns_get_best(const alns_state* st, int32_t chain, int32_t* mk, uint16_t* ops, uint16_t* rt_end, void* stream);
-/* Host copies of the iteration count and every chain's current and best
- * makespan, temperature and operator weights ([chains][6], [chains][4]); any
- * pointer may be NULL.  Synchronises the device. */
-int alns_get_state(const alns_state* st, int64_t* iterations, int32_t* z, int32_t* zb, double* T, double* wD,
-                   double* wR);
+/* Host copies of the iteration count, the number of exact evaluations done
+ * so far (insertion tuples priced and removal gains), and every chain's
+ * current and best makespan, temperature and operator weights ([chains][6],
+ * [chains][4]); any pointer may be NULL.  Synchronises the device. */
+int alns_get_state(const alns_state* st, int64_t* iterations, int64_t* evals, int32_t* z, int32_t* zb, double* T,
+                   double* wD, double* wR);
 int alns_state_destroy(alns_state* st);
 
 #ifdef __cplusplus

@@ -44,7 +44,7 @@ SIGNATURES = {
     "vrprpd_set_destroy": (C.c_int, [_P]),
     "vrprpd_set_info": (C.c_int, [_P, _P, _P, _P, _P]),
     "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
-    "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
                                _P, _P, _P, _P]),
@@ -53,7 +53,7 @@ SIGNATURES = {
     "alns_step": (C.c_int, [_P, _I32, _P]),
     "alns_set_trace": (C.c_int, [_P, _P, _I64]),
     "alns_get_best": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
-    "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "alns_state_destroy": (C.c_int, [_P]),
 }
 
@@ -162,7 +162,7 @@ def vrprpd_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None
 
 def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_bases=1,
                        base_inst=None, base_op_off=None, base_rt_off=None, seg_base=None,
-                       want_each=True, stream=None):
+                       want_each=True, blocks_per_seg=None, stream=None):
     """Exact makespan of insertion tuples against base partial solutions (see
     vrprpd_insert_scan in vrprpd.h).  tuples: device uint8 tensor holding the
     packed 8-byte tuples (TUPLE_DTYPE).  Returns (mk, status, seg_top3)."""
@@ -172,13 +172,15 @@ def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_b
     mk = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
     st = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
     top = torch.empty((max(S_, 0), 3), dtype=torch.int64, device=dev)
+    if blocks_per_seg is None:      # about 64 tuples per workgroup
+        blocks_per_seg = max(1, min(65535, -(-T // max(1, S_ * 64))))
     _check(load().vrprpd_insert_scan(
         S.handle, num_bases, _dptr(base_inst, torch.int32, "base_inst"),
         _dptr(base_op_off, torch.int64, "base_op_off"), _dptr(base_ops, torch.uint16, "base_ops"),
         _dptr(base_rt_off, torch.int64, "base_rt_off"), _dptr(base_rt, torch.uint16, "base_rt"),
         S_, _dptr(seg_off, torch.int64, "seg_off"), _dptr(seg_base, torch.int32, "seg_base"),
         _dptr(tuples, torch.uint8, "tuples"), _dptr(mk, torch.int32, "mk"), _dptr(st, None, "st"),
-        _dptr(top, torch.int64, "seg_top3"), _stream(stream)))
+        _dptr(top, torch.int64, "seg_top3"), blocks_per_seg, _stream(stream)))
     return mk, st, top
 
 
@@ -292,14 +294,15 @@ class AlnsState:
 
     def state(self):
         it = C.c_int64()
+        ev = C.c_int64()
         z = np.zeros(self.chains, np.int32)
         zb = np.zeros(self.chains, np.int32)
         T = np.zeros(self.chains, np.float64)
         wD = np.zeros((self.chains, 6), np.float64)
         wR = np.zeros((self.chains, 4), np.float64)
-        _check(load().alns_get_state(self.handle, C.byref(it), z.ctypes.data, zb.ctypes.data, T.ctypes.data,
-                                     wD.ctypes.data, wR.ctypes.data))
-        return dict(iterations=it.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
+        _check(load().alns_get_state(self.handle, C.byref(it), C.byref(ev), z.ctypes.data, zb.ctypes.data,
+                                     T.ctypes.data, wD.ctypes.data, wR.ctypes.data))
+        return dict(iterations=it.value, evals=ev.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -59,6 +59,7 @@ struct AlnsDev {
     int64_t *base_op_off, *base_rt_off;   // [C] offsets of the current W buffers
     int64_t* trace;                // [C][trace_cap][4] or null
     int64_t trace_cap;
+    unsigned long long* evals;     // exact evaluations performed (tuples and removal gains)
 };
 
 __device__ __forceinline__ uint32_t adraw(uint64_t seed, uint32_t a, uint32_t it, uint32_t chain)
@@ -303,6 +304,7 @@ __global__ __launch_bounds__(64 * WPB) void k_gains(AlnsDev a, int per_block)
         const int zc = group_max<GL>(rv);
         if (li == 0) a.gains[(int64_t)c * (a.N + 1) + cust] = (long long)zS - zc;
     }
+    if (threadIdx.x == 0) atomicAdd(a.evals, (unsigned long long)(c1 - c0 + 1));
 }
 
 // ---------------------------------------------------------------- destroy
@@ -692,6 +694,11 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
         fail = 0;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < nl; ++i) tot += (unsigned long long)a.seg_cnt[c * a.Q + i];
+        atomicAdd(a.evals, tot);
+    }
     for (int i = 0; i < nl; ++i) {
         const int sidx = c * a.Q + i;
         const long long key0 = a.seg_top3[3 * sidx];
@@ -1061,7 +1068,7 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     A(d.rstate, C); A(d.rem, (size_t)C * Q); A(d.left, (size_t)C * Q); A(d.gains, (size_t)C * (N + 1));
     A(d.tuples, (size_t)C * Q * TPC); A(d.tmk, (size_t)C * Q * TPC); A(d.tst, (size_t)C * Q * TPC);
     A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
-    A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C);
+    A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C); A(d.evals, 1);
 #undef A
     if (rc != VRPRPD_OK) {
         alns_state_destroy(s);
@@ -1223,7 +1230,7 @@ static int one_iteration(alns_state* s, hipStream_t st)
     }
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
-                d.C * d.Q};
+                d.C * d.Q, std::max(1, (d.TPC + 63) / 64)};
     for (int r = 0; r < d.Q; ++r) {
         auto* ke = k_enum<DT>;
         if (s->lds_enum > 64 * 1024)
@@ -1291,14 +1298,15 @@ extern "C" int alns_get_best(const alns_state* s, int32_t chain, int32_t* mk, ui
     return VRPRPD_OK;
 }
 
-extern "C" int alns_get_state(const alns_state* s, int64_t* iterations, int32_t* z, int32_t* zb, double* T,
-                              double* wD, double* wR)
+extern "C" int alns_get_state(const alns_state* s, int64_t* iterations, int64_t* evals, int32_t* z, int32_t* zb,
+                              double* T, double* wD, double* wR)
 {
     using namespace vrprpd;
     if (!s) return set_error(VRPRPD_EINVAL, "alns_get_state: state is NULL");
     VRP_HIP(hipDeviceSynchronize());
     const int C = s->d.C;
     if (iterations) *iterations = s->it;
+    if (evals) VRP_HIP(hipMemcpy(evals, s->d.evals, sizeof(int64_t), hipMemcpyDeviceToHost));
     if (z) VRP_HIP(hipMemcpy(z, s->d.z, C * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (zb) VRP_HIP(hipMemcpy(zb, s->d.zb, C * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (T) VRP_HIP(hipMemcpy(T, s->d.T, C * sizeof(double), hipMemcpyDeviceToHost));

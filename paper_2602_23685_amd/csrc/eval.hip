@@ -37,7 +37,7 @@ struct GroupLayout {
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-constexpr int kStepOps = 4;   // ops a lane may take per sweep step
+constexpr int kStepOps = 8;   // most ops a lane may take per sweep step (LDS padding)
 
 __host__ __device__ inline int op_capacity(int n_max) { return 2 * n_max + kStepOps; }
 
@@ -67,7 +67,7 @@ __device__ __forceinline__ void stage_code(OpStore<DT>& S, uint32_t* bits, int j
     S.set_code(j, ok ? cd : 0u);
 }
 
-template <typename DT, int GL, int WPB>
+template <typename DT, int GL, int WPB, int K>
 __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int q = q0 + v * GL;
-                x[v] = q < nvec ? vec[q] : make_uint4(0, 0, 0, 0);
+                x[v] = vec[q < nvec ? q : nvec - 1];
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -152,15 +152,17 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
             cbad = cbad || (old & mask);
         }
         // ready[c] = ~p_c ("not dropped yet"; the drop reads p_c back from it)
-        for (int c0 = li; c0 <= n; c0 += 4 * GL) {
-            int pv[4];
+        // (loads clamped to p_n rather than predicated, so all eight issue
+        // back to back instead of one branch and one wait each)
+        for (int c0 = li; c0 <= n; c0 += 8 * GL) {
+            int pv[8];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 8; ++v) {
                 const int c = c0 + v * GL;
-                pv[v] = c <= n ? P[c] : 0;
+                pv[v] = P[c <= n ? c : n];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 8; ++v) {
                 const int c = c0 + v * GL;
                 if (c <= n) ready[c] = ~pv[v];
             }
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     // ---- phase 2: timing sweep ----------------------------------------------
     const bool veh = li < m;
     SweepOut o{0, 0, 0, 0, false};
-    if (!gbad) o = sweep_group<GL, kStepOps, DT>(S, ready, veh ? s : 0, veh ? e : 0);
+    if (!gbad) o = sweep_group<GL, K, DT>(S, ready, veh ? s : 0, veh ? e : 0);
 
     uint32_t st = 0;
     int z = 0;
@@ -230,6 +232,8 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     }
 }
 
+constexpr int kEvalStep = 4;   // ops per lane per sweep step
+
 struct LaunchShape {
     int gl, wpb, group_bytes, lds;
 };
@@ -249,7 +253,7 @@ static LaunchShape eval_shape(int n_max, int m_max, int dist16)
 template <typename DT, int GL, int WPB>
 static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
 {
-    auto* k = eval_kernel<DT, GL, WPB>;
+    auto* k = eval_kernel<DT, GL, WPB, kEvalStep>;
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));

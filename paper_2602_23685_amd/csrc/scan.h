@@ -22,6 +22,7 @@ struct ScanArgs {
     int64_t* seg_top3;
     const int32_t* seg_cnt;   // internal: segment s covers [seg_off[s], seg_off[s] + seg_cnt[s])
     int32_t num_bases, num_inst, n_max, num_seg;
+    int32_t blocks_per_seg;   // blocks sharing one segment's tuples (>= 1)
 };
 
 // Launches the insertion-scan kernel for the arguments above.

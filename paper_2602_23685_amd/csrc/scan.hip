@@ -62,6 +62,7 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / GL, li = lane % GL, gidx = wave * G + grp;
     const int seg = blockIdx.x;
+    const int ychunk = blockIdx.y, ny = gridDim.y;   // blocks sharing the segment
     const ScanLayout L = scan_layout<WPB, GL>(a.n_max, OpStore<DT>::kBytesPerOp);
     int* pblk = reinterpret_cast<int*>(smem + L.p_off);
     uint32_t* bits = reinterpret_cast<uint32_t*>(smem + L.bits_off);
@@ -78,10 +79,7 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
 
     const int64_t t0 = a.seg_off[seg];
     const int64_t t1 = a.seg_cnt ? t0 + a.seg_cnt[seg] : a.seg_off[seg + 1];
-    if (t1 <= t0) {                      // empty segment: nothing to stage
-        if (threadIdx.x < 3) a.seg_top3[3 * seg + threadIdx.x] = INT64_MAX;
-        return;
-    }
+    if (t1 <= t0 + (int64_t)ychunk * WPB * G) return;   // nothing for this block: skip the staging
     int bi = a.seg_base ? a.seg_base[seg] : 0;
     const bool bad_base_idx = bi < 0 || bi >= a.num_bases;
     if (bad_base_idx) bi = 0;
@@ -161,7 +159,7 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
     const bool veh = li < m;
     const int my_s = veh && !base_bad && !seg_bad ? rs_[li] : 0;
     const int my_len = veh && !base_bad && !seg_bad ? re_[li] - my_s : 0;
-    for (int64_t t = t0 + gidx; t < t1; t += WPB * G) {
+    for (int64_t t = t0 + (int64_t)ychunk * WPB * G + gidx; t < t1; t += (int64_t)ny * WPB * G) {
         const vrprpd_tuple tp = a.tuples[t];
         const int c = tp.c, vD = tp.vD, vP = tp.vP, pD = tp.pD, pP = tp.pP;
         bool valid = !seg_bad && c >= 1 && c <= n && vD < m && vP < m;
@@ -250,10 +248,26 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
     if (tid == 0) {
         long long t3[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
         for (int i = 0; i < 3 * WPB * G; ++i) top3_insert(t3, topbuf[i]);
-        a.seg_top3[3 * seg + 0] = t3[0];
-        a.seg_top3[3 * seg + 1] = t3[1];
-        a.seg_top3[3 * seg + 2] = t3[2];
+        // Merge into the segment's sorted triple, shared with the other blocks
+        // of the segment: each key goes through the three slots with atomicMin,
+        // carrying down whatever it displaces, so the slots end up holding the
+        // three smallest keys whatever the order of the blocks.
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(a.seg_top3 + 3 * seg);
+        for (int i = 0; i < 3 && t3[i] != INT64_MAX; ++i) {
+            unsigned long long carry = (unsigned long long)t3[i];
+            for (int sl = 0; sl < 3; ++sl) {
+                const unsigned long long old = atomicMin(&dst[sl], carry);
+                carry = old > carry ? old : carry;
+            }
+        }
     }
+}
+
+// seg_top3 <- INT64_MAX before the scan blocks merge into it.
+__global__ void top3_fill_kernel(int64_t* top, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) top[i] = INT64_MAX;
 }
 
 template <typename DT, int GL>
@@ -267,7 +281,11 @@ int launch_scan(const ScanArgs& a, hipStream_t stream)
     if (L.bytes > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     L.bytes));
-    hipLaunchKernelGGL(k, dim3(a.num_seg), dim3(64 * WPB), L.bytes, stream, a);
+    const int64_t cnt = 3 * (int64_t)a.num_seg;
+    hipLaunchKernelGGL(top3_fill_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.seg_top3, cnt);
+    VRP_HIP(hipGetLastError());
+    const int ny = a.blocks_per_seg > 0 ? a.blocks_per_seg : 1;
+    hipLaunchKernelGGL(k, dim3(a.num_seg, ny), dim3(64 * WPB), L.bytes, stream, a);
     VRP_HIP(hipGetLastError());
     return VRPRPD_OK;
 }
@@ -293,10 +311,11 @@ extern "C" int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, cons
                                   const int64_t* base_op_off, const uint16_t* base_ops,
                                   const int64_t* base_rt_off, const uint16_t* base_rt_end, int32_t num_seg,
                                   const int64_t* seg_off, const int32_t* seg_base, const vrprpd_tuple* tuples,
-                                  int32_t* mk_out, uint32_t* st_out, int64_t* seg_top3, void* stream)
+                                  int32_t* mk_out, uint32_t* st_out, int64_t* seg_top3, int32_t blocks_per_seg,
+                                  void* stream)
 {
     if (!set) return set_error(VRPRPD_EINVAL, "vrprpd_insert_scan: set is NULL");
-    if (num_bases < 1 || num_seg < 0)
+    if (num_bases < 1 || num_seg < 0 || blocks_per_seg < 0 || blocks_per_seg > 65535)
         return set_error(VRPRPD_EINVAL, "vrprpd_insert_scan: need num_bases >= 1 and num_seg >= 0");
     if (num_seg == 0) return VRPRPD_OK;
     if (!base_ops || !base_rt_end || !seg_off || !tuples || !seg_top3)
@@ -308,6 +327,6 @@ extern "C" int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, cons
     const int m_max = base_inst ? set->m_max : set->host[0].m;
     ScanArgs a{set->d_inst, set->d_dist, set->d_proc, base_inst, base_op_off, base_ops, base_rt_off, base_rt_end,
                seg_off, seg_base, tuples, mk_out, st_out, seg_top3, nullptr, num_bases, set->num_inst, n_lds,
-               num_seg};
+               num_seg, blocks_per_seg};
     return insert_scan_launch(a, m_max, set->dist16, reinterpret_cast<hipStream_t>(stream));
 }

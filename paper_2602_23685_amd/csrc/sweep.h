@@ -95,16 +95,17 @@ __device__ __forceinline__ int sweep_step(SweepOut& o, const uint32_t* cd, const
         }
         const bool ok = go && (u < n_left) && (!isP || rdy);
         const int tn = isP ? (arr > rv ? arr : rv) : arr;
-        if (ok && !isP) {
-            int val;
-            if constexpr (kPolarity) {
-                const int x = arr + pblk[c];
-                val = pol ? ~x : x;
-            } else {
-                val = arr + ~r[u];
-            }
-            lds_store(&ready[c], val);
+        // A drop publishes its ready time.  Every other case writes to the
+        // unused slot ready[0] instead of branching around the store.
+        const bool pub = ok && !isP;
+        int val;
+        if constexpr (kPolarity) {
+            const int x = arr + pblk[pub ? c : 0];
+            val = pol ? ~x : x;
+        } else {
+            val = arr + ~r[u];
         }
+        lds_store(&ready[pub ? c : 0], val);
         o.t = ok ? tn : o.t;
         o.w += ok ? (isP ? -1 : 1) : 0;
         o.wmax = o.w > o.wmax ? o.w : o.wmax;

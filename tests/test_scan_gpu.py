@@ -24,9 +24,9 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def run_scan(P, S, bops, brt, tuples, seg_off):
+def run_scan(P, S, bops, brt, tuples, seg_off, blocks_per_seg=None):
     mk, st, top = P.vrprpd_insert_scan(S, dev(bops), dev(brt), dev(seg_off),
-                                       dev(tuples.view(np.uint8)))
+                                       dev(tuples.view(np.uint8)), blocks_per_seg=blocks_per_seg)
     torch.cuda.synchronize()
     return mk.cpu().numpy(), st.cpu().numpy().view(np.uint32), top.cpu().numpy()
 
@@ -106,3 +106,17 @@ def test_scan_empty_segments(orc, P):
     mk, st, top = run_scan(P, S, bops, brt, tuples, seg_off)
     omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg_off)
     assert np.array_equal(top, otop) and np.all(top[[0, 2, 4]] == INT64_MAX)
+
+
+@pytest.mark.parametrize("bps", [1, 3, 40])
+def test_scan_split_segments(orc, P, bps):
+    """Several workgroups per segment merge their top-3 keys atomically; the
+    result must not depend on how many share a segment."""
+    inst = synth.make_instance(50, 3, 4, 12, "2x", seed=14)
+    bops, brt = make_base(inst, 9, 5)
+    tuples = synth.random_tuples(bops, brt, 50, 3, 2500, seed=10)
+    seg_off = np.array([0, 1, 700, 2000, 2500], np.int64)
+    S = P.InstanceSet([inst])
+    mk, st, top = run_scan(P, S, bops, brt, tuples, seg_off, blocks_per_seg=bps)
+    omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg_off)
+    assert np.array_equal(mk, omk) and np.array_equal(st, ost) and np.array_equal(top, otop)
