@@ -118,7 +118,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-race", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only copy 256 MiB three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_ref:
+        import torch
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 256 MiB three times")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)

@@ -68,6 +68,7 @@ extern "C" {
 #define VRPRPD_ALLOW_PARTIAL 1 /* customers may be absent (neither op present) */
 
 typedef struct vrprpd_set vrprpd_set;
+typedef struct vrprpd_mlp vrprpd_mlp;
 
 typedef struct {
     int32_t n;          /* customers, 1 <= n <= 10000 (per-candidate state lives in LDS) */
@@ -321,6 +322,112 @@ int alns_get_best(const alns_state* st, int32_t chain, int32_t* mk, uint16_t* op
 int alns_get_state(const alns_state* st, int64_t* iterations, int64_t* evals, int32_t* z, int32_t* zb, double* T,
                    double* wD, double* wR);
 int alns_state_destroy(alns_state* st);
+
+/* ---- ALNS with a learned destroy proposal ----------------------------------
+ * (Section 6 names learned destroy operators as future work; this is the
+ * library's form.)  Each iteration every chain builds K candidate removal
+ * sets with the roulette-selected destroy operator, candidate j drawing its
+ * random words at counters 16 + 4096 j + i (candidate 0 is the plain
+ * operator's set).  The network (vrprpd_mlp_*) scores each customer of the
+ * current solution S from 64 features; a set's score is the sum over its
+ * customers, the predicted (z' - z) / z; the chain takes the lowest score
+ * (ties to the lower index) -- or, with probability eps (Philox counter 3),
+ * candidate 0.  Repair, acceptance and scoring are unchanged: the exact
+ * evaluator prices every insertion and judges every makespan.
+ *
+ * Features of customer c in S (fp32, each one correctly rounded division of
+ * two integers, stored as bfloat16 [C][n_max][64], row c - 1): with z the
+ * makespan, dbar = max(1, floor(sum_i d[0][i] / n)), for c's drop D and
+ * pickup P: vehicle v, 0-based position i, route length L, start time t,
+ * arrival a, neighbours prev / next (depot 0 at the route ends), route finish
+ * f, walk = drops - pickups up to the op, g = z - z(S without c):
+ *  0 1, 1 d(0,c)/dbar, 2 p_c/dbar, 3 tD/z, 4 tP/z, 5 (tP-tD-p_c)/z,
+ *  6 (tP-aP)/z, 7 [vD=vP], 8 iD/LD, 9 iP/LP, 10 fD/z, 11 fP/z, 12 [fD=z],
+ *  13 [fP=z], 14 (d(prevD,c)+d(c,nextD)-d(prevD,nextD))/dbar, 15 the same
+ *  for P, 16 d(prevD,c)/dbar, 17 d(c,nextD)/dbar, 18 d(prevP,c)/dbar,
+ *  19 d(c,nextP)/dbar, 20 g/z, 21 walkD/k, 22 walkP/k, 23 LD m/(2n),
+ *  24 LP m/(2n), 25 (iP-iD)/LD if vD=vP else 0, 26 nearest other node/dbar,
+ *  27 (sum of the 4 nearest other nodes)/(4 dbar) (fewer others: all of
+ *  them), 28 (z-fD)/z, 29 (z-fP)/z, 30 [g>0], 31 p_c/(tP-tD) (1 if tP=tD);
+ *  32..63 = 0..31 times [fD=z or fP=z].
+ *
+ * mlp: not owned; NULL turns the proposal off (K = 1).  Its max_rows must be
+ * >= chains x n_max.  EINVAL unless 1 <= K <= 64 and 0 <= eps <= 1. */
+int alns_set_learned(alns_state* st, vrprpd_mlp* mlp, int32_t K, double eps, void* stream);
+/* Starts recording one (features of the removed customers, (z' - z) / z)
+ * set per chain per iteration, up to `capacity` sets (0: stop and free),
+ * from the next iteration on; z' is the repaired candidate's makespan (a
+ * failed repair records an empty set).  Synchronises the stream. */
+int alns_record(alns_state* st, int64_t capacity, void* stream);
+/* Sets recorded so far and the most customers a set can hold (q_max). */
+int alns_record_info(const alns_state* st, int64_t* sets, int32_t* q_max);
+/* A training batch of num_sets recorded sets drawn uniformly with
+ * replacement (Philox, seed): x (device bf16 [num_sets * q_max][64]) gets
+ * their rows back to back, seg_off (device int64 [num_sets + 1]) the row
+ * offsets, target (device fp32 [num_sets]) the makespan changes. */
+int alns_record_batch(const alns_state* st, int32_t num_sets, uint64_t seed, uint16_t* x, int64_t* seg_off,
+                      float* target, void* stream);
+/* Device copies of the last iteration's features ([C][n_max][64] bf16),
+ * candidate sets ([C][K][q_max] and counts [C][K]) and choices ([C]); any
+ * pointer may be NULL. */
+int alns_get_learned(const alns_state* st, uint16_t* feat, int32_t* cand_rem, int32_t* cand_cnt, int32_t* chosen,
+                     void* stream);
+
+/* ---- Learned destroy proposal: the scorer network --------------------------
+ * The paper names learned destroy operators as future work (Section 6) and
+ * fixes no model.  This library's: per-customer features (VRPRPD_MLP_IN =
+ * 64) -> 256 -> 256 -> 256 -> 1, ReLU after each hidden layer.  A removal
+ * set's score is the sum of its customers' scores; training fits it to the
+ * makespan change the set produced by mean squared error over sets.
+ * Precision: bfloat16 GEMM operands (features, weights, hidden activations
+ * and masked upstream gradients, rounded to nearest even) with fp32
+ * accumulation on the matrix cores; biases, head, loss, gradients and the
+ * master weights in fp32.
+ * Flat parameter layout (fp32, VRPRPD_MLP_NUM_PARAMS values): W1[256][64],
+ * b1[256], W2[256][256], b2[256], W3[256][256], b3[256], w4[256], b4[1]
+ * (weights [out][in]).
+ * The handle owns its parameters, momentum and all activations and
+ * workspaces for up to max_rows rows (about 3.1 KB per row plus 150 KB per
+ * 1024 rows); calls on one handle are ordered by the caller's stream and
+ * must not overlap. */
+#define VRPRPD_MLP_IN 64
+#define VRPRPD_MLP_HIDDEN 256
+#define VRPRPD_MLP_NUM_PARAMS 148481
+/* params: host fp32 flat vector, or NULL for Glorot-uniform weights (Philox
+ * draws from seed) and zero biases.  Synchronous.  EINVAL unless 1 <=
+ * max_rows <= 2^26; ENOMEM; EHIP. */
+int vrprpd_mlp_create(vrprpd_mlp** out, int64_t max_rows, const float* params, uint64_t seed);
+int vrprpd_mlp_destroy(vrprpd_mlp* mlp);
+/* Device copies of the parameters and/or of the last backward's gradient
+ * (either pointer may be NULL). */
+int vrprpd_mlp_get_params(const vrprpd_mlp* mlp, float* params, float* grad, void* stream);
+/* Replaces the parameters (device fp32 flat) and clears the momentum. */
+int vrprpd_mlp_set_params(vrprpd_mlp* mlp, const float* params, void* stream);
+/* Scores rows: x is device bf16 [rows][64] (16-byte aligned, kept by
+ * reference until the next forward: backward reads it); y (device fp32
+ * [rows]) may be NULL.  Hidden activations stay in the handle.  EINVAL if
+ * rows > max_rows. */
+int vrprpd_mlp_forward(vrprpd_mlp* mlp, int64_t rows, const uint16_t* x, float* y, void* stream);
+/* Set scores of the last forward: set_score[s] = sum of the scores of rows
+ * [seg_off[s], seg_off[s+1]) (device int64 offsets, non-decreasing, within
+ * the rows). */
+int vrprpd_mlp_set_scores(vrprpd_mlp* mlp, int32_t num_sets, const int64_t* seg_off, float* set_score, void* stream);
+/* Loss of the last forward against target[s] (device fp32): stores each
+ * set's squared error in sq_err (device, nullable; the loss is their mean)
+ * and keeps dL/dscore per row for vrprpd_mlp_backward. */
+int vrprpd_mlp_loss(vrprpd_mlp* mlp, int32_t num_sets, const int64_t* seg_off, const float* target, float* sq_err,
+                    void* stream);
+/* Gradient of the loss through the last forward, from dy (device fp32
+ * [rows], dL/d(row score)) or, when dy is NULL, from vrprpd_mlp_loss.  The
+ * result (flat, fp32) stays in the handle for vrprpd_mlp_sgd_step. */
+int vrprpd_mlp_backward(vrprpd_mlp* mlp, const float* dy, void* stream);
+/* Heavy-ball step: v = momentum v + grad; p = p - lr v (fp32), then the
+ * bfloat16 copy is refreshed.  EINVAL unless lr >= 0, 0 <= momentum < 1. */
+int vrprpd_mlp_sgd_step(vrprpd_mlp* mlp, float lr, float momentum, void* stream);
+/* Device copy of a kept tensor of the last forward/backward, bf16
+ * [rows][256]: layer 0..2 = hidden activations h1..h3, 3..4 = the two
+ * masked-gradient buffers (after a backward: 3 holds dz1, 4 holds dz2). */
+int vrprpd_mlp_hidden(const vrprpd_mlp* mlp, int32_t layer, uint16_t* out, void* stream);
 
 #ifdef __cplusplus
 }

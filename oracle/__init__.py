@@ -110,6 +110,9 @@ def _declare_alns(L):
     L.orc_det_exp.argtypes = [C.c_double]
     L.orc_alns_qrange.restype = None
     L.orc_alns_qrange.argtypes = [C.c_int, P, P]
+    L.orc_alns_destroy.restype = C.c_int32
+    L.orc_alns_destroy.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                   C.c_int32, P]
 
 
 def det_exp(x):
@@ -120,6 +123,20 @@ def alns_qrange(n):
     a, b = C.c_int(), C.c_int()
     lib().orc_alns_qrange(n, C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def alns_destroy(inst, op, ops, rt_end, q, q_min, seed, it, chain, cand=0):
+    """Removed customers (list) of destroy operator `op` on a complete
+    solution, as in iteration `it` of chain `chain`, candidate `cand`."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    rem = np.zeros(oi.n + 1, dtype=np.int32)
+    cnt = lib().orc_alns_destroy(oi.ref, op, _ptr(ops), _ptr(rt), q, q_min, seed & (2**64 - 1), it, chain, cand,
+                                 _ptr(rem))
+    if cnt < 0:
+        raise ValueError("solution is not feasible")
+    return [int(x) for x in rem[:cnt]]
 
 
 def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False):

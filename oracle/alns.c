@@ -259,18 +259,21 @@ static void removal_gains(const orc_inst* I, const sol_t* S, int32_t z, long lon
     memset(gone, 0, (size_t)n + 1);
 }
 
-/* Returns the number of removed customers written to rem (in order). */
+/* Returns the number of removed customers written to rem (in order).
+ * Candidate `cand` of a learned proposal draws its random words at counter
+ * offsets 16 + 4096 cand + i (cand 0: the plain operator's draws). */
 static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, int q_min, uint64_t seed,
-                   uint32_t it, uint32_t chain, int* rem, sol_t* tmp, unsigned char* gone)
+                   uint32_t it, uint32_t chain, int cand, int* rem, sol_t* tmp, unsigned char* gone)
 {
     const int n = I->n, m = I->m, N1 = n + 1;
+    const uint32_t db = 16u + 4096u * (uint32_t)cand;
     int cnt = 0;
     if (q > n) q = n;
     if (op == 0) {                                   /* random: partial Fisher-Yates */
         int* a = malloc((size_t)n * sizeof(int));
         for (int i = 0; i < n; ++i) a[i] = i + 1;
         for (int i = 0; i < q; ++i) {
-            int j = i + uint_below(adraw(seed, 16 + i, it, chain), n - i);
+            int j = i + uint_below(adraw(seed, db + i, it, chain), n - i);
             int x = a[i]; a[i] = a[j]; a[j] = x;
             rem[cnt++] = a[i];
         }
@@ -293,7 +296,7 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
                 for (int i = 0; i < n; ++i) tot += w[i];
                 if (tot == 0) break;
                 unsigned long long target =
-                    (unsigned long long)(((unsigned __int128)adraw(seed, 16 + s, it, chain) * tot) >> 32);
+                    (unsigned long long)(((unsigned __int128)adraw(seed, db + s, it, chain) * tot) >> 32);
                 unsigned long long acc = 0;
                 int pick = -1;
                 for (int i = 0; i < n; ++i) {
@@ -349,7 +352,7 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
                 if (S->ops[j] & 1) pv[c] = v;
                 else { dv[c] = v; td[c] = times[j]; }
             }
-        int seedc = 1 + uint_below(adraw(seed, 16, it, chain), n);
+        int seedc = 1 + uint_below(adraw(seed, db, it, chain), n);
         kc_t* k = malloc((size_t)n * sizeof(kc_t));
         int nk = 0;
         for (int c = 1; c <= n; ++c) {
@@ -365,7 +368,7 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
         for (int i = 0; i < nk && cnt < q; ++i) rem[cnt++] = k[i].c;
         free(k); free(times); free(td); free(dv); free(pv);
     } else if (op == 3) {                            /* cluster */
-        int cen = 1 + uint_below(adraw(seed, 16, it, chain), n);
+        int cen = 1 + uint_below(adraw(seed, db, it, chain), n);
         kc_t* k = malloc((size_t)n * sizeof(kc_t));
         int nk = 0;
         for (int c = 1; c <= n; ++c) {
@@ -381,7 +384,7 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
     } else {                                         /* route */
         int nonempty = 0;
         for (int v = 0; v < m; ++v) nonempty += rlen(S, v) > 0;
-        int pickv = uint_below(adraw(seed, 16, it, chain), nonempty);
+        int pickv = uint_below(adraw(seed, db, it, chain), nonempty);
         int v = 0;
         for (int seen = -1; v < m; ++v)
             if (rlen(S, v) > 0 && ++seen == pickv) break;
@@ -559,7 +562,7 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
             const int q = q_min + uint_below(adraw(seed, 2, u_it, u_ch), q_max - q_min + 1);
             c->aD[di]++;
             c->aR[ri]++;
-            int nrem = destroy(I, di, &c->S, c->z, q, q_min, seed, u_it, u_ch, rem, &tmp, gone);
+            int nrem = destroy(I, di, &c->S, c->z, q, q_min, seed, u_it, u_ch, 0, rem, &tmp, gone);
             memset(gone, 0, (size_t)n + 1);
             for (int i = 0; i < nrem; ++i) gone[rem[i]] = 1;
             sol_remove(&c->S, gone, m, &work);
@@ -661,4 +664,34 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
     free(C); sol_free(&work); sol_free(&tmp); sol_free(&tmp2);
     free(dbuf); free(pbuf); free(tbuf); free(rem); free(gone);
     return best;
+}
+
+
+/* One destroy operator applied to a complete solution (ops / rt_end) as
+ * iteration `it` of chain `chain` would apply it, candidate `cand`; writes
+ * the removed customers to rem (up to q) and returns their number, or -1 if
+ * the solution is not feasible. */
+int32_t orc_alns_destroy(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, int32_t q,
+                         int32_t q_min, uint64_t seed, uint32_t it, uint32_t chain, int32_t cand, int32_t* rem)
+{
+    const int n = I->n, m = I->m;
+    sol_t S, tmp;
+    sol_alloc(&S, n, m);
+    sol_alloc(&tmp, n, m);
+    S.L = rt_end[m - 1];
+    memcpy(S.ops, ops, (size_t)S.L * sizeof(uint16_t));
+    memcpy(S.rt, rt_end, (size_t)m * sizeof(uint16_t));
+    int32_t z;
+    int rc = -1;
+    if (sol_eval(I, &S, &z, NULL) == 0) {
+        unsigned char* gone = calloc((size_t)n + 1, 1);
+        int* r = malloc((size_t)(n + 1) * sizeof(int));
+        rc = destroy(I, op, &S, z, q, q_min, seed, it, chain, cand, r, &tmp, gone);
+        for (int i = 0; i < rc; ++i) rem[i] = r[i];
+        free(r);
+        free(gone);
+    }
+    sol_free(&S);
+    sol_free(&tmp);
+    return rc;
 }

@@ -91,6 +91,12 @@ void orc_alns_qrange(int n, int* q_min, int* q_max);
 int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
                      uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
                      uint16_t* best_rt, int32_t* best_mk, int64_t* trace);
+/* One destroy operator on a complete feasible solution, as iteration `it` of
+ * chain `chain` applies it, candidate `cand` of a learned proposal (draw
+ * counters 16 + 4096 cand + i).  Returns the number of removed customers
+ * written to rem, or -1 if the solution is infeasible. */
+int32_t orc_alns_destroy(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, int32_t q,
+                         int32_t q_min, uint64_t seed, uint32_t it, uint32_t chain, int32_t cand, int32_t* rem);
 
 /* Warm-start population from one solution (Section 4.4.4). */
 void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,

@@ -55,7 +55,24 @@ SIGNATURES = {
     "alns_get_best": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
     "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "alns_state_destroy": (C.c_int, [_P]),
+    "alns_set_learned": (C.c_int, [_P, _P, _I32, C.c_double, _P]),
+    "alns_record": (C.c_int, [_P, _I64, _P]),
+    "alns_record_info": (C.c_int, [_P, _P, _P]),
+    "alns_record_batch": (C.c_int, [_P, _I32, _U64, _P, _P, _P, _P]),
+    "alns_get_learned": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "vrprpd_mlp_create": (C.c_int, [C.POINTER(C.c_void_p), _I64, _P, _U64]),
+    "vrprpd_mlp_destroy": (C.c_int, [_P]),
+    "vrprpd_mlp_get_params": (C.c_int, [_P, _P, _P, _P]),
+    "vrprpd_mlp_set_params": (C.c_int, [_P, _P, _P]),
+    "vrprpd_mlp_forward": (C.c_int, [_P, _I64, _P, _P, _P]),
+    "vrprpd_mlp_set_scores": (C.c_int, [_P, _I32, _P, _P, _P]),
+    "vrprpd_mlp_loss": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
+    "vrprpd_mlp_backward": (C.c_int, [_P, _P, _P]),
+    "vrprpd_mlp_sgd_step": (C.c_int, [_P, C.c_float, C.c_float, _P]),
+    "vrprpd_mlp_hidden": (C.c_int, [_P, _I32, _P, _P]),
 }
+
+MLP_IN, MLP_HIDDEN, MLP_NUM_PARAMS = 64, 256, 148481
 
 
 def load():
@@ -304,9 +321,139 @@ class AlnsState:
                                      T.ctypes.data, wD.ctypes.data, wR.ctypes.data))
         return dict(iterations=it.value, evals=ev.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
 
+    # ---- learned destroy proposal ------------------------------------------
+    def set_learned(self, mlp, K=8, eps=0.1, stream=None):
+        """Score K candidate removal sets per chain with `mlp` (None: off)."""
+        self._mlp = mlp
+        self.K = K if mlp is not None else 1
+        _check(load().alns_set_learned(self.handle, mlp.handle if mlp is not None else None, K, float(eps),
+                                       _stream(stream)))
+
+    def record(self, capacity, stream=None):
+        _check(load().alns_record(self.handle, int(capacity), _stream(stream)))
+
+    def record_info(self):
+        sets, q = C.c_int64(), C.c_int32()
+        _check(load().alns_record_info(self.handle, C.byref(sets), C.byref(q)))
+        return sets.value, q.value
+
+    def record_batch(self, num_sets, seed, stream=None):
+        """(x [rows, 64] uint16 bf16 bits, seg_off [num_sets + 1], target
+        [num_sets]) of num_sets recorded sets; x has room for q_max rows per
+        set, the filled rows are x[:seg_off[-1]]."""
+        _, q = self.record_info()
+        x = torch.zeros((num_sets * q, MLP_IN), dtype=torch.uint16, device="cuda")
+        seg = torch.empty(num_sets + 1, dtype=torch.int64, device="cuda")
+        tgt = torch.empty(num_sets, dtype=torch.float32, device="cuda")
+        _check(load().alns_record_batch(self.handle, num_sets, seed & (2**64 - 1), _dptr(x), _dptr(seg),
+                                        _dptr(tgt), _stream(stream)))
+        return x, seg, tgt
+
+    def learned_state(self, stream=None):
+        """Device copies of the last iteration's features, candidate sets,
+        counts and choices."""
+        K = getattr(self, "K", 1)
+        _, q = self.record_info()
+        feat = torch.empty((self.chains, self.n_max, MLP_IN), dtype=torch.uint16, device="cuda")
+        rem = torch.empty((self.chains, K, q), dtype=torch.int32, device="cuda")
+        cnt = torch.empty((self.chains, K), dtype=torch.int32, device="cuda")
+        chosen = torch.empty(self.chains, dtype=torch.int32, device="cuda")
+        _check(load().alns_get_learned(self.handle, _dptr(feat), _dptr(rem), _dptr(cnt), _dptr(chosen),
+                                       _stream(stream)))
+        return feat, rem, cnt, chosen
+
     def close(self):
         if getattr(self, "handle", None):
             load().alns_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The destroy-proposal scorer network on the device (vrprpd_mlp_*).
+    Features are bfloat16 bit patterns in a torch.uint16 (or torch.bfloat16)
+    device tensor of shape [rows, 64]."""
+
+    def __init__(self, max_rows, params=None, seed=0):
+        h = C.c_void_p()
+        host = None
+        if params is not None:
+            host = np.ascontiguousarray(params, dtype=np.float32)
+            if host.shape != (MLP_NUM_PARAMS,):
+                raise ValueError(f"params must have {MLP_NUM_PARAMS} values")
+        _check(load().vrprpd_mlp_create(C.byref(h), int(max_rows),
+                                        None if host is None else host.ctypes.data, seed & (2**64 - 1)))
+        self.handle = h
+        self.max_rows = int(max_rows)
+        self.rows = 0
+
+    @staticmethod
+    def _x(x):
+        if x.dtype == torch.bfloat16:
+            x = x.view(torch.uint16)
+        return _dptr(x, torch.uint16, "x")
+
+    def forward(self, x, y=None, stream=None):
+        rows = int(x.shape[0])
+        if rows and tuple(x.shape) != (rows, MLP_IN):
+            raise ValueError(f"x must be [rows, {MLP_IN}]")
+        if y is None:
+            y = torch.empty(rows, dtype=torch.float32, device="cuda")
+        self._xkeep = x
+        _check(load().vrprpd_mlp_forward(self.handle, rows, self._x(x) if rows else None,
+                                         _dptr(y, torch.float32, "y"), _stream(stream)))
+        self.rows = rows
+        return y
+
+    def set_scores(self, seg_off, out=None, stream=None):
+        S = int(seg_off.shape[0]) - 1
+        if out is None:
+            out = torch.empty(S, dtype=torch.float32, device="cuda")
+        _check(load().vrprpd_mlp_set_scores(self.handle, S, _dptr(seg_off, torch.int64, "seg_off"),
+                                            _dptr(out, torch.float32, "set_score"), _stream(stream)))
+        return out
+
+    def loss(self, seg_off, target, sq_err=None, stream=None):
+        S = int(seg_off.shape[0]) - 1
+        if sq_err is None:
+            sq_err = torch.empty(S, dtype=torch.float32, device="cuda")
+        _check(load().vrprpd_mlp_loss(self.handle, S, _dptr(seg_off, torch.int64, "seg_off"),
+                                      _dptr(target, torch.float32, "target"),
+                                      _dptr(sq_err, torch.float32, "sq_err"), _stream(stream)))
+        return sq_err
+
+    def backward(self, dy=None, stream=None):
+        _check(load().vrprpd_mlp_backward(self.handle, _dptr(dy, torch.float32, "dy"), _stream(stream)))
+
+    def sgd_step(self, lr, momentum=0.0, stream=None):
+        _check(load().vrprpd_mlp_sgd_step(self.handle, float(lr), float(momentum), _stream(stream)))
+
+    def params(self, stream=None):
+        p = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device="cuda")
+        _check(load().vrprpd_mlp_get_params(self.handle, _dptr(p), None, _stream(stream)))
+        return p
+
+    def grad(self, stream=None):
+        g = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device="cuda")
+        _check(load().vrprpd_mlp_get_params(self.handle, None, _dptr(g), _stream(stream)))
+        return g
+
+    def set_params(self, params, stream=None):
+        _check(load().vrprpd_mlp_set_params(self.handle, _dptr(params, torch.float32, "params"), _stream(stream)))
+
+    def hidden(self, layer, stream=None):
+        out = torch.empty((self.rows, MLP_HIDDEN), dtype=torch.uint16, device="cuda")
+        _check(load().vrprpd_mlp_hidden(self.handle, layer, _dptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().vrprpd_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -15,6 +15,7 @@
 // and every import_interval iterations the chains of an instance adopt the
 // best solution among them.  The operator and tie-breaking rules follow the
 // readings stated in the header of vrprpd.h's alns section.
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -60,6 +61,23 @@ struct AlnsDev {
     int64_t* trace;                // [C][trace_cap][4] or null
     int64_t trace_cap;
     unsigned long long* evals;     // exact evaluations performed (tuples and removal gains)
+    // learned destroy proposal (Section 6 names learned operators as future
+    // work; this library's form): K candidate removal sets per chain, scored
+    // by the network from per-customer features
+    int32_t K;                     // candidates per chain (1: the plain operator's set only)
+    int32_t learn_on;              // features (and gains for every chain) each iteration
+    double eps;                    // probability of keeping the plain operator's set
+    uint16_t* feat;                // [C][N][64] bf16 features of S's customers (row cust - 1)
+    float* fstat;                  // [C][N + 1][2] static features of the chain's instance
+    int32_t* dbar;                 // [C]
+    float* score;                  // [C][N] network scores
+    int32_t *cand_rem, *cand_cnt;  // [C][K][Q], [C][K]
+    int32_t* chosen;               // [C] candidate taken this iteration
+    // (state, removal set, makespan change) records
+    uint16_t* rec_x;               // [rec_cap][Q][64]
+    float* rec_t;                  // [rec_cap] (z' - z) / z
+    int32_t* rec_n;                // [rec_cap] removed customers
+    int64_t rec_cap, rec_base;     // capacity in sets; iteration of the first record
 };
 
 __device__ __forceinline__ uint32_t adraw(uint64_t seed, uint32_t a, uint32_t it, uint32_t chain)
@@ -259,7 +277,7 @@ __global__ __launch_bounds__(64 * WPB) void k_gains(AlnsDev a, int per_block)
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x;
     const int di = a.di[c];
-    if (di != 1 && di != 5) return;
+    if (!a.learn_on && di != 1 && di != 5) return;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int n = I.n, m = I.m, N1 = n + 1;
     const int c0 = 1 + blockIdx.y * per_block;
@@ -313,6 +331,8 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x;
+    const int cand = blockIdx.y;                        // candidate: draws at 16 + 4096 cand + i
+    const uint32_t db = 16u + 4096u * (uint32_t)cand;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int n = I.n, m = I.m, N1 = n + 1;
     const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
@@ -370,7 +390,7 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
         __syncthreads();
         if (threadIdx.x == 0) {
             for (int i = 0; i < q; ++i) {
-                const int j = i + uint_below(adraw(a.seed, 16 + i, it, uc), n - i);
+                const int j = i + uint_below(adraw(a.seed, db + i, it, uc), n - i);
                 const int x = perm[i];
                 perm[i] = perm[j];
                 perm[j] = x;
@@ -392,7 +412,7 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
             int cnt = 0;
             for (int s2 = 0; s2 < q; ++s2) {
                 if (tot == 0) break;
-                const unsigned long long w32 = adraw(a.seed, 16 + s2, it, uc);
+                const unsigned long long w32 = adraw(a.seed, db + s2, it, uc);
                 const unsigned long long hi = (w32 * (tot >> 32)) + ((w32 * (tot & 0xFFFFFFFFull)) >> 32);
                 unsigned long long acc = 0;
                 int pick = -1;
@@ -410,7 +430,7 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
             sh_cnt = cnt;
         }
     } else if (di == 2 || di == 3) {                 // Shaw, cluster
-        const int cen = 1 + uint_below(adraw(a.seed, 16, it, uc), n);
+        const int cen = 1 + uint_below(adraw(a.seed, db, it, uc), n);
         for (int x = threadIdx.x; x < npow; x += blockDim.x) {
             unsigned long long k = ~0ull;
             const int cc = x + 1;
@@ -445,7 +465,7 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
         if (threadIdx.x == 0) {
             int nonempty = 0;
             for (int v = 0; v < m; ++v) nonempty += re[v] > rs[v];
-            const int pickv = uint_below(adraw(a.seed, 16, it, uc), nonempty);
+            const int pickv = uint_below(adraw(a.seed, db, it, uc), nonempty);
             int v = 0;
             for (int seen = -1; v < m; ++v)
                 if (re[v] > rs[v] && ++seen == pickv) break;
@@ -517,19 +537,62 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
         }
     }
     __syncthreads();
-    const int nrem = sh_cnt;
-    // W = S without the removed customers
+    if (threadIdx.x == 0) {
+        const int nrem = sh_cnt;
+        int32_t* out = a.cand_rem + ((int64_t)c * a.K + cand) * a.Q;
+        for (int i = 0; i < nrem; ++i) out[i] = rem[i];
+        a.cand_cnt[(int64_t)c * a.K + cand] = nrem;
+    }
+}
+
+// ---------------------------------------------------------------- apply
+// Block per chain: takes one candidate removal set (the plain operator's,
+// candidate 0, unless the network picked another) and builds the partial
+// solution W = S without it.
+template <typename DT>
+__global__ __launch_bounds__(256) void k_apply(AlnsDev a, uint32_t it, int use_scores)
+{
+    const int c = blockIdx.x;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int m = I.m, n = I.n;
+    __shared__ int pick;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* flag = smem;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        if (use_scores && a.K > 1 && !(unit_d(adraw(a.seed, 3, it, (uint32_t)c)) < a.eps)) {
+            // lowest predicted makespan change; ties to the lower index
+            float best = 0.f;
+            for (int j = 0; j < a.K; ++j) {
+                const int cnt = a.cand_cnt[(int64_t)c * a.K + j];
+                const int32_t* r = a.cand_rem + ((int64_t)c * a.K + j) * a.Q;
+                float sc = 0.f;
+                for (int i = 0; i < cnt; ++i) sc += a.score[(int64_t)c * a.N + r[i] - 1];
+                if (j == 0 || sc < best) {
+                    best = sc;
+                    k = j;
+                }
+            }
+        }
+        pick = k;
+        a.chosen[c] = k;
+    }
     for (int x = threadIdx.x; x <= n; x += blockDim.x) flag[x] = 0;
     __syncthreads();
+    const int k = pick;
+    const int nrem = a.cand_cnt[(int64_t)c * a.K + k];
+    const int32_t* rem = a.cand_rem + ((int64_t)c * a.K + k) * a.Q;
     for (int i = threadIdx.x; i < nrem; i += blockDim.x) flag[rem[i]] = 1;
     __syncthreads();
     uint16_t* wops = a.W_ops + ((int64_t)2 * c + 0) * 2 * a.N;
     uint16_t* wrt = a.W_rt + ((int64_t)2 * c + 0) * a.M;
+    const uint16_t* sops = a.S_ops + (int64_t)c * 2 * a.N;
+    const uint16_t* srt = a.S_rt + (int64_t)c * a.M;
     if (threadIdx.x == 0) {
-        int w = 0;
+        int w = 0, j = 0;
         for (int v = 0; v < m; ++v) {
-            for (int j = rs[v]; j < re[v]; ++j)
-                if (!flag[S.code(j) >> 1]) wops[w++] = (uint16_t)S.code(j);
+            for (; j < srt[v]; ++j)
+                if (!flag[sops[j] >> 1]) wops[w++] = sops[j];
             wrt[v] = (uint16_t)w;
         }
         a.W_cur[c] = 0;
@@ -537,7 +600,10 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
         a.base_rt_off[c] = ((int64_t)2 * c + 0) * a.M;
         a.nrem[c] = nrem;
         a.nleft[c] = nrem;
-        for (int i = 0; i < nrem; ++i) a.left[c * a.Q + i] = rem[i];
+        for (int i = 0; i < nrem; ++i) {
+            a.left[c * a.Q + i] = rem[i];
+            a.rem[c * a.Q + i] = rem[i];
+        }
         int KD = 0, KP = 0;
         if (a.prm.tuple_budget > 0) {
             long long tc = (long long)a.prm.tuple_budget / ((long long)nrem * (nrem + 1) / 2);
@@ -550,6 +616,175 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
         a.KD[c] = KD;
         a.KP[c] = KP;
         a.rstate[c] = nrem > 0 ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------------------- features
+// Per-customer features of the learned destroy proposal (the feature list is
+// in vrprpd.h).  Every feature is one correctly rounded fp32 division of two
+// integers converted once to fp32, then rounded to bfloat16.
+__device__ __forceinline__ float fdiv(long long a, long long b) { return __fdiv_rn((float)a, (float)b); }
+
+// Block per chain, once: dbar and the two static features of every customer
+// (distance to the nearest other node, mean of the four nearest).
+template <typename DT>
+__global__ __launch_bounds__(256) void k_static(AlnsDev a)
+{
+    const int c = blockIdx.x;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    __shared__ long long part[256];
+    long long sum = 0;
+    for (int x = 1 + threadIdx.x; x <= n; x += blockDim.x) sum += (long long)D[x];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+        const long long db = t / n;
+        part[0] = db > 1 ? db : 1;
+        a.dbar[c] = (int32_t)part[0];
+    }
+    __syncthreads();
+    const long long db = part[0];
+    for (int cust = 1 + threadIdx.x; cust <= n; cust += blockDim.x) {
+        long long best[4] = {LLONG_MAX, LLONG_MAX, LLONG_MAX, LLONG_MAX};
+        for (int j = 0; j <= n; ++j) {
+            if (j == cust) continue;
+            long long v = (long long)D[(int64_t)cust * N1 + j];
+            for (int r = 0; r < 4; ++r) {
+                if (v < best[r]) {
+                    const long long t = best[r];
+                    best[r] = v;
+                    v = t;
+                }
+            }
+        }
+        const int cnt = n < 4 ? n : 4;    // n other nodes (the depot included)
+        long long s4 = 0;
+        for (int r = 0; r < cnt; ++r) s4 += best[r];
+        float* f = a.fstat + ((int64_t)c * (a.N + 1) + cust) * 2;
+        f[0] = fdiv(best[0], db);
+        f[1] = fdiv(s4, (long long)cnt * db);
+    }
+}
+
+// Block per chain: the schedule of S (one recorded sweep), then one thread
+// per customer.
+template <typename DT>
+__global__ __launch_bounds__(256) void k_features(AlnsDev a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1, k = I.k;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    Carve cv{smem};
+    int* times = cv.take<int>(2 * a.N + kAlnsStep);
+    int* walk = cv.take<int>(2 * a.N + kAlnsStep);
+    int* pblk = cv.take<int>(a.N + 1);
+    uint16_t* posD = cv.take<uint16_t>(a.N + 2);
+    uint16_t* posP = cv.take<uint16_t>(a.N + 2);
+    int* rs = cv.take<int>(kMaxM);
+    int* re = cv.take<int>(kMaxM);
+    int* fin = cv.take<int>(kMaxM);
+    int* ready = cv.take<int>(a.N + 1);
+    unsigned char* ops_base = cv.take<unsigned char>((size_t)OpStore<DT>::kBytesPerOp * (2 * a.N + kAlnsStep));
+    OpStore<DT> S;
+    S.init(ops_base, 2 * a.N + kAlnsStep);
+    const int L = stage_solution(S, a.S_ops + (int64_t)c * 2 * a.N, a.S_rt + (int64_t)c * a.M, m, D, N1, rs, re);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const uint32_t cd = S.code(j);
+        if (cd & 1u) posP[cd >> 1] = (uint16_t)j;
+        else posD[cd >> 1] = (uint16_t)j;
+    }
+    for (int x = threadIdx.x; x <= n; x += blockDim.x) {
+        pblk[x] = x ? P[x] : 0;
+        ready[x] = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int ret;
+        const auto R = del_route<DT, true>(S, rs, re, threadIdx.x, m, posD, posP, 0, D, N1, times, ret);
+        (void)sweep_route<kAlnsStep, 64>(R, ready, pblk, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int v = threadIdx.x;
+        int w = 0;
+        for (int j = rs[v]; j < re[v]; ++j) {
+            w += (S.code(j) & 1u) ? -1 : 1;
+            walk[j] = w;
+        }
+        fin[v] = re[v] > rs[v] ? times[re[v] - 1] + (int)D[(int)(S.code(re[v] - 1) >> 1) * N1] : 0;
+    }
+    __syncthreads();
+    const long long z = a.z[c];
+    const long long db = a.dbar[c];
+    uint16_t* out = a.feat + (int64_t)c * a.N * 64;
+    for (int cust = 1 + threadIdx.x; cust <= n; cust += blockDim.x) {
+        const int jD = posD[cust], jP = posP[cust];
+        int vD = 0, vP = 0;
+        while (vD < m - 1 && jD >= re[vD]) ++vD;
+        while (vP < m - 1 && jP >= re[vP]) ++vP;
+        const int sD = rs[vD], sP = rs[vP];
+        const int LD = re[vD] - sD, LP = re[vP] - sP;
+        const int iD = jD - sD, iP = jP - sP;
+        const int prevD = iD > 0 ? (int)(S.code(jD - 1) >> 1) : 0;
+        const int nextD = iD + 1 < LD ? (int)(S.code(jD + 1) >> 1) : 0;
+        const int prevP = iP > 0 ? (int)(S.code(jP - 1) >> 1) : 0;
+        const int nextP = iP + 1 < LP ? (int)(S.code(jP + 1) >> 1) : 0;
+        const long long tD = times[jD], tP = times[jP];
+        const long long aP = (iP > 0 ? (long long)times[jP - 1] : 0) + (long long)D[prevP * N1 + cust];
+        const long long fD = fin[vD], fP = fin[vP];
+        const long long pc = P[cust];
+        const long long g = a.gains[(int64_t)c * (a.N + 1) + cust];
+        const bool same = vD == vP;
+        const long long dpc_D = D[prevD * N1 + cust], dcn_D = D[cust * N1 + nextD];
+        const long long dpc_P = D[prevP * N1 + cust], dcn_P = D[cust * N1 + nextP];
+        float b[32];
+        b[0] = 1.f;
+        b[1] = fdiv(D[cust], db);
+        b[2] = fdiv(pc, db);
+        b[3] = fdiv(tD, z);
+        b[4] = fdiv(tP, z);
+        b[5] = fdiv(tP - tD - pc, z);
+        b[6] = fdiv(tP - aP, z);
+        b[7] = same ? 1.f : 0.f;
+        b[8] = fdiv(iD, LD);
+        b[9] = fdiv(iP, LP);
+        b[10] = fdiv(fD, z);
+        b[11] = fdiv(fP, z);
+        b[12] = fD == z ? 1.f : 0.f;
+        b[13] = fP == z ? 1.f : 0.f;
+        b[14] = fdiv(dpc_D + dcn_D - (long long)D[prevD * N1 + nextD], db);
+        b[15] = fdiv(dpc_P + dcn_P - (long long)D[prevP * N1 + nextP], db);
+        b[16] = fdiv(dpc_D, db);
+        b[17] = fdiv(dcn_D, db);
+        b[18] = fdiv(dpc_P, db);
+        b[19] = fdiv(dcn_P, db);
+        b[20] = fdiv(g, z);
+        b[21] = fdiv(walk[jD], k);
+        b[22] = fdiv(walk[jP], k);
+        b[23] = fdiv((long long)LD * m, 2LL * n);
+        b[24] = fdiv((long long)LP * m, 2LL * n);
+        b[25] = same ? fdiv(iP - iD, LD) : 0.f;
+        const float* fs = a.fstat + ((int64_t)c * (a.N + 1) + cust) * 2;
+        b[26] = fs[0];
+        b[27] = fs[1];
+        b[28] = fdiv(z - fD, z);
+        b[29] = fdiv(z - fP, z);
+        b[30] = g > 0 ? 1.f : 0.f;
+        b[31] = tP > tD ? fdiv(pc, tP - tD) : 1.f;
+        const float gate = (fD == z || fP == z) ? 1.f : 0.f;
+        uint16_t* row = out + (int64_t)(cust - 1) * 64;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            row[i] = f2bf(b[i]);
+            row[32 + i] = f2bf(b[i] * gate);
+        }
     }
 }
 
@@ -808,10 +1043,12 @@ __global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t 
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int m = I.m;
     __shared__ int copyS, copyB;
+    __shared__ int64_t rec_slot;
     if (threadIdx.x == 0) {
         const alns_params& P = a.prm;
         const int di = a.di[c], ri = a.ri[c];
         const bool ok = a.rstate[c] == 1;
+        const int z_before = a.z[c];
         const int zn = ok ? a.zn[c] : INT32_MAX;
         int accepted = 0;
         copyS = copyB = 0;
@@ -869,6 +1106,16 @@ __global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t 
                 a.aR[k] = 0;
             }
         }
+        rec_slot = -1;
+        if (a.rec_x) {
+            const int64_t slot = ((int64_t)it - a.rec_base) * a.C + c;
+            if (slot >= 0 && slot < a.rec_cap) {
+                rec_slot = slot;
+                const int nr = ok ? a.nrem[c] : 0;
+                a.rec_n[slot] = nr;
+                a.rec_t[slot] = ok ? (float)(((double)zn - (double)z_before) / (double)z_before) : 0.f;
+            }
+        }
         if (a.trace && trace_it >= 0 && trace_it < a.trace_cap) {
             int64_t* tr = a.trace + ((int64_t)c * a.trace_cap + trace_it) * 4;
             tr[0] = zn;
@@ -878,6 +1125,15 @@ __global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t 
         }
     }
     __syncthreads();
+    if (rec_slot >= 0) {
+        // the removed customers' feature rows, as they were before the destroy
+        const int nr = a.rec_n[rec_slot];
+        uint16_t* dst = a.rec_x + rec_slot * a.Q * 64;
+        for (int e = threadIdx.x; e < nr * 64; e += blockDim.x) {
+            const int cust = a.rem[c * a.Q + e / 64];
+            dst[e] = a.feat[((int64_t)c * a.N + cust - 1) * 64 + (e & 63)];
+        }
+    }
     if (copyS || copyB) {
         const int wb = a.W_cur[c];
         const uint16_t* wops = a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N;
@@ -930,6 +1186,60 @@ __global__ __launch_bounds__(256) void k_import(AlnsDev a, int cpi)
     }
 }
 
+// ---------------------------------------------------------------- records
+constexpr uint32_t kTagBatch = 0x42544348u;
+
+__device__ __forceinline__ int64_t batch_slot(uint64_t seed, int i, int64_t count)
+{
+    const uint64_t w = ((uint64_t)philox_word(seed, (uint32_t)i, 1, 0, kTagBatch) << 32) |
+                       philox_word(seed, (uint32_t)i, 0, 0, kTagBatch);
+    return (int64_t)(w % (uint64_t)count);
+}
+
+// One block: set i of the batch is record slot batch_slot(i) (uniform, with
+// replacement); its rows start at seg_off[i].
+__global__ __launch_bounds__(1024) void k_batch_index(AlnsDev a, int S, uint64_t seed, int64_t count, int64_t* seg_off,
+                                                      float* target)
+{
+    __shared__ int64_t carry;
+    __shared__ int64_t part[1024];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < S; base += 1024) {
+        const int i = base + threadIdx.x;
+        int64_t nr = 0;
+        if (i < S) {
+            const int64_t slot = batch_slot(seed, i, count);
+            nr = a.rec_n[slot];
+            target[i] = a.rec_t[slot];
+        }
+        part[threadIdx.x] = nr;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (i < S) seg_off[i] = carry + part[threadIdx.x] - nr;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) seg_off[S] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_batch_rows(AlnsDev a, uint64_t seed, int64_t count, const int64_t* seg_off,
+                                                   uint16_t* x)
+{
+    const int i = blockIdx.x;
+    const int64_t slot = batch_slot(seed, i, count);
+    const int64_t r0 = seg_off[i];
+    const int nr = (int)(seg_off[i + 1] - r0);
+    const uint16_t* src = a.rec_x + slot * a.Q * 64;
+    for (int e = threadIdx.x; e < nr * 64; e += blockDim.x) x[r0 * 64 + e] = src[e];
+}
+
 }  // namespace vrprpd
 
 // ============================================================== host side
@@ -942,7 +1252,10 @@ struct alns_state {
     int dist16 = 1;
     std::vector<void*> allocs;
     int64_t trace_base = 0;            // iteration of trace row 0
-    int lds_gain = 0, lds_destroy = 0, lds_enum = 0;
+    int lds_gain = 0, lds_destroy = 0, lds_enum = 0, lds_feat = 0;
+    vrprpd_mlp* mlp = nullptr;         // learned destroy proposal's network (not owned)
+    int32_t cand_cap = 1;              // candidates the cand_* buffers hold
+    std::vector<void*> rec_allocs;     // record buffers (freed when recording restarts)
 };
 
 namespace vrprpd {
@@ -1005,6 +1318,7 @@ extern "C" int alns_state_destroy(alns_state* s)
 {
     if (!s) return VRPRPD_OK;
     for (void* p : s->allocs) (void)hipFree(p);
+    for (void* p : s->rec_allocs) (void)hipFree(p);
     delete s;
     return VRPRPD_OK;
 }
@@ -1069,7 +1383,10 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     A(d.tuples, (size_t)C * Q * TPC); A(d.tmk, (size_t)C * Q * TPC); A(d.tst, (size_t)C * Q * TPC);
     A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
     A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C); A(d.evals, 1);
+    A(d.cand_rem, (size_t)C * Q); A(d.cand_cnt, C); A(d.chosen, C);
 #undef A
+    d.K = 1;
+    d.eps = 1.0;
     if (rc != VRPRPD_OK) {
         alns_state_destroy(s);
         return rc;
@@ -1180,8 +1497,20 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
         t.take<unsigned char>(bpo * (2 * N + kAlnsStep));
         s->lds_destroy = (int)t.bytes;
         s->lds_enum = 2 * 8 * pow2_ge(2 * N + M + 1);
+        LdsSize f;
+        f.take<int>(2 * N + kAlnsStep);
+        f.take<int>(2 * N + kAlnsStep);
+        f.take<int>(N + 1);
+        f.take<uint16_t>(N + 2);
+        f.take<uint16_t>(N + 2);
+        f.take<int>(kMaxM);
+        f.take<int>(kMaxM);
+        f.take<int>(kMaxM);
+        f.take<int>(N + 1);
+        f.take<unsigned char>(bpo * (2 * N + kAlnsStep));
+        s->lds_feat = (int)f.bytes;
     }
-    if ((size_t)std::max(s->lds_gain, std::max(s->lds_destroy, s->lds_enum)) > kLdsPerCu) {
+    if ((size_t)std::max(std::max(s->lds_gain, s->lds_feat), std::max(s->lds_destroy, s->lds_enum)) > kLdsPerCu) {
         alns_state_destroy(s);
         return set_error(VRPRPD_EINVAL, "alns_state_create: n = %d needs too much LDS", N);
     }
@@ -1220,14 +1549,29 @@ static int one_iteration(alns_state* s, hipStream_t st)
     else if (d.M <= 32) rc = launch_gains<DT, 32>(s, st);
     else rc = launch_gains<DT, 64>(s, st);
     if (rc) return rc;
+    if (d.learn_on) {
+        auto* kf = k_features<DT>;
+        if (s->lds_feat > 64 * 1024)
+            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kf),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_feat));
+        hipLaunchKernelGGL(kf, dim3(d.C), dim3(256), s->lds_feat, st, d);
+        VRP_HIP(hipGetLastError());
+    }
     {
         auto* k = k_destroy<DT>;
         if (s->lds_destroy > 64 * 1024)
             VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_destroy));
-        hipLaunchKernelGGL(k, dim3(d.C), dim3(256), s->lds_destroy, st, d, it);
+        hipLaunchKernelGGL(k, dim3(d.C, d.K), dim3(256), s->lds_destroy, st, d, it);
         VRP_HIP(hipGetLastError());
     }
+    const int use_scores = (s->mlp && d.K > 1) ? 1 : 0;
+    if (use_scores) {
+        rc = vrprpd_mlp_forward(s->mlp, (int64_t)d.C * d.N, d.feat, d.score, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_apply<DT>, dim3(d.C), dim3(256), d.N + 1, st, d, it, use_scores);
+    VRP_HIP(hipGetLastError());
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
                 d.C * d.Q, std::max(1, (d.TPC + 63) / 64)};
@@ -1312,5 +1656,137 @@ extern "C" int alns_get_state(const alns_state* s, int64_t* iterations, int64_t*
     if (T) VRP_HIP(hipMemcpy(T, s->d.T, C * sizeof(double), hipMemcpyDeviceToHost));
     if (wD) VRP_HIP(hipMemcpy(wD, s->d.wD, (size_t)kND * C * sizeof(double), hipMemcpyDeviceToHost));
     if (wR) VRP_HIP(hipMemcpy(wR, s->d.wR, (size_t)kNR * C * sizeof(double), hipMemcpyDeviceToHost));
+    return VRPRPD_OK;
+}
+
+// ---------------------------------------------------------------- learned proposal
+static int ensure_features(alns_state* s, hipStream_t st)
+{
+    using namespace vrprpd;
+    AlnsDev& d = s->d;
+    if (d.feat) return VRPRPD_OK;
+    int rc = VRPRPD_OK;
+    if ((rc = alloc_n(s, &d.feat, (size_t)d.C * d.N * 64)) || (rc = alloc_n(s, &d.fstat, (size_t)d.C * (d.N + 1) * 2)) ||
+        (rc = alloc_n(s, &d.dbar, d.C)) || (rc = alloc_n(s, &d.score, (size_t)d.C * d.N)))
+        return rc;
+    if (s->dist16)
+        hipLaunchKernelGGL(k_static<uint16_t>, dim3(d.C), dim3(256), 0, st, d);
+    else
+        hipLaunchKernelGGL(k_static<int32_t>, dim3(d.C), dim3(256), 0, st, d);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_set_learned(alns_state* s, vrprpd_mlp* mlp, int32_t K, double eps, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || K < 1 || K > 64 || !(eps >= 0.0 && eps <= 1.0))
+        return set_error(VRPRPD_EINVAL, "alns_set_learned: need 1 <= K <= 64 and 0 <= eps <= 1");
+    AlnsDev& d = s->d;
+    if (mlp && mlp_max_rows(mlp) < (int64_t)d.C * d.N)
+        return set_error(VRPRPD_EINVAL, "alns_set_learned: the network scores %lld rows at once, %d chains x n = %d "
+                                        "need %lld", (long long)mlp_max_rows(mlp), d.C, d.N, (long long)d.C * d.N);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!mlp) K = 1;
+    if (K > s->cand_cap) {
+        int rc;
+        if ((rc = alloc_n(s, &d.cand_rem, (size_t)d.C * K * d.Q)) || (rc = alloc_n(s, &d.cand_cnt, (size_t)d.C * K)))
+            return rc;
+        s->cand_cap = K;
+    }
+    if (mlp) {
+        const int rc = ensure_features(s, st);
+        if (rc) return rc;
+    }
+    s->mlp = mlp;
+    d.K = K;
+    d.eps = eps;
+    d.learn_on = (mlp != nullptr || d.rec_x != nullptr) ? 1 : 0;
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_record(alns_state* s, int64_t capacity, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || capacity < 0) return set_error(VRPRPD_EINVAL, "alns_record: bad arguments");
+    AlnsDev& d = s->d;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    VRP_HIP(hipStreamSynchronize(st));
+    for (void* p : s->rec_allocs) (void)hipFree(p);
+    s->rec_allocs.clear();
+    d.rec_x = nullptr;
+    d.rec_t = nullptr;
+    d.rec_n = nullptr;
+    d.rec_cap = 0;
+    if (capacity > 0) {
+        int rc = ensure_features(s, st);
+        if (rc) return rc;
+        const size_t bytes[3] = {(size_t)capacity * d.Q * 64 * sizeof(uint16_t), (size_t)capacity * sizeof(float),
+                                 (size_t)capacity * sizeof(int32_t)};
+        void* p[3] = {nullptr, nullptr, nullptr};
+        for (int i = 0; i < 3; ++i) {
+            hipError_t e = hipMalloc(&p[i], bytes[i]);
+            if (e != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+                return set_error(VRPRPD_ENOMEM, "alns_record: %lld sets do not fit (%s)", (long long)capacity,
+                                 hipGetErrorString(e));
+            }
+            s->rec_allocs.push_back(p[i]);
+        }
+        d.rec_x = static_cast<uint16_t*>(p[0]);
+        d.rec_t = static_cast<float*>(p[1]);
+        d.rec_n = static_cast<int32_t*>(p[2]);
+        d.rec_cap = capacity;
+        d.rec_base = s->it;
+    }
+    d.learn_on = (s->mlp != nullptr || d.rec_x != nullptr) ? 1 : 0;
+    return VRPRPD_OK;
+}
+
+static int64_t record_count(const alns_state* s)
+{
+    if (!s->d.rec_x) return 0;
+    const int64_t done = (s->it - s->d.rec_base) * s->d.C;
+    return done < s->d.rec_cap ? done : s->d.rec_cap;
+}
+
+extern "C" int alns_record_info(const alns_state* s, int64_t* sets, int32_t* q_max)
+{
+    if (!s) return vrprpd::set_error(VRPRPD_EINVAL, "alns_record_info: state is NULL");
+    if (sets) *sets = record_count(s);
+    if (q_max) *q_max = s->d.Q;
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_record_batch(const alns_state* s, int32_t num_sets, uint64_t seed, uint16_t* x, int64_t* seg_off,
+                                 float* target, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || num_sets < 1 || !x || !seg_off || !target)
+        return set_error(VRPRPD_EINVAL, "alns_record_batch: bad arguments");
+    const int64_t count = record_count(s);
+    if (count < 1) return set_error(VRPRPD_EINVAL, "alns_record_batch: nothing recorded yet");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_batch_index, dim3(1), dim3(1024), 0, st, s->d, num_sets, seed, count, seg_off, target);
+    hipLaunchKernelGGL(k_batch_rows, dim3(num_sets), dim3(256), 0, st, s->d, seed, count, seg_off, x);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_get_learned(const alns_state* s, uint16_t* feat, int32_t* cand_rem, int32_t* cand_cnt,
+                                int32_t* chosen, void* stream)
+{
+    using namespace vrprpd;
+    if (!s) return set_error(VRPRPD_EINVAL, "alns_get_learned: state is NULL");
+    const AlnsDev& d = s->d;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (feat) {
+        if (!d.feat) return set_error(VRPRPD_EINVAL, "alns_get_learned: features are off");
+        VRP_HIP(hipMemcpyAsync(feat, d.feat, (size_t)d.C * d.N * 64 * 2, hipMemcpyDeviceToDevice, st));
+    }
+    if (cand_rem)
+        VRP_HIP(hipMemcpyAsync(cand_rem, d.cand_rem, (size_t)d.C * d.K * d.Q * 4, hipMemcpyDeviceToDevice, st));
+    if (cand_cnt) VRP_HIP(hipMemcpyAsync(cand_cnt, d.cand_cnt, (size_t)d.C * d.K * 4, hipMemcpyDeviceToDevice, st));
+    if (chosen) VRP_HIP(hipMemcpyAsync(chosen, d.chosen, (size_t)d.C * 4, hipMemcpyDeviceToDevice, st));
     return VRPRPD_OK;
 }

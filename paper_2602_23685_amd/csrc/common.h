@@ -28,6 +28,7 @@ struct InstDev {
 // Records a message for vrprpd_last_error() and returns code.
 int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
+int64_t mlp_max_rows(const vrprpd_mlp* h);   // rows a network handle can score at once
 
 #define VRP_HIP(call)                                                      \
     do {                                                                   \
@@ -45,6 +46,24 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     const int x = b % kXcds, i = b / kXcds;
     return x * q + (x < r ? x : r) + i;
 }
+
+// p[i] for 0 <= i with i * sizeof(T) < 2^32: the byte offset is formed in 32
+// bits so that a wave-uniform p becomes the scalar base of the load.
+template <typename T>
+__device__ __forceinline__ T ld_elem(const T* p, int i)
+{
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+}
+
+// fp32 -> bfloat16 bits, round to nearest even (finite inputs).
+__host__ __device__ __forceinline__ uint16_t f2bf(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // Cross-lane helpers over groups of GL consecutive lanes of a wavefront.
 template <int GL>

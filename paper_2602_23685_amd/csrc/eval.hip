@@ -51,23 +51,34 @@ __host__ __device__ inline GroupLayout group_layout(int n_max, int bytes_per_op)
     return g;
 }
 
-// Records one op code of the staged candidate: its cover bit (a second copy
-// of an op sets `bad`) and its LDS slot.  Branch-free so that a lane's eight
-// codes issue eight LDS atomics back to back.
-template <typename DT>
-__device__ __forceinline__ void stage_code(OpStore<DT>& S, uint32_t* bits, int j, uint32_t cd, int n, bool& bad,
-                                           uint32_t& old, uint32_t& mask)
+// Stages op j of the candidate: marks its cover bit (a second copy of an op
+// sets `dup`, a code outside [1, n] sets `bad`) and stores its code with the
+// travel time from the previous op of the flat list (pc; route starts are
+// re-pointed at the depot afterwards).  Branch-free so that many ops' LDS
+// atomics and distance gathers issue back to back.
+struct Staged {
+    uint32_t cd;
+    int idx;
+};
+
+// `live` false stages nothing (a clamped duplicate load): no cover bit, no flag.
+__device__ __forceinline__ Staged stage_code(uint32_t* bits, uint32_t cd, uint32_t pc, int n, int N1, bool live,
+                                            bool& bad)
 {
     const int c = (int)(cd >> 1);
     const bool ok = c >= 1 && c <= n;
-    bad = bad || !ok;
     const int bitpos = ok ? 2 * c + (int)(cd & 1u) : 0;
-    mask = ok ? 1u << (bitpos & 31) : 0u;
-    old = atomicOr(&bits[bitpos >> 5], mask);
-    S.set_code(j, ok ? cd : 0u);
+    const uint32_t mask = (ok && live) ? 1u << (bitpos & 31) : 0u;
+    const uint32_t old = atomicOr(&bits[bitpos >> 5], mask);
+    bad = bad || (live && (!ok || (old & mask)));
+    int p = (int)(pc >> 1);
+    p = p <= n ? p : 0;
+    return Staged{ok ? cd : 0u, p * N1 + (ok ? c : 0)};
 }
 
-template <typename DT, int GL, int WPB, int K>
+// kOneInst: every candidate uses instance 0 (no instance array), so the
+// instance's distance and processing rows are wave-uniform (scalar bases).
+template <typename DT, int GL, int WPB, int K, bool kOneInst>
 __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -85,7 +96,7 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     OpStore<DT> S;
     S.init(gs + L.ops_off, op_capacity(a.n_max));
 
-    int ii = (live && a.inst) ? a.inst[b] : 0;
+    int ii = (!kOneInst && live && a.inst) ? a.inst[b] : 0;
     const bool bad_inst = ii < 0 || ii >= a.num_inst;
     if (bad_inst) ii = 0;
     const InstDev I = a.inst_tab[ii];
@@ -106,65 +117,91 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     if (total > 2 * n) bad = true;
     bool gbad = !live || group_ballot<GL>(bad) != 0;
 
-    // ---- phase 1a: stream the ops in (16-byte loads), check cover ----------
+    // ---- phase 1: stage ready[], the ops and every travel time -----------
     const int nwords = (2 * N1 + 31) / 32;
     for (int w = li; w < nwords; w += GL) bits[w] = 0u;
     wave_lds_fence();
     bool cbad = false;
     if (!gbad) {
+        // ready[c] = ~p_c ("not dropped yet"; the drop reads p_c back from
+        // it).  The p row is 16-byte aligned and padded: int4 loads, all of a
+        // lane's in flight together (clamped, not predicated).
+        {
+            const int4* P4 = reinterpret_cast<const int4*>(P);
+            int4* R4 = reinterpret_cast<int4*>(ready);
+            const int np4 = (N1 + 3) >> 2;
+            constexpr int VP = 8;
+            for (int q0 = li; q0 < np4; q0 += VP * GL) {
+                int4 x[VP];
+#pragma unroll
+                for (int v = 0; v < VP; ++v) {
+                    const int q = q0 + v * GL;
+                    x[v] = P4[q < np4 ? q : np4 - 1];
+                }
+#pragma unroll
+                for (int v = 0; v < VP; ++v) {
+                    const int q = q0 + v * GL;
+                    if (q < np4) R4[q] = make_int4(~x[v].x, ~x[v].y, ~x[v].z, ~x[v].w);
+                }
+            }
+        }
+        // Ops: 16-byte vectors of 8 codes from HBM (plus the code before each
+        // vector, an L1/L2 hit), then all their distance gathers at once.
         int head = (int)((8 - (((uintptr_t)ops >> 1) & 7)) & 7);
         head = head < total ? head : total;
-        for (int j = li; j < head; j += GL) {
-            uint32_t old, mask;
-            stage_code(S, bits, j, ops[j], n, cbad, old, mask);
-            cbad = cbad || (old & mask);
-        }
         const int nvec = (total - head) >> 3;
+        const int tail0 = head + 8 * nvec;
+        const int nscalar = head + (total - tail0);
+        for (int t = li; t < nscalar; t += GL) {
+            const int j = t < head ? t : tail0 + (t - head);
+            const uint32_t cd = ops[j];
+            const uint32_t pt = ops[j > 0 ? j - 1 : 0];
+            const Staged g = stage_code(bits, cd, j > 0 ? pt : 0u, n, N1, true, cbad);
+            S.set(j, g.cd, (int)ld_elem(D, g.idx));
+        }
         const uint4* vec = reinterpret_cast<const uint4*>(ops + head);
-        constexpr int V = 4;   // 16-byte loads in flight per lane
+        constexpr int V = 4;   // vectors per lane per batch: 32 gathers in flight
         for (int q0 = li; q0 < nvec; q0 += V * GL) {
             uint4 x[V];
+            uint32_t pv[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                int q = q0 + v * GL;
+                q = q < nvec ? q : nvec - 1;
+                x[v] = vec[q];
+                const int j = head + 8 * q;
+                const uint32_t pt = ops[j > 0 ? j - 1 : 0];
+                pv[v] = j > 0 ? pt : 0u;
+            }
+            int idx[V][8];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int q = q0 + v * GL;
-                x[v] = vec[q < nvec ? q : nvec - 1];
+                const bool in = q < nvec;
+                const uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
+                uint32_t prev = pv[v];
+#pragma unroll
+                for (int h = 0; h < 8; ++h) {
+                    const uint32_t cd = (w4[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+                    const Staged g = stage_code(bits, cd, prev, n, N1, in, cbad);
+                    if (in) S.put_code(head + 8 * q + h, g.cd);
+                    idx[v][h] = g.idx;
+                    prev = cd;
+                }
             }
+            int lg[V][8];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int h = 0; h < 8; ++h) lg[v][h] = (int)ld_elem(D, idx[v][h]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int q = q0 + v * GL;
                 if (q < nvec) {
                     const int j = head + 8 * q;
-                    const uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
-                    uint32_t old[8], mask[8];
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        stage_code(S, bits, j + 2 * h, w4[h] & 0xFFFFu, n, cbad, old[2 * h], mask[2 * h]);
-                        stage_code(S, bits, j + 2 * h + 1, w4[h] >> 16, n, cbad, old[2 * h + 1], mask[2 * h + 1]);
-                    }
-#pragma unroll
-                    for (int h = 0; h < 8; ++h) cbad = cbad || (old[h] & mask[h]);
+                    for (int h = 0; h < 8; ++h) S.put_leg(j + h, lg[v][h]);
                 }
-            }
-        }
-        for (int j = head + 8 * nvec + li; j < total; j += GL) {
-            uint32_t old, mask;
-            stage_code(S, bits, j, ops[j], n, cbad, old, mask);
-            cbad = cbad || (old & mask);
-        }
-        // ready[c] = ~p_c ("not dropped yet"; the drop reads p_c back from it)
-        // (loads clamped to p_n rather than predicated, so all eight issue
-        // back to back instead of one branch and one wait each)
-        for (int c0 = li; c0 <= n; c0 += 8 * GL) {
-            int pv[8];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const int c = c0 + v * GL;
-                pv[v] = P[c <= n ? c : n];
-            }
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const int c = c0 + v * GL;
-                if (c <= n) ready[c] = ~pv[v];
             }
         }
     }
@@ -174,38 +211,11 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
             const uint32_t two = (bits[(2 * c) >> 5] >> ((2 * c) & 31)) & 3u;
             if (!(two == 3u || (two == 0u && a.partial))) cbad = true;
         }
-    }
-    gbad = gbad || group_ballot<GL>(cbad) != 0;
-
-    // ---- phase 1b: every travel time d[prev][c], gathered in batches so ---
-    // that many loads are in flight per lane.  Legs first assume the previous
-    // op of the flat list is the previous stop; the first op of each route is
-    // then re-pointed at the depot.
-    if (!gbad) {
-        constexpr int U = 16;
-        for (int j0 = li; j0 < total; j0 += U * GL) {
-            int idx[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * GL;
-                const int jj = j < total ? j : 0;
-                const int c = (int)(S.code(jj) >> 1);
-                const int pc = jj > 0 ? (int)(S.code(jj - 1) >> 1) : 0;
-                idx[u] = pc * N1 + c;
-            }
-            int lg[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) lg[u] = (int)D[idx[u]];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * GL;
-                if (j < total) S.set_leg(j, lg[u]);
-            }
-        }
-        wave_lds_fence();
+        // the first op of each route comes from the depot
         if (li < m && s < e) S.set_leg(s, (int)D[(int)(S.code(s) >> 1)]);
-        wave_lds_fence();
     }
+    wave_lds_fence();
+    gbad = gbad || group_ballot<GL>(cbad) != 0;
 
     // ---- phase 2: timing sweep ----------------------------------------------
     const bool veh = li < m;
@@ -253,7 +263,7 @@ static LaunchShape eval_shape(int n_max, int m_max, int dist16)
 template <typename DT, int GL, int WPB>
 static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
 {
-    auto* k = eval_kernel<DT, GL, WPB, kEvalStep>;
+    auto* k = a.inst ? eval_kernel<DT, GL, WPB, kEvalStep, false> : eval_kernel<DT, GL, WPB, kEvalStep, true>;
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));

@@ -86,7 +86,7 @@ extern "C" int vrprpd_set_create(vrprpd_set** out, int32_t num_inst, const vrprp
         InstDev& h = s->host[i];
         h = InstDev{D.n, D.m, D.k, D.R, D.load_model, 0, dsz, psz};
         dsz += N1 * N1;
-        psz += N1;
+        psz += (N1 + 3) & ~int64_t(3);   // 16-byte aligned rows: kernels read p in int4 vectors
         if (D.n > s->n_max) s->n_max = D.n;
         if (D.m > s->m_max) s->m_max = D.m;
         if (D.n != desc[0].n || D.m != desc[0].m) s->uniform_nm = false;

@@ -33,6 +33,10 @@ struct OpStore<uint16_t> {
     __device__ __forceinline__ void set_code(int j, uint32_t cd) { w[j] = cd; }
     __device__ __forceinline__ uint32_t code(int j) const { return w[j] & 0xFFFFu; }
     __device__ __forceinline__ void set_leg(int j, int leg) { w[j] = (w[j] & 0xFFFFu) | ((uint32_t)leg << 16); }
+    __device__ __forceinline__ void set(int j, uint32_t cd, int leg) { w[j] = cd | ((uint32_t)leg << 16); }
+    // halves written separately (no read-modify-write)
+    __device__ __forceinline__ void put_code(int j, uint32_t cd) { reinterpret_cast<uint16_t*>(w)[2 * j] = (uint16_t)cd; }
+    __device__ __forceinline__ void put_leg(int j, int leg) { reinterpret_cast<uint16_t*>(w)[2 * j + 1] = (uint16_t)leg; }
     __device__ __forceinline__ void load(int j, uint32_t& cd, int& leg) const
     {
         const uint32_t x = w[j];
@@ -54,6 +58,13 @@ struct OpStore<int32_t> {
     __device__ __forceinline__ void set_code(int j, uint32_t cd) { c[j] = (uint16_t)cd; }
     __device__ __forceinline__ uint32_t code(int j) const { return c[j]; }
     __device__ __forceinline__ void set_leg(int j, int leg) { l[j] = leg; }
+    __device__ __forceinline__ void set(int j, uint32_t cd, int leg)
+    {
+        c[j] = (uint16_t)cd;
+        l[j] = leg;
+    }
+    __device__ __forceinline__ void put_code(int j, uint32_t cd) { c[j] = (uint16_t)cd; }
+    __device__ __forceinline__ void put_leg(int j, int leg) { l[j] = leg; }
     __device__ __forceinline__ void load(int j, uint32_t& cd, int& leg) const
     {
         cd = c[j];
