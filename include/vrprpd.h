@@ -256,6 +256,33 @@ int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint16_t* ops, c
                      int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed, int64_t key_stride,
                      float* prio_out, float* hint_out, void* stream);
 
+/*
+ * brkga_state — many instances' BRKGA populations evolved together (the
+ * batched form): each generation decodes and evaluates every individual of
+ * every population in one brkga_decode_eval launch, then ranks, keeps each
+ * population's best and evolves every population in one launch each, all
+ * captured once as a HIP graph per population buffer and replayed
+ * (use_graph = 1) or launched directly (0, same results).  Population p (of
+ * instance inst_ids[p]) is Np individuals of 2 n_p priorities and hints at
+ * key_stride = 2 n_max, seeded pop_seed = seed + 0x9E3779B97F4A7C15 * p
+ * (mod 2^64); generation g of population p equals brkga_evolve with that
+ * seed and generation g.  The set's largest instance must be among
+ * inst_ids.  prio0 / hint0 (device [n_inst * Np][2 n_max]) give the initial
+ * populations, or NULL for U(0,1) genes (Philox, counter (gene / 4,
+ * individual, 0, 'RAND'), key pop_seed).
+ */
+typedef struct brkga_state brkga_state;
+int brkga_state_create(brkga_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
+                       int32_t Np, int32_t n_elite, int32_t n_mutant, double rho_e, uint64_t seed,
+                       const float* prio0, const float* hint0, void* stream);
+int brkga_state_step(brkga_state* st, int32_t generations, int32_t use_graph, void* stream);
+/* Generations done (host), best fitness per population so far (host
+ * [n_inst], synchronises), the best chromosomes (device [n_inst][2 n_max])
+ * and the current populations (device); any pointer may be NULL. */
+int brkga_state_get(const brkga_state* st, int64_t* generations, int64_t* best_fitness, float* best_prio,
+                    float* best_hint, float* prio, float* hint, void* stream);
+int brkga_state_destroy(brkga_state* st);
+
 /* ---- ALNS (Section 4.2) ----------------------------------------------------
  * alns_params: the hyper-parameters of Table 2 (Section 4.2.6) plus this
  * library's repair budget.  Defaults: T0 = 0.30, alpha = 0.9998, reheat =
@@ -304,8 +331,14 @@ typedef struct alns_state alns_state;
 int alns_state_create(alns_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
                       int32_t chains_per_inst, const alns_params* params, uint64_t seed,
                       const uint16_t* init_ops, const uint16_t* init_rt, void* stream);
-/* Runs `iterations` more iterations of every chain (asynchronous on stream). */
+/* Runs `iterations` more iterations of every chain (asynchronous on stream).
+ * By default the launches of one iteration are captured once into a HIP
+ * graph (on a stream of the state's own) and the graph is replayed per
+ * iteration; the iteration number lives in device memory.  The capture is
+ * redone after alns_set_trace, alns_set_learned or alns_record. */
 int alns_step(alns_state* st, int32_t iterations, void* stream);
+/* enable = 0: launch every kernel of every iteration instead (same results). */
+int alns_set_graph(alns_state* st, int32_t enable);
 /* Records (candidate makespan, current z, best z, destroy | repair << 8 |
  * outcome << 16 | removed << 24) of every chain for the next `capacity`
  * iterations into trace [chains][capacity][4] int64 (device), or stops

@@ -55,6 +55,12 @@ SIGNATURES = {
     "alns_get_best": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
     "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "alns_state_destroy": (C.c_int, [_P]),
+    "brkga_state_create": (C.c_int, [C.POINTER(C.c_void_p), _P, _I32, _P, _I32, _I32, _I32, C.c_double, _U64,
+                                     _P, _P, _P]),
+    "brkga_state_step": (C.c_int, [_P, _I32, _I32, _P]),
+    "brkga_state_get": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_state_destroy": (C.c_int, [_P]),
+    "alns_set_graph": (C.c_int, [_P, _I32]),
     "alns_set_learned": (C.c_int, [_P, _P, _I32, C.c_double, _P]),
     "alns_record": (C.c_int, [_P, _I64, _P]),
     "alns_record_info": (C.c_int, [_P, _P, _P]),
@@ -257,6 +263,54 @@ def brkga_warm_start(S: InstanceSet, ops, rt_end, Np, n_warm, n_variants, seed, 
     return po, ho
 
 
+class BrkgaState:
+    """Batched BRKGA over several instances (brkga_state_*)."""
+
+    def __init__(self, S: InstanceSet, inst_ids, Np, n_elite, n_mutant, rho_e, seed, prio0=None, hint0=None,
+                 stream=None):
+        ids = (C.c_int32 * len(inst_ids))(*inst_ids)
+        h = C.c_void_p()
+        _check(load().brkga_state_create(C.byref(h), S.handle, len(inst_ids), ids, Np, n_elite, n_mutant,
+                                         float(rho_e), seed & (2**64 - 1), _dptr(prio0, torch.float32, "prio0"),
+                                         _dptr(hint0, torch.float32, "hint0"), _stream(stream)))
+        self.handle = h
+        self.P, self.Np, self.stride = len(inst_ids), Np, 2 * S.n_max
+
+    def step(self, generations, graph=True, stream=None):
+        _check(load().brkga_state_step(self.handle, generations, 1 if graph else 0, _stream(stream)))
+
+    def best(self, stream=None):
+        """(best fitness per population (numpy), best prio, best hint)."""
+        f = np.zeros(self.P, np.int64)
+        bp = torch.empty((self.P, self.stride), dtype=torch.float32, device="cuda")
+        bh = torch.empty_like(bp)
+        _check(load().brkga_state_get(self.handle, None, f.ctypes.data, _dptr(bp), _dptr(bh), None, None,
+                                      _stream(stream)))
+        return f, bp, bh
+
+    def population(self, stream=None):
+        p = torch.empty((self.P * self.Np, self.stride), dtype=torch.float32, device="cuda")
+        h = torch.empty_like(p)
+        _check(load().brkga_state_get(self.handle, None, None, None, None, _dptr(p), _dptr(h), _stream(stream)))
+        return p, h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().brkga_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pop_seed(seed, p):
+    """Seed of population p of a batched BRKGA run."""
+    return (seed + 0x9E3779B97F4A7C15 * p) & (2**64 - 1)
+
+
 class AlnsParams(C.Structure):
     """alns_params of vrprpd.h (Table 2 hyper-parameters plus the repair budget)."""
     _fields_ = [("T0", C.c_double), ("alpha", C.c_double), ("reheat", C.c_double), ("gate", C.c_double),
@@ -320,6 +374,11 @@ class AlnsState:
         _check(load().alns_get_state(self.handle, C.byref(it), C.byref(ev), z.ctypes.data, zb.ctypes.data,
                                      T.ctypes.data, wD.ctypes.data, wR.ctypes.data))
         return dict(iterations=it.value, evals=ev.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
+
+    def set_graph(self, enable):
+        """Replay one captured iteration (True, the default) or launch every
+        kernel of every iteration (False)."""
+        _check(load().alns_set_graph(self.handle, 1 if enable else 0))
 
     # ---- learned destroy proposal ------------------------------------------
     def set_learned(self, mlp, K=8, eps=0.1, stream=None):

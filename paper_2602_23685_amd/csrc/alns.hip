@@ -59,7 +59,8 @@ struct AlnsDev {
     int64_t *seg_off, *seg_top3;
     int64_t *base_op_off, *base_rt_off;   // [C] offsets of the current W buffers
     int64_t* trace;                // [C][trace_cap][4] or null
-    int64_t trace_cap;
+    int64_t trace_cap, trace_base; // capacity; iteration of trace row 0
+    uint32_t* it_dev;              // iteration counter (advanced by k_tick at the end of an iteration)
     unsigned long long* evals;     // exact evaluations performed (tuples and removal gains)
     // learned destroy proposal (Section 6 names learned operators as future
     // work; this library's form): K candidate removal sets per chain, scored
@@ -167,8 +168,9 @@ struct LdsSize {
 };
 
 // ---------------------------------------------------------------- begin
-__global__ void k_begin(AlnsDev a, uint32_t it)
+__global__ void k_begin(AlnsDev a)
 {
+    const uint32_t it = *a.it_dev;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
@@ -327,8 +329,9 @@ __global__ __launch_bounds__(64 * WPB) void k_gains(AlnsDev a, int per_block)
 
 // ---------------------------------------------------------------- destroy
 template <typename DT>
-__global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
+__global__ __launch_bounds__(256) void k_destroy(AlnsDev a)
 {
+    const uint32_t it = *a.it_dev;
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x;
     const int cand = blockIdx.y;                        // candidate: draws at 16 + 4096 cand + i
@@ -550,8 +553,9 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a, uint32_t it)
 // candidate 0, unless the network picked another) and builds the partial
 // solution W = S without it.
 template <typename DT>
-__global__ __launch_bounds__(256) void k_apply(AlnsDev a, uint32_t it, int use_scores)
+__global__ __launch_bounds__(256) void k_apply(AlnsDev a, int use_scores)
 {
+    const uint32_t it = *a.it_dev;
     const int c = blockIdx.x;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int m = I.m, n = I.n;
@@ -1037,8 +1041,10 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
 }
 
 // ---------------------------------------------------------------- accept
-__global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t trace_it)
+__global__ __launch_bounds__(256) void k_accept(AlnsDev a)
 {
+    const uint32_t it = *a.it_dev;
+    const int64_t trace_it = a.trace ? (int64_t)it - a.trace_base : -1;
     const int c = blockIdx.x;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int m = I.m;
@@ -1154,6 +1160,7 @@ __global__ __launch_bounds__(256) void k_accept(AlnsDev a, uint32_t it, int64_t 
 // Block per instance: chains [c0, c0 + cpi) adopt the best of them.
 __global__ __launch_bounds__(256) void k_import(AlnsDev a, int cpi)
 {
+    if (a.prm.import_interval <= 0 || (*a.it_dev + 1) % (uint32_t)a.prm.import_interval != 0) return;
     const int c0 = blockIdx.x * cpi;
     __shared__ int bc;
     if (threadIdx.x == 0) {
@@ -1240,6 +1247,12 @@ __global__ __launch_bounds__(256) void k_batch_rows(AlnsDev a, uint64_t seed, in
     for (int e = threadIdx.x; e < nr * 64; e += blockDim.x) x[r0 * 64 + e] = src[e];
 }
 
+// ---------------------------------------------------------------- tick
+__global__ void k_tick(AlnsDev a)
+{
+    if (threadIdx.x == 0) *a.it_dev += 1u;
+}
+
 }  // namespace vrprpd
 
 // ============================================================== host side
@@ -1251,14 +1264,20 @@ struct alns_state {
     int64_t it = 0;                    // iterations done
     int dist16 = 1;
     std::vector<void*> allocs;
-    int64_t trace_base = 0;            // iteration of trace row 0
     int lds_gain = 0, lds_destroy = 0, lds_enum = 0, lds_feat = 0;
     vrprpd_mlp* mlp = nullptr;         // learned destroy proposal's network (not owned)
     int32_t cand_cap = 1;              // candidates the cand_* buffers hold
     std::vector<void*> rec_allocs;     // record buffers (freed when recording restarts)
+    bool use_graph = true;             // replay a captured iteration (alns_set_graph)
+    hipStream_t cap = nullptr;         // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;    // rebuilt after any change of the launch arguments
 };
 
 namespace vrprpd {
+
+template <typename DT>
+static int set_attributes(alns_state* s);
 
 static int alloc_dev(alns_state* s, void** p, size_t bytes)
 {
@@ -1317,6 +1336,9 @@ static void qrange(const alns_params& P, int n, int* qmin, int* qmax)
 extern "C" int alns_state_destroy(alns_state* s)
 {
     if (!s) return VRPRPD_OK;
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     for (void* p : s->allocs) (void)hipFree(p);
     for (void* p : s->rec_allocs) (void)hipFree(p);
     delete s;
@@ -1383,7 +1405,7 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     A(d.tuples, (size_t)C * Q * TPC); A(d.tmk, (size_t)C * Q * TPC); A(d.tst, (size_t)C * Q * TPC);
     A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
     A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C); A(d.evals, 1);
-    A(d.cand_rem, (size_t)C * Q); A(d.cand_cnt, C); A(d.chosen, C);
+    A(d.cand_rem, (size_t)C * Q); A(d.cand_cnt, C); A(d.chosen, C); A(d.it_dev, 1);
 #undef A
     d.K = 1;
     d.eps = 1.0;
@@ -1514,6 +1536,11 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
         alns_state_destroy(s);
         return set_error(VRPRPD_EINVAL, "alns_state_create: n = %d needs too much LDS", N);
     }
+    rc = s->dist16 ? set_attributes<uint16_t>(s) : set_attributes<int32_t>(s);
+    if (rc != VRPRPD_OK) {
+        alns_state_destroy(s);
+        return rc;
+    }
     *out = s;
     return VRPRPD_OK;
 }
@@ -1521,28 +1548,46 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
 namespace vrprpd {
 
 template <typename DT, int GL>
+static const void* gains_kernel()
+{
+    return reinterpret_cast<const void*>(k_gains<DT, GL, kGainWaves>);
+}
+
+// Dynamic-LDS limits of the kernels of one iteration, set once per state
+// (never during a graph capture).
+template <typename DT>
+static int set_attributes(alns_state* s)
+{
+    const void* ks[4] = {s->d.M <= 16 ? gains_kernel<DT, 16>() : (s->d.M <= 32 ? gains_kernel<DT, 32>()
+                                                                                : gains_kernel<DT, 64>()),
+                         reinterpret_cast<const void*>(k_destroy<DT>), reinterpret_cast<const void*>(k_enum<DT>),
+                         reinterpret_cast<const void*>(k_features<DT>)};
+    const int lds[4] = {s->lds_gain, s->lds_destroy, s->lds_enum, s->lds_feat};
+    for (int i = 0; i < 4; ++i)
+        if (lds[i] > 64 * 1024) VRP_HIP(hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds[i]));
+    return VRPRPD_OK;
+}
+
+template <typename DT, int GL>
 static int launch_gains(alns_state* s, hipStream_t st)
 {
     constexpr int WPB = kGainWaves;
     constexpr int per_block = 64;
     const AlnsDev& d = s->d;
-    auto* k = k_gains<DT, GL, WPB>;
-    if (s->lds_gain > 64 * 1024)
-        VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    s->lds_gain));
-    hipLaunchKernelGGL(k, dim3(d.C, (d.N + per_block - 1) / per_block), dim3(64 * WPB), s->lds_gain, st, d,
-                       per_block);
+    hipLaunchKernelGGL((k_gains<DT, GL, WPB>), dim3(d.C, (d.N + per_block - 1) / per_block), dim3(64 * WPB),
+                       s->lds_gain, st, d, per_block);
     VRP_HIP(hipGetLastError());
     return VRPRPD_OK;
 }
 
+// The launches of one iteration.  Nothing here depends on host-side state
+// that changes between iterations (the iteration number lives on the
+// device), so the sequence can be captured once and replayed.
 template <typename DT>
-static int one_iteration(alns_state* s, hipStream_t st)
+static int launch_iteration(alns_state* s, hipStream_t st)
 {
     AlnsDev& d = s->d;
-    const uint32_t it = (uint32_t)s->it;
-    const int64_t trace_it = d.trace ? s->it - s->trace_base : -1;
-    hipLaunchKernelGGL(k_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, it);
+    hipLaunchKernelGGL(k_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d);
     VRP_HIP(hipGetLastError());
     int rc;
     if (d.M <= 16) rc = launch_gains<DT, 16>(s, st);
@@ -1550,49 +1595,68 @@ static int one_iteration(alns_state* s, hipStream_t st)
     else rc = launch_gains<DT, 64>(s, st);
     if (rc) return rc;
     if (d.learn_on) {
-        auto* kf = k_features<DT>;
-        if (s->lds_feat > 64 * 1024)
-            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kf),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_feat));
-        hipLaunchKernelGGL(kf, dim3(d.C), dim3(256), s->lds_feat, st, d);
+        hipLaunchKernelGGL(k_features<DT>, dim3(d.C), dim3(256), s->lds_feat, st, d);
         VRP_HIP(hipGetLastError());
     }
-    {
-        auto* k = k_destroy<DT>;
-        if (s->lds_destroy > 64 * 1024)
-            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_destroy));
-        hipLaunchKernelGGL(k, dim3(d.C, d.K), dim3(256), s->lds_destroy, st, d, it);
-        VRP_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_destroy<DT>, dim3(d.C, d.K), dim3(256), s->lds_destroy, st, d);
+    VRP_HIP(hipGetLastError());
     const int use_scores = (s->mlp && d.K > 1) ? 1 : 0;
     if (use_scores) {
         rc = vrprpd_mlp_forward(s->mlp, (int64_t)d.C * d.N, d.feat, d.score, st);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_apply<DT>, dim3(d.C), dim3(256), d.N + 1, st, d, it, use_scores);
+    hipLaunchKernelGGL(k_apply<DT>, dim3(d.C), dim3(256), d.N + 1, st, d, use_scores);
     VRP_HIP(hipGetLastError());
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
                 d.C * d.Q, std::max(1, (d.TPC + 63) / 64)};
     for (int r = 0; r < d.Q; ++r) {
-        auto* ke = k_enum<DT>;
-        if (s->lds_enum > 64 * 1024)
-            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ke),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_enum));
-        hipLaunchKernelGGL(ke, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
+        hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
         VRP_HIP(hipGetLastError());
         if ((rc = insert_scan_launch(sa, d.M, s->dist16, st))) return rc;
         hipLaunchKernelGGL(k_select, dim3(d.C), dim3(256), 0, st, d);
         VRP_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d, it, trace_it);
+    hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d);
     VRP_HIP(hipGetLastError());
-    s->it += 1;
-    if (d.prm.import_interval > 0 && s->it % d.prm.import_interval == 0 && s->cpi > 1) {
+    if (s->cpi > 1 && d.prm.import_interval > 0) {
         hipLaunchKernelGGL(k_import, dim3(s->n_inst), dim3(256), 0, st, d, s->cpi);
         VRP_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, d);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+static int launch_iteration_any(alns_state* s, hipStream_t st)
+{
+    return s->dist16 ? launch_iteration<uint16_t>(s, st) : launch_iteration<int32_t>(s, st);
+}
+
+static void drop_graph(alns_state* s)
+{
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+}
+
+// Captures one iteration's launches on the state's own stream.
+static int build_graph(alns_state* s)
+{
+    drop_graph(s);
+    if (!s->cap) VRP_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    VRP_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_iteration_any(s, s->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_error(e, "alns_step: hipStreamEndCapture");
+    s->graph = g;
+    VRP_HIP(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
     return VRPRPD_OK;
 }
 
@@ -1603,10 +1667,30 @@ extern "C" int alns_step(alns_state* s, int32_t iterations, void* stream)
     using namespace vrprpd;
     if (!s || iterations < 0) return set_error(VRPRPD_EINVAL, "alns_step: bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    for (int i = 0; i < iterations; ++i) {
-        const int rc = s->dist16 ? one_iteration<uint16_t>(s, st) : one_iteration<int32_t>(s, st);
-        if (rc) return rc;
+    if (s->use_graph && iterations > 0) {
+        if (!s->gexec) {
+            const int rc = build_graph(s);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < iterations; ++i) {
+            VRP_HIP(hipGraphLaunch(s->gexec, st));
+            s->it += 1;
+        }
+        return VRPRPD_OK;
     }
+    for (int i = 0; i < iterations; ++i) {
+        const int rc = launch_iteration_any(s, st);
+        if (rc) return rc;
+        s->it += 1;
+    }
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_set_graph(alns_state* s, int32_t enable)
+{
+    if (!s) return vrprpd::set_error(VRPRPD_EINVAL, "alns_set_graph: state is NULL");
+    s->use_graph = enable != 0;
+    vrprpd::drop_graph(s);
     return VRPRPD_OK;
 }
 
@@ -1615,7 +1699,8 @@ extern "C" int alns_set_trace(alns_state* s, int64_t* trace, int64_t capacity)
     if (!s || (trace && capacity < 1)) return vrprpd::set_error(VRPRPD_EINVAL, "alns_set_trace: bad arguments");
     s->d.trace = trace;
     s->d.trace_cap = trace ? capacity : 0;
-    s->trace_base = s->it;
+    s->d.trace_base = s->it;
+    vrprpd::drop_graph(s);
     return VRPRPD_OK;
 }
 
@@ -1702,6 +1787,7 @@ extern "C" int alns_set_learned(alns_state* s, vrprpd_mlp* mlp, int32_t K, doubl
     d.K = K;
     d.eps = eps;
     d.learn_on = (mlp != nullptr || d.rec_x != nullptr) ? 1 : 0;
+    drop_graph(s);
     return VRPRPD_OK;
 }
 
@@ -1740,6 +1826,7 @@ extern "C" int alns_record(alns_state* s, int64_t capacity, void* stream)
         d.rec_base = s->it;
     }
     d.learn_on = (s->mlp != nullptr || d.rec_x != nullptr) ? 1 : 0;
+    drop_graph(s);
     return VRPRPD_OK;
 }
 

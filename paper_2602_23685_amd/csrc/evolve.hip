@@ -21,10 +21,13 @@
 namespace vrprpd {
 
 // rank_of[i] = #{ j : (f_j, j) < (f_i, i) }; order[rank_of[i]] = i.
+// Population blockIdx.y occupies entries [y Np, (y + 1) Np) of fit and order.
 __global__ __launch_bounds__(256) void rank_kernel(const int64_t* __restrict__ fit, int32_t Np,
                                                    int32_t* __restrict__ order)
 {
     __shared__ int64_t tile[1024];
+    fit += (int64_t)blockIdx.y * Np;
+    order += (int64_t)blockIdx.y * Np;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int64_t fi = i < Np ? fit[i] : 0;
     int rank = 0;
@@ -51,12 +54,31 @@ struct EvolveArgs {
     uint64_t seed;
     int32_t Np, genes, n_elite, n_mutant;
     uint32_t thr24, generation;
+    const uint32_t* gen_dev;    // generation read from device memory (batched form), else `generation`
+    const int32_t* genes_of;    // genes of each population (batched form), else `genes`
 };
 
+// Seed of population p of a batched run (population 0 keeps the seed).
+__host__ __device__ inline uint64_t pop_seed(uint64_t seed, int p) { return seed + 0x9E3779B97F4A7C15ull * (uint64_t)p; }
+
+// Block (child, population).
 __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a)
 {
     const int i = blockIdx.x;
-    const int G = a.genes;
+    const int pop = blockIdx.y;
+    if (pop) {
+        const int64_t rows = (int64_t)pop * a.Np;
+        a.prio += rows * a.stride;
+        a.prio_out += rows * a.stride;
+        if (a.hint) {
+            a.hint += rows * a.stride;
+            a.hint_out += rows * a.stride;
+        }
+        a.order += rows;
+    }
+    a.seed = pop_seed(a.seed, pop);
+    if (a.gen_dev) a.generation = *a.gen_dev;
+    const int G = a.genes_of ? a.genes_of[pop] : a.genes;
     const int total = a.hint ? 2 * G : G;
     float* dp = a.prio_out + (int64_t)i * a.stride;
     float* dh = a.hint ? a.hint_out + (int64_t)i * a.stride : nullptr;
@@ -191,7 +213,7 @@ extern "C" int brkga_evolve(int32_t Np, int32_t genes, int64_t key_stride, const
     VRP_HIP(hipGetLastError());
     const uint32_t thr = (uint32_t)std::floor(rho_e * 16777216.0);
     EvolveArgs a{prio, hint, rank_out, prio_out, hint_out, key_stride, seed, Np, genes, n_elite, n_mutant,
-                 thr, generation};
+                 thr, generation, nullptr, nullptr};
     hipLaunchKernelGGL(evolve_kernel, dim3(Np), dim3(256), 0, st, a);
     VRP_HIP(hipGetLastError());
     return VRPRPD_OK;
@@ -214,6 +236,256 @@ extern "C" int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint1
         hipLaunchKernelGGL(warm_fill_kernel, dim3(Np - 1), dim3(256), 0, st, G, key_stride, n_warm, n_variants,
                            seed, prio_out, hint_out);
         VRP_HIP(hipGetLastError());
+    }
+    return VRPRPD_OK;
+}
+
+// ============================================================== batched form
+// Many instances' populations evolved together (one decode launch over every
+// individual, one rank and one evolve launch over every population), one
+// generation captured as a HIP graph per population buffer and replayed.
+// Population p uses seed pop_seed(seed, p), so it evolves exactly as a
+// single-population run of brkga_evolve with that seed would.
+namespace vrprpd {
+
+__global__ __launch_bounds__(256) void random_pop_kernel(int64_t stride, const int32_t* genes_of, int32_t Np,
+                                                         uint64_t seed, float* prio, float* hint)
+{
+    const int i = blockIdx.x, pop = blockIdx.y;
+    const int G = genes_of[pop];
+    const uint64_t sd = pop_seed(seed, pop);
+    const int64_t row = (int64_t)pop * Np + i;
+    for (int blk = threadIdx.x; 4 * blk < 2 * G; blk += 256) {
+        const Philox4 r = philox4x32_10((uint32_t)blk, (uint32_t)i, 0u, kTagRandom, (uint32_t)sd, (uint32_t)(sd >> 32));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * blk + u;
+            if (j >= 2 * G) break;
+            if (j < G) prio[row * stride + j] = unit24(r.x[u]);
+            else hint[row * stride + j - G] = unit24(r.x[u]);
+        }
+    }
+}
+
+// Block per population, after ranking: keep the best individual seen so far.
+__global__ __launch_bounds__(256) void best_kernel(int32_t Np, int64_t stride, const int32_t* order, const int64_t* fit,
+                                                   const float* prio, const float* hint, int64_t* best_fit,
+                                                   float* best_prio, float* best_hint)
+{
+    const int pop = blockIdx.x;
+    const int b = order[(int64_t)pop * Np];
+    const int64_t f = fit[(int64_t)pop * Np + b];
+    __shared__ int better;
+    if (threadIdx.x == 0) better = f < best_fit[pop];
+    __syncthreads();
+    if (!better) return;
+    const int64_t row = (int64_t)pop * Np + b;
+    for (int64_t j = threadIdx.x; j < stride; j += 256) {
+        best_prio[pop * stride + j] = prio[row * stride + j];
+        best_hint[pop * stride + j] = hint[row * stride + j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) best_fit[pop] = f;
+}
+
+__global__ void gen_tick_kernel(uint32_t* gen)
+{
+    if (threadIdx.x == 0) *gen += 1u;
+}
+
+}  // namespace vrprpd
+
+struct brkga_state {
+    const vrprpd_set* set = nullptr;
+    int32_t P = 0, Np = 0, ne = 0, nm = 0;
+    uint32_t thr = 0;
+    uint64_t seed = 0;
+    int64_t stride = 0;
+    int64_t generations = 0;
+    float* prio[2] = {nullptr, nullptr};
+    float* hint[2] = {nullptr, nullptr};
+    int cur = 0;
+    int32_t *inst_of_row = nullptr, *genes_of = nullptr, *order = nullptr, *mk = nullptr, *unsch = nullptr;
+    uint32_t* status = nullptr;
+    int64_t *fit = nullptr, *best_fit = nullptr;
+    float *best_prio = nullptr, *best_hint = nullptr;
+    uint32_t* gen_dev = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<void*> allocs;
+};
+
+namespace vrprpd {
+
+// decode + evaluate the population in buffer `from`, keep the best, rank,
+// evolve into the other buffer, advance the generation counter
+static int brkga_generation(brkga_state* s, int from, hipStream_t st)
+{
+    const int64_t B = (int64_t)s->P * s->Np;
+    int rc = brkga_decode_eval(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->fit, s->mk,
+                               s->unsch, s->status, nullptr, nullptr, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(rank_kernel, dim3((s->Np + 255) / 256, s->P), dim3(256), 0, st, s->fit, s->Np, s->order);
+    hipLaunchKernelGGL(best_kernel, dim3(s->P), dim3(256), 0, st, s->Np, s->stride, s->order, s->fit, s->prio[from],
+                       s->hint[from], s->best_fit, s->best_prio, s->best_hint);
+    EvolveArgs a{s->prio[from], s->hint[from], s->order, s->prio[from ^ 1], s->hint[from ^ 1], s->stride, s->seed,
+                 s->Np, 0, s->ne, s->nm, s->thr, 0u, s->gen_dev, s->genes_of};
+    hipLaunchKernelGGL(evolve_kernel, dim3(s->Np, s->P), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(gen_tick_kernel, dim3(1), dim3(64), 0, st, s->gen_dev);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
+}  // namespace vrprpd
+
+extern "C" int brkga_state_destroy(brkga_state* s)
+{
+    if (!s) return VRPRPD_OK;
+    for (int i = 0; i < 2; ++i) {
+        if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
+        if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
+    }
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    for (void* p : s->allocs) (void)hipFree(p);
+    delete s;
+    return VRPRPD_OK;
+}
+
+extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
+                                  int32_t Np, int32_t n_elite, int32_t n_mutant, double rho_e, uint64_t seed,
+                                  const float* prio0, const float* hint0, void* stream)
+{
+    if (!out) return set_error(VRPRPD_EINVAL, "brkga_state_create: out is NULL");
+    *out = nullptr;
+    if (!set || n_inst < 1 || !inst_ids || Np < 2 || n_elite < 1 || n_mutant < 0 || n_elite + n_mutant > Np ||
+        Np - n_elite < 1 || !(rho_e >= 0.0 && rho_e <= 1.0) || ((prio0 == nullptr) != (hint0 == nullptr)))
+        return set_error(VRPRPD_EINVAL, "brkga_state_create: bad arguments");
+    if ((int64_t)n_inst * Np > INT32_MAX) return set_error(VRPRPD_EINVAL, "brkga_state_create: too many individuals");
+    int n_max = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (inst_ids[i] < 0 || inst_ids[i] >= set->num_inst)
+            return set_error(VRPRPD_EINVAL, "brkga_state_create: instance id %d out of range", inst_ids[i]);
+        n_max = std::max(n_max, set->host[inst_ids[i]].n);
+    }
+    if (n_max != set->n_max)
+        return set_error(VRPRPD_EINVAL, "brkga_state_create: the set's largest instance must be among inst_ids "
+                                        "(the decoder sizes its keys by the set)");
+    brkga_state* s = new brkga_state;
+    s->set = set;
+    s->P = n_inst;
+    s->Np = Np;
+    s->ne = n_elite;
+    s->nm = n_mutant;
+    s->thr = (uint32_t)std::floor(rho_e * 16777216.0);
+    s->seed = seed;
+    s->stride = 2 * (int64_t)set->n_max;
+    const int64_t B = (int64_t)n_inst * Np;
+    hipError_t e = hipSuccess;
+    auto A = [&](void** p, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(p, bytes ? bytes : 16);
+        if (e == hipSuccess) {
+            s->allocs.push_back(*p);
+            e = hipMemset(*p, 0, bytes ? bytes : 16);
+        }
+    };
+    for (int i = 0; i < 2; ++i) {
+        A((void**)&s->prio[i], B * s->stride * 4);
+        A((void**)&s->hint[i], B * s->stride * 4);
+    }
+    A((void**)&s->inst_of_row, B * 4);
+    A((void**)&s->genes_of, n_inst * 4);
+    A((void**)&s->order, B * 4);
+    A((void**)&s->mk, B * 4);
+    A((void**)&s->unsch, B * 4);
+    A((void**)&s->status, B * 4);
+    A((void**)&s->fit, B * 8);
+    A((void**)&s->best_fit, n_inst * 8);
+    A((void**)&s->best_prio, n_inst * s->stride * 4);
+    A((void**)&s->best_hint, n_inst * s->stride * 4);
+    A((void**)&s->gen_dev, 4);
+    if (e != hipSuccess) {
+        brkga_state_destroy(s);
+        return set_error(VRPRPD_ENOMEM, "brkga_state_create: %s", hipGetErrorString(e));
+    }
+    std::vector<int32_t> rows(B), genes(n_inst);
+    std::vector<int64_t> bf(n_inst, INT64_MAX);
+    for (int p = 0; p < n_inst; ++p) {
+        genes[p] = 2 * set->host[inst_ids[p]].n;
+        for (int i = 0; i < Np; ++i) rows[(int64_t)p * Np + i] = inst_ids[p];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if ((e = hipMemcpy(s->inst_of_row, rows.data(), B * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->genes_of, genes.data(), n_inst * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(s->best_fit, bf.data(), n_inst * 8, hipMemcpyHostToDevice)) != hipSuccess) {
+        brkga_state_destroy(s);
+        return hip_error(e, "brkga_state_create: upload");
+    }
+    if (prio0) {
+        if ((e = hipMemcpyAsync(s->prio[0], prio0, B * s->stride * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(s->hint[0], hint0, B * s->stride * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess) {
+            brkga_state_destroy(s);
+            return hip_error(e, "brkga_state_create: copy of the initial population");
+        }
+    } else {
+        hipLaunchKernelGGL(random_pop_kernel, dim3(Np, n_inst), dim3(256), 0, st, s->stride, s->genes_of, Np, seed,
+                           s->prio[0], s->hint[0]);
+        if ((e = hipGetLastError()) != hipSuccess) {
+            brkga_state_destroy(s);
+            return hip_error(e, "brkga_state_create: initial population");
+        }
+    }
+    *out = s;
+    return VRPRPD_OK;
+}
+
+extern "C" int brkga_state_step(brkga_state* s, int32_t generations, int32_t use_graph, void* stream)
+{
+    if (!s || generations < 0) return set_error(VRPRPD_EINVAL, "brkga_state_step: bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int g = 0; g < generations; ++g) {
+        const int from = s->cur;
+        if (use_graph) {
+            if (!s->gexec[from]) {
+                if (!s->cap) VRP_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+                VRP_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+                const int rc = brkga_generation(s, from, s->cap);
+                hipGraph_t gr = nullptr;
+                const hipError_t e = hipStreamEndCapture(s->cap, &gr);
+                if (rc) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return rc;
+                }
+                if (e != hipSuccess) return hip_error(e, "brkga_state_step: hipStreamEndCapture");
+                s->graph[from] = gr;
+                VRP_HIP(hipGraphInstantiate(&s->gexec[from], gr, nullptr, nullptr, 0));
+            }
+            VRP_HIP(hipGraphLaunch(s->gexec[from], st));
+        } else {
+            const int rc = brkga_generation(s, from, st);
+            if (rc) return rc;
+        }
+        s->cur ^= 1;
+        s->generations += 1;
+    }
+    return VRPRPD_OK;
+}
+
+extern "C" int brkga_state_get(const brkga_state* s, int64_t* generations, int64_t* best_fitness, float* best_prio,
+                               float* best_hint, float* prio, float* hint, void* stream)
+{
+    if (!s) return set_error(VRPRPD_EINVAL, "brkga_state_get: state is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t B = (int64_t)s->P * s->Np;
+    if (generations) *generations = s->generations;
+    if (best_prio) VRP_HIP(hipMemcpyAsync(best_prio, s->best_prio, s->P * s->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (best_hint) VRP_HIP(hipMemcpyAsync(best_hint, s->best_hint, s->P * s->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (prio) VRP_HIP(hipMemcpyAsync(prio, s->prio[s->cur], B * s->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (hint) VRP_HIP(hipMemcpyAsync(hint, s->hint[s->cur], B * s->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (best_fitness) {
+        VRP_HIP(hipStreamSynchronize(st));
+        VRP_HIP(hipMemcpy(best_fitness, s->best_fit, s->P * 8, hipMemcpyDeviceToHost));
     }
     return VRPRPD_OK;
 }

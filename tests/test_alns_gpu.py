@@ -79,3 +79,31 @@ def test_alns_continues_across_calls(orc, P):
         assert np.array_equal(sa[key], sb[key]), key
     ref = orc.alns_run(inst, orc.alns_params(import_interval=7), 3, 20, 5, ops, rt)
     assert np.array_equal(sa["zb"], ref["best_mk"])
+
+
+def test_graph_replay_equals_eager_launches(orc, P):
+    """The captured iteration replayed many times gives the eager launch
+    sequence's trajectory, with other device work and host synchronisation
+    between replays; every replayed iteration is compared."""
+    inst = synth.make_instance(40, 4, 5, 20, "2x", seed=91)
+    ops, rt = synth.round_robin_solution(inst)
+    prm = P.alns_params(tuple_budget=400, import_interval=5)
+    S = P.InstanceSet([inst])
+    mk_state = lambda: P.AlnsState(S, [0], 3, prm, 31, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+    g, e = mk_state(), mk_state()
+    e.set_graph(False)
+    tg, te = g.set_trace(24), e.set_trace(24)
+    cand_ops, cand_rt = synth.random_candidates(inst, 64, seed=5)
+    d_ops, d_rt = torch.from_numpy(cand_ops).cuda(), torch.from_numpy(cand_rt).cuda()
+    for chunk in (1, 1, 2, 5, 7, 8):
+        g.step(chunk)
+        P.vrprpd_eval(S, d_ops, d_rt)          # eager work between replays
+        torch.cuda.synchronize()
+        e.step(chunk)
+        torch.cuda.synchronize()
+        sg, se = g.state(), e.state()
+        for key in ("z", "zb", "T", "wD", "wR"):
+            assert np.array_equal(sg[key], se[key]), (chunk, key)
+    assert np.array_equal(tg.cpu().numpy(), te.cpu().numpy())
+    ref = orc.alns_run(inst, orc.alns_params(tuple_budget=400, import_interval=5), 3, 24, 31, ops, rt, trace=True)
+    assert np.array_equal(tg.cpu().numpy(), ref["trace"])

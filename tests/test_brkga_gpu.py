@@ -110,3 +110,43 @@ def test_generation_loop_matches_oracle(orc, P):
         gp, gh, _ = P.brkga_evolve(gp, gh, out["fitness"], ne, nm, 0.7, 77, gen)
         op_, oh_, _ = orc.brkga_evolve(op_, oh_, of, ne, nm, orc.rho_threshold(0.7), 77, gen)
         assert np.array_equal(gp.cpu().numpy().view(np.uint32), op_.view(np.uint32))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_populations_match_oracle(orc, P, graph):
+    """Three instances of different size evolved as one batched state: every
+    population equals the oracle's single-population run with its seed, and
+    the kept best fitness is the best decoded so far."""
+    insts = [synth.make_instance(16, 2, 2, 4, "base", seed=31),
+             synth.make_instance(40, 4, 5, 20, "2x", seed=32),
+             synth.make_instance(25, 3, 3, 9, "1R10", seed=33)]
+    S = P.InstanceSet(insts)
+    Np, gens, seed = 96, 5, 2024
+    ne, nm = orc.brkga_sizes(Np)
+    stride = 2 * 40
+    g = np.random.Generator(np.random.Philox(key=77))
+    p0 = np.zeros((3 * Np, stride), np.float32)
+    h0 = np.zeros((3 * Np, stride), np.float32)
+    for p, inst in enumerate(insts):
+        p0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
+        h0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
+    st = P.BrkgaState(S, [0, 1, 2], Np, ne, nm, 0.7, seed, dev(p0), dev(h0))
+    st.step(2, graph=graph)
+    torch.cuda.synchronize()
+    st.step(gens - 2, graph=graph)
+    best, _, _ = st.best()
+    pop_p, pop_h = st.population()
+    pop_p, pop_h = pop_p.cpu().numpy(), pop_h.cpu().numpy()
+    for p, inst in enumerate(insts):
+        G = 2 * inst.n
+        op_ = p0[p * Np:(p + 1) * Np, :G].copy()
+        oh_ = h0[p * Np:(p + 1) * Np, :G].copy()
+        bf = np.iinfo(np.int64).max
+        for gen in range(gens):
+            fit = orc.decode_batch(inst, op_, oh_)[0]
+            bf = min(bf, int(fit.min()))
+            op_, oh_, _ = orc.brkga_evolve(op_, oh_, fit, ne, nm, orc.rho_threshold(0.7), P.pop_seed(seed, p), gen)
+        assert best[p] == bf, (p, best[p], bf)
+        assert np.array_equal(pop_p[p * Np:(p + 1) * Np, :G].view(np.uint32), op_.view(np.uint32)), p
+        assert np.array_equal(pop_h[p * Np:(p + 1) * Np, :G].view(np.uint32), oh_.view(np.uint32)), p
+    st.close()
