@@ -110,6 +110,156 @@ def time_to_oracle_best(P, torch, iters_oracle=2000, chains=32, budget_iters=400
             "reached": bool(best is not None and best <= z_target)}
 
 
+def _multi_init(insts, ids, synth, torch):
+    """Initial solutions of instances `ids` laid out for a multi-instance
+    ALNS state (stride 2 n_max ops, m_max route ends)."""
+    n_max = max(insts[i].n for i in ids)
+    m_max = max(insts[i].m for i in ids)
+    ops = np.zeros((len(ids), 2 * n_max), np.uint16)
+    rt = np.zeros((len(ids), m_max), np.uint16)
+    for j, i in enumerate(ids):
+        o, r = synth.round_robin_solution(insts[i], vehicles=min(insts[i].m, insts[i].R))
+        ops[j, :len(o)] = o
+        rt[j, :len(r)] = r
+    return torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda()
+
+
+def batched_form(P, torch, count=256, cpi=2, iters=10, gens=10, Np=128):
+    """The batched form on instances of uneven size: every instance's ALNS
+    chains and BRKGA population advance together, one graph replay per
+    n-bucket per iteration or generation, against the same work done
+    instance by instance with direct launches."""
+    import synth
+    insts = synth.batched_instances(count)
+    edges = [0, 50, 150, 450, 10**9]
+    buckets = [[i for i, x in enumerate(insts) if edges[b] <= x.n < edges[b + 1]] for b in range(4)]
+    buckets = [b for b in buckets if b]
+    prm = P.alns_params(tuple_budget=4096, import_interval=0)
+    ne, nm = int(0.15 * Np), int(0.15 * Np)
+    # batched
+    log(f"batched form: {count} instances in {len(buckets)} n-buckets")
+    sets, states, pops = [], [], []
+    for b in buckets:
+        S = P.InstanceSet([insts[i] for i in b])
+        o, r = _multi_init(insts, b, synth, torch)
+        states.append(P.AlnsState(S, list(range(len(b))), cpi, prm, 11, o, r))
+        ids = list(range(len(b)))
+        pops.append(P.BrkgaState(S, ids, Np, ne, nm, 0.7, 13))
+        sets.append(S)
+    for st in states:
+        st.step(1)
+    for pp in pops:
+        pp.step(1)
+    torch.cuda.synchronize()
+    e0 = sum(st.state()["evals"] for st in states)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        for st in states:
+            st.step(1)
+    torch.cuda.synchronize()
+    t_alns_b = time.perf_counter() - t0
+    e1 = sum(st.state()["evals"] for st in states)
+    t0 = time.perf_counter()
+    for pp in pops:
+        pp.step(gens)
+    torch.cuda.synchronize()
+    t_brkga_b = time.perf_counter() - t0
+    zb_b = np.concatenate([st.state()["zb"].reshape(-1, cpi).min(axis=1) for st in states])
+    # instance by instance, direct launches
+    log("batched form: the same work instance by instance")
+    plain, pl_pops = [], []
+    for i, x in enumerate(insts):
+        S = P.InstanceSet([x])
+        o, r = synth.round_robin_solution(x, vehicles=min(x.m, x.R))
+        st = P.AlnsState(S, [0], cpi, prm, 11, torch.from_numpy(o).cuda(), torch.from_numpy(r).cuda())
+        st.set_graph(False)
+        st.step(1)
+        plain.append((S, st))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        for S, st in plain:
+            st.step(1)
+    torch.cuda.synchronize()
+    t_alns_p = time.perf_counter() - t0
+    # BRKGA per instance: decode + evolve launches per generation
+    keys = []
+    for i, x in enumerate(insts):
+        pr, hi = synth.random_keys(Np, x.n, seed=500 + i)
+        keys.append((plain[i][0], torch.from_numpy(pr).cuda(), torch.from_numpy(hi).cuda()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for S, pr, hi in keys:
+        for gen in range(gens):
+            out = P.brkga_decode_eval(S, pr, hi)
+            pr, hi, _ = P.brkga_evolve(pr, hi, out["fitness"], ne, nm, 0.7, 13, gen)
+    torch.cuda.synchronize()
+    t_brkga_p = time.perf_counter() - t0
+    zb_p = np.array([st.state()["zb"].min() for _, st in plain])
+    ns = np.array([x.n for x in insts])
+    return {"instances": count, "n_range": [int(ns.min()), int(ns.max())], "n_buckets": len(buckets),
+            "chains_per_instance": cpi, "alns_iterations": iters, "brkga_generations": gens, "population": Np,
+            "alns_seconds_batched": t_alns_b, "alns_seconds_one_by_one": t_alns_p,
+            "alns_speedup": t_alns_p / t_alns_b, "alns_evals_per_s_batched": (e1 - e0) / t_alns_b,
+            "brkga_seconds_batched": t_brkga_b, "brkga_seconds_one_by_one": t_brkga_p,
+            "brkga_speedup": t_brkga_p / t_brkga_b,
+            "mean_best_ratio_batched_vs_one_by_one": float(np.mean(zb_b / zb_p))}
+
+
+def learned_form(P, torch, n=500, chains=32, rec_iters=200, train_steps=1500, ab_iters=200, K=8, eps=0.1):
+    """The learned form on the cfg5 instance shape: plain ALNS records
+    (removal set, makespan change) pairs, the network trains on them with the
+    library's kernels, then learned and plain ALNS run from the same start;
+    reported: held-out loss, each run's best, and the wall time the learned
+    run needs to reach the plain run's final best."""
+    import synth
+    from paper_2602_23685_amd import learned
+    inst = synth.make_instance(n, 10, 8, 50, "base", seed=5005)
+    ops, rt = synth.round_robin_solution(inst, vehicles=10)
+    S = P.InstanceSet([inst])
+    prm = P.alns_params(tuple_budget=16384, import_interval=100)
+    mk = lambda seed: P.AlnsState(S, [0], chains, prm, seed, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+    log(f"learned form: recording {rec_iters} x {chains} sets")
+    tr_run, te_run = mk(101), mk(102)
+    t0 = time.perf_counter()
+    sets = learned.record(tr_run, rec_iters)
+    t_rec = time.perf_counter() - t0
+    learned.record(te_run, max(10, rec_iters // 5))
+    _, q = tr_run.record_info()
+    M = P.Mlp(max_rows=max(512 * q, chains * n), seed=7)
+    log(f"learned form: training {train_steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    learned.train(M, tr_run, steps=train_steps, batch_sets=512, lr=1e-3, momentum=0.9)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    loss, base = learned.held_out(M, te_run)
+    log("learned form: A/B")
+    res = {}
+    for name in ("plain", "learned"):
+        st = mk(103)
+        if name == "learned":
+            st.set_learned(M, K=K, eps=eps)
+        st.step(1)
+        torch.cuda.synchronize()
+        hist, t0 = [], time.perf_counter()
+        for it in range(ab_iters // 10):
+            st.step(10)
+            hist.append((time.perf_counter() - t0, int(st.state()["zb"].min())))
+        res[name] = hist
+    target = res["plain"][-1][1]
+    reach = next((t for t, z in res["learned"] if z <= target), None)
+    return {"n": n, "m": 10, "k": 8, "R": 50, "rule": "base", "chains": chains, "recorded_sets": sets,
+            "record_seconds": t_rec, "train_steps": train_steps, "train_batch_sets": 512,
+            "train_seconds": t_train, "heldout_loss": loss, "heldout_mean_predictor_loss": base,
+            "ab_iterations": ab_iters, "K": K, "eps": eps,
+            "plain_best": res["plain"][-1][1], "learned_best": res["learned"][-1][1],
+            "plain_seconds": res["plain"][-1][0], "learned_seconds": res["learned"][-1][0],
+            "learned_seconds_to_plain_best": reach,
+            "note": "training pairs from plain ALNS on this instance; the paper's 1M-pair scale is "
+                    "not run by the benchmark"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +268,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-race", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 256 MiB three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -250,6 +401,9 @@ def main():
     if not args.no_race:
         log("time to oracle-best (n=16)")
         out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
+    if not args.no_forms:
+        out["batched_form"] = batched_form(P, torch)
+        out["learned_form"] = learned_form(P, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds)

@@ -127,6 +127,21 @@ int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int
                 const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
                 int32_t* makespan, uint32_t* status, void* stream);
 
+/* Autotuner of vrprpd_eval's launch shape (waves per block 1, 2, 4 within
+ * the LDS limit x ops per lane per sweep step 2, 4): runs every shape on the
+ * caller's batch `reps` times, checks that each gives the default shape's
+ * makespans and statuses bit for bit (EHIP otherwise), and keeps the fastest
+ * in the set for later vrprpd_eval launches of the same (n, m) -- n, m of the
+ * instance, or n_max, m_max when inst != NULL.  Arguments as vrprpd_eval;
+ * outputs the chosen shape and, if ms_out != NULL, the mean milliseconds of
+ * the six shapes in the order (1,2), (1,4), (2,2), (2,4), (4,2), (4,4)
+ * (-1: over the LDS limit).  Synchronous; not concurrent with other calls
+ * on the same set. */
+int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                         const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                         int32_t* makespan, uint32_t* status, int32_t reps, int32_t* wpb_out, int32_t* step_out,
+                         float* ms_out, void* stream);
+
 /* One way to put a removed customer back into a partial solution
  * (Section 4.2.3, repair operators): its drop into route vD before index pD
  * (pD = len(vD) appends), its pickup into route vP before index pP, where pP
@@ -426,8 +441,8 @@ int alns_get_learned(const alns_state* st, uint16_t* feat, int32_t* cand_rem, in
 #define VRPRPD_MLP_IN 64
 #define VRPRPD_MLP_HIDDEN 256
 #define VRPRPD_MLP_NUM_PARAMS 148481
-/* params: host fp32 flat vector, or NULL for Glorot-uniform weights (Philox
- * draws from seed) and zero biases.  Synchronous.  EINVAL unless 1 <=
+/* params: host fp32 flat vector, or NULL for Glorot-uniform hidden weights
+ * (Philox draws from seed), zero biases and a zero head (w4, b4).  Synchronous.  EINVAL unless 1 <=
  * max_rows <= 2^26; ENOMEM; EHIP. */
 int vrprpd_mlp_create(vrprpd_mlp** out, int64_t max_rows, const float* params, uint64_t seed);
 int vrprpd_mlp_destroy(vrprpd_mlp* mlp);
@@ -447,7 +462,8 @@ int vrprpd_mlp_forward(vrprpd_mlp* mlp, int64_t rows, const uint16_t* x, float* 
 int vrprpd_mlp_set_scores(vrprpd_mlp* mlp, int32_t num_sets, const int64_t* seg_off, float* set_score, void* stream);
 /* Loss of the last forward against target[s] (device fp32): stores each
  * set's squared error in sq_err (device, nullable; the loss is their mean)
- * and keeps dL/dscore per row for vrprpd_mlp_backward. */
+ * and keeps dL/dscore per row for vrprpd_mlp_backward (zero for rows in no
+ * set). */
 int vrprpd_mlp_loss(vrprpd_mlp* mlp, int32_t num_sets, const int64_t* seg_off, const float* target, float* sq_err,
                     void* stream);
 /* Gradient of the loss through the last forward, from dy (device fp32

@@ -44,6 +44,7 @@ SIGNATURES = {
     "vrprpd_set_destroy": (C.c_int, [_P]),
     "vrprpd_set_info": (C.c_int, [_P, _P, _P, _P, _P]),
     "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "vrprpd_autotune_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P, _P, _P]),
     "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
@@ -181,6 +182,23 @@ def vrprpd_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None
         _dptr(rt_end, torch.uint16, "rt_end"), ALLOW_PARTIAL if partial else 0,
         _dptr(makespan, torch.int32, "makespan"), _dptr(status, None, "status"), _stream(stream)))
     return makespan, status
+
+
+def vrprpd_autotune_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None, partial=False,
+                         reps=3, stream=None):
+    """Tune vrprpd_eval's launch shape on this batch; returns (waves per
+    block, ops per step, mean ms of the six shapes)."""
+    B = rt_end.shape[0]
+    mk = torch.empty(B, dtype=torch.int32, device="cuda")
+    st = torch.empty(B, dtype=torch.int32, device="cuda")
+    w, k = C.c_int32(), C.c_int32()
+    ms = np.zeros(6, np.float32)
+    _check(load().vrprpd_autotune_eval(S.handle, B, _dptr(inst, torch.int32, "inst"),
+                                       _dptr(op_off, torch.int64, "op_off"), _dptr(ops, torch.uint16, "ops"),
+                                       _dptr(rt_off, torch.int64, "rt_off"), _dptr(rt_end, torch.uint16, "rt_end"),
+                                       ALLOW_PARTIAL if partial else 0, _dptr(mk), _dptr(st), reps, C.byref(w),
+                                       C.byref(k), ms.ctypes.data, _stream(stream)))
+    return w.value, k.value, ms
 
 
 def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_bases=1,

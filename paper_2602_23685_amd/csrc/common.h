@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "vrprpd.h"
@@ -132,4 +134,7 @@ struct vrprpd_set {
     vrprpd::InstDev* d_inst = nullptr;
     void* d_dist = nullptr;            // uint16_t or int32_t, per dist16
     int32_t* d_proc = nullptr;
+    // launch shapes of vrprpd_eval chosen by vrprpd_autotune_eval, keyed by
+    // (n, m) of the launch: (waves per block, ops per lane per sweep step)
+    std::map<std::pair<int, int>, std::pair<int, int>> eval_tuned;
 };

@@ -242,28 +242,37 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
     }
 }
 
-constexpr int kEvalStep = 4;   // ops per lane per sweep step
+constexpr int kEvalStep = 4;   // default ops per lane per sweep step
 
 struct LaunchShape {
-    int gl, wpb, group_bytes, lds;
+    int gl, wpb, group_bytes, lds, step;
 };
 
-static LaunchShape eval_shape(int n_max, int m_max, int dist16)
+static int max_wpb(int n_max, int gl, int dist16)
+{
+    const int gb = group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
+    const int per_wave = (64 / gl) * gb;
+    int w = 4;
+    while (w > 1 && (size_t)w * per_wave > 64 * 1024) w >>= 1;
+    return w;
+}
+
+static LaunchShape eval_shape(int n_max, int m_max, int dist16, int wpb, int step)
 {
     LaunchShape sh;
     sh.gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
     sh.group_bytes = group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
     const int per_wave = (64 / sh.gl) * sh.group_bytes;
-    sh.wpb = 4;
-    while (sh.wpb > 1 && (size_t)sh.wpb * per_wave > 64 * 1024) sh.wpb >>= 1;
+    sh.wpb = wpb > 0 ? wpb : max_wpb(n_max, sh.gl, dist16);
     sh.lds = sh.wpb * per_wave;
+    sh.step = step > 0 ? step : kEvalStep;
     return sh;
 }
 
-template <typename DT, int GL, int WPB>
+template <typename DT, int GL, int WPB, int K>
 static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
 {
-    auto* k = a.inst ? eval_kernel<DT, GL, WPB, kEvalStep, false> : eval_kernel<DT, GL, WPB, kEvalStep, true>;
+    auto* k = a.inst ? eval_kernel<DT, GL, WPB, K, false> : eval_kernel<DT, GL, WPB, K, true>;
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
@@ -272,13 +281,19 @@ static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
     return VRPRPD_OK;
 }
 
-template <typename DT, int GL>
-static int dispatch_wpb(const EvalArgs& a, int wpb, int lds, hipStream_t st)
+template <typename DT, int GL, int WPB>
+static int dispatch_step(const EvalArgs& a, int step, int lds, hipStream_t st)
 {
-    switch (wpb) {
-    case 4: return launch_eval<DT, GL, 4>(a, lds, st);
-    case 2: return launch_eval<DT, GL, 2>(a, lds, st);
-    default: return launch_eval<DT, GL, 1>(a, lds, st);
+    return step == 2 ? launch_eval<DT, GL, WPB, 2>(a, lds, st) : launch_eval<DT, GL, WPB, 4>(a, lds, st);
+}
+
+template <typename DT, int GL>
+static int dispatch_wpb(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
+{
+    switch (sh.wpb) {
+    case 4: return dispatch_step<DT, GL, 4>(a, sh.step, sh.lds, st);
+    case 2: return dispatch_step<DT, GL, 2>(a, sh.step, sh.lds, st);
+    default: return dispatch_step<DT, GL, 1>(a, sh.step, sh.lds, st);
     }
 }
 
@@ -286,19 +301,16 @@ template <typename DT>
 static int dispatch_gl(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
 {
     switch (sh.gl) {
-    case 16: return dispatch_wpb<DT, 16>(a, sh.wpb, sh.lds, st);
-    case 32: return dispatch_wpb<DT, 32>(a, sh.wpb, sh.lds, st);
-    default: return dispatch_wpb<DT, 64>(a, sh.wpb, sh.lds, st);
+    case 16: return dispatch_wpb<DT, 16>(a, sh, st);
+    case 32: return dispatch_wpb<DT, 32>(a, sh, st);
+    default: return dispatch_wpb<DT, 64>(a, sh, st);
     }
 }
 
-}  // namespace vrprpd
-
-using namespace vrprpd;
-
-extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
-                           const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
-                           int32_t* makespan, uint32_t* status, void* stream)
+// Validates the arguments and launches one shape (wpb, step <= 0: default).
+static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                       const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                       int32_t* makespan, uint32_t* status, hipStream_t st, int wpb, int step)
 {
     if (!set) return set_error(VRPRPD_EINVAL, "vrprpd_eval: set is NULL");
     if (B < 0) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B < 0");
@@ -310,7 +322,14 @@ extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: instances differ in n or m; pass op_off and rt_off");
     const int n_lds = inst ? set->n_max : set->host[0].n;
     const int m_max = inst ? set->m_max : set->host[0].m;
-    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16);
+    if (wpb <= 0 && step <= 0) {
+        const auto it = set->eval_tuned.find({n_lds, m_max});
+        if (it != set->eval_tuned.end()) {
+            wpb = it->second.first;
+            step = it->second.second;
+        }
+    }
+    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16, wpb, step);
     if ((size_t)sh.lds > kLdsPerCu)
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: n=%d needs %d B of LDS per candidate", n_lds, sh.lds);
     const int64_t per_block = (int64_t)sh.wpb * (64 / sh.gl);
@@ -319,6 +338,85 @@ extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst
     EvalArgs a{set->d_inst, set->d_dist, set->d_proc, inst, op_off, ops, rt_off, rt_end, makespan, status,
                B, (flags & VRPRPD_ALLOW_PARTIAL) ? 1 : 0, (int32_t)nb, n_lds, sh.group_bytes,
                set->num_inst};
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     return set->dist16 ? dispatch_gl<uint16_t>(a, sh, st) : dispatch_gl<int32_t>(a, sh, st);
+}
+
+}  // namespace vrprpd
+
+using namespace vrprpd;
+
+extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                           const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                           int32_t* makespan, uint32_t* status, void* stream)
+{
+    return eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status,
+                       reinterpret_cast<hipStream_t>(stream), 0, 0);
+}
+
+extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                                    const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
+                                    int32_t* makespan, uint32_t* status, int32_t reps, int32_t* wpb_out,
+                                    int32_t* step_out, float* ms_out, void* stream)
+{
+    if (!set || B < 1 || reps < 1 || !makespan || !status)
+        return set_error(VRPRPD_EINVAL, "vrprpd_autotune_eval: need a set, B >= 1, reps >= 1 and outputs");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int n_lds = inst ? set->n_max : set->host[0].n;
+    const int m_max = inst ? set->m_max : set->host[0].m;
+    const int gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
+    const int wmax = max_wpb(n_lds, gl, set->dist16);
+    // reference outputs of the default shape, kept on the host
+    int rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, -1, kEvalStep);
+    if (rc) return rc;
+    std::vector<int32_t> mk0(B), mk1(B);
+    std::vector<uint32_t> st0(B), st1(B);
+    VRP_HIP(hipStreamSynchronize(st));
+    VRP_HIP(hipMemcpy(mk0.data(), makespan, B * 4, hipMemcpyDeviceToHost));
+    VRP_HIP(hipMemcpy(st0.data(), status, B * 4, hipMemcpyDeviceToHost));
+    hipEvent_t e0, e1;
+    VRP_HIP(hipEventCreate(&e0));
+    VRP_HIP(hipEventCreate(&e1));
+    float best = 0.f;
+    int bw = wmax, bs = kEvalStep, v = 0;
+    const int wpbs[3] = {1, 2, 4}, steps[2] = {2, 4};
+    for (int wi = 0; wi < 3; ++wi) {
+        const int w = wpbs[wi];
+        for (int si = 0; si < 2; ++si, ++v) {
+            const int k = steps[si];
+            float ms = -1.f;
+            if (w <= wmax) {
+                rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, w, k);
+                if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = set_error(VRPRPD_EHIP, "event");
+                for (int r = 0; r < reps && !rc; ++r)
+                    rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, w, k);
+                if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: timing failed");
+                if (!rc && (hipMemcpy(mk1.data(), makespan, B * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                            hipMemcpy(st1.data(), status, B * 4, hipMemcpyDeviceToHost) != hipSuccess))
+                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: copy failed");
+                if (!rc && (mk1 != mk0 || st1 != st0))
+                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: shape (%d waves, step %d) disagrees with "
+                                                "the default shape", w, k);
+                if (rc) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                ms /= (float)reps;
+                if (best == 0.f || ms < best) {
+                    best = ms;
+                    bw = w;
+                    bs = k;
+                }
+            }
+            if (ms_out) ms_out[v] = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set->eval_tuned[{n_lds, m_max}] = {bw, bs};
+    if (wpb_out) *wpb_out = bw;
+    if (step_out) *step_out = bs;
+    return VRPRPD_OK;
 }

@@ -459,14 +459,15 @@ int launch_gemm(const GemmArgs& g, int splits, hipStream_t st)
     return VRPRPD_OK;
 }
 
-// Glorot-uniform weights, zero biases: U(-a, a), a = sqrt(6 / (in + out)),
-// from Philox words (counter = parameter index, tag "MLPI").
+// Glorot-uniform hidden weights, U(-a, a) with a = sqrt(6 / (in + out)),
+// from Philox words (counter = parameter index, tag "MLPI"); zero biases and
+// a zero head, so an untrained network predicts no change for every set.
 void init_params(std::vector<float>& v, uint64_t seed)
 {
     const int dims[5] = {kIn, kHid, kHid, kHid, 1};
     const int64_t offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
     std::fill(v.begin(), v.end(), 0.f);
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < 3; ++l) {
         const double a = std::sqrt(6.0 / (dims[l] + dims[l + 1]));
         const int64_t cnt = (int64_t)dims[l] * dims[l + 1];
         for (int64_t i = 0; i < cnt; ++i) {
@@ -626,6 +627,8 @@ extern "C" int vrprpd_mlp_loss(vrprpd_mlp* h, int32_t num_sets, const int64_t* s
     if (rc) return rc;
     if (!target) return set_error(VRPRPD_EINVAL, "vrprpd_mlp_loss: target is NULL");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // rows outside every set get no gradient
+    hipLaunchKernelGGL(fill_kernel, dim3((h->rows + 255) / 256), dim3(256), 0, st, h->dy, 0.f, h->rows);
     hipLaunchKernelGGL(set_loss_kernel, dim3((num_sets + 3) / 4), dim3(256), 0, st, (int)h->rows, num_sets, 4,
                        h->head_part, h->p + kOffB4, seg_off, target, nullptr, h->dy, sq_err, nullptr);
     VRP_HIP(hipGetLastError());

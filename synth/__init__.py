@@ -321,3 +321,22 @@ def relabel_candidates(ops, rt_end, n, B, seed):
         out[s:s + b] = ((c << 1) | (o & 1)).astype(np.uint16)
         rt[s:s + b] = rt_end[src]
     return out, rt
+
+
+BATCH_RULES = ("base", "2x", "5x", "1R10", "1R20")
+
+
+def batched_instances(count: int = 256, seed: int = 4000, n_min: int = 17, n_max: int = 1000):
+    """Instances of uneven size for the batched form: n = round(exp U[ln
+    n_min, ln n_max]), m = ceil(n / 100) + 1, R = floor(n / 10), k ~
+    U_int[5, 10], processing rules cycled base/2x/5x/1R10/1R20; instance i
+    is generated with seed + i."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(g.uniform(np.log(n_min), np.log(n_max)))))
+        m = -(-n // 100) + 1
+        R = max(1, n // 10)
+        k = int(g.integers(5, 11))
+        out.append(make_instance(n, m, k, R, BATCH_RULES[i % len(BATCH_RULES)], seed=seed + i))
+    return out

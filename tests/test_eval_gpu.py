@@ -164,3 +164,21 @@ def test_eval_empty_batch(P):
     e16 = torch.empty(0, dtype=torch.uint16, device="cuda")
     mk, st = P.vrprpd_eval(S, e16, e16, B=0)
     assert mk.numel() == 0
+
+
+@pytest.mark.parametrize("n,m,B", [(100, 4, 4096), (37, 17, 2048), (1000, 10, 2048)])
+def test_autotuned_shapes_agree_with_oracle(orc, P, n, m, B):
+    """The autotuner runs every launch shape (it checks that they agree bit for
+    bit) and later launches use the chosen one; the oracle checks a sample."""
+    inst = synth.make_instance(n, m, max(2, n // m), n, "2x", seed=8800 + n)
+    ops, rt = synth.random_candidates(inst, B, seed=n)
+    S = P.InstanceSet([inst])
+    d_ops, d_rt = torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda()
+    w, k, ms = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)
+    assert w in (1, 2, 4) and k in (2, 4)
+    assert ms[{1: 0, 2: 2, 4: 4}[w] + (0 if k == 2 else 1)] > 0
+    assert ms[1] > 0                  # one wave per block, step 4: always fits
+    mk, st = gpu_eval(P, S, ops, rt)
+    pick = synth.rng(n).choice(B, size=min(B, 300), replace=False)
+    omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
+    assert np.array_equal(mk[pick], omk) and np.array_equal(st[pick], ost)

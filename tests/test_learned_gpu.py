@@ -175,3 +175,45 @@ def test_learned_chains_stay_feasible(orc, P):
     st.step(5)                         # back to the plain operator
     M.close()
     st.close()
+
+
+def test_trained_network_gains(orc, P):
+    """Plain ALNS records (removal set, makespan change) pairs; the network is
+    trained on the GPU with the library's kernels; on another run's records
+    it predicts the change better than the mean does.  Then learned and
+    plain ALNS run the same iterations from the same start: the outcome is
+    printed (the gain in makespan is a measurement, not asserted)."""
+    from paper_2602_23685_amd import learned
+    n, m, k, R = 100, 4, 5, 20
+    inst = synth.make_instance(n, m, k, R, "base", seed=7500)
+    ops, rt = synth.round_robin_solution(inst, vehicles=m)
+    S = P.InstanceSet([inst])
+    prm = P.alns_params(tuple_budget=2000, import_interval=50)
+    chains = 32
+    mk = lambda seed: P.AlnsState(S, [0], chains, prm, seed, torch.from_numpy(ops).cuda(),
+                                  torch.from_numpy(rt).cuda())
+    train_run, test_run = mk(1), mk(2)
+    n_train = learned.record(train_run, 120)
+    n_test = learned.record(test_run, 40)
+    assert n_train == 120 * chains and n_test == 40 * chains
+    _, q = train_run.record_info()
+    M = P.Mlp(max_rows=max(512 * q, chains * n), seed=5)
+    before, base = learned.held_out(M, test_run)
+    losses = learned.train(M, train_run, steps=400, batch_sets=512, lr=1e-3, momentum=0.9, log_every=100)
+    after, base2 = learned.held_out(M, test_run)
+    print(f"\nheld-out set loss: untrained {before:.3e}, trained {after:.3e}, mean predictor {base:.3e}; "
+          f"training losses {['%.3e' % x for x in losses]}")
+    assert np.isfinite(after) and after < base
+    # A/B from the same start and seed
+    plain, learn = mk(3), mk(3)
+    learn.set_learned(M, K=8, eps=0.1)
+    iters = 150
+    plain.step(iters)
+    learn.step(iters)
+    zp, zl = plain.state()["zb"], learn.state()["zb"]
+    print(f"after {iters} iterations x {chains} chains: plain best {zp.min()} mean {zp.mean():.1f}; "
+          f"learned best {zl.min()} mean {zl.mean():.1f}")
+    for st_ in (plain, learn):
+        mk_, bops, brt = st_.best()
+        assert orc.eval_one(inst, bops.cpu().numpy()[:2 * n], brt.cpu().numpy()[:m]) == (mk_, 0)
+    M.close()

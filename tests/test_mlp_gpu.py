@@ -83,11 +83,12 @@ def test_exact_network_loss_and_sgd(P):
     net = sparse_int_net(g)
     rows = 700
     X = g.integers(-2, 3, size=(rows, 64)).astype(np.float64)
-    # 64 sets of uneven size, two of them empty: S = 64 keeps 2 err / S dyadic
-    cuts = np.sort(g.integers(0, rows + 1, size=63))
+    # 64 sets of uneven size, two of them empty, the last 50 rows in none:
+    # S = 64 keeps 2 err / S dyadic
+    cuts = np.sort(g.integers(0, rows - 49, size=63))
     cuts[10] = cuts[11]
     cuts[40] = cuts[41]
-    seg = np.concatenate([[0], cuts, [rows]]).astype(np.int64)
+    seg = np.concatenate([[0], cuts, [rows - 50]]).astype(np.int64)
     y_ref, acts, _ = net.forward_mixed(X)
     # targets within 8 of the scores keep every gradient sum well inside fp32
     score0 = np.array([y_ref[seg[s]:seg[s + 1]].sum() for s in range(64)])
@@ -103,6 +104,9 @@ def test_exact_network_loss_and_sgd(P):
     M = P.Mlp(max_rows=rows, params=net.flat())
     x = dev_bf16(X)
     M.forward(x)
+    # a loss over every row first leaves row gradients behind in the handle
+    full = torch.tensor([0, rows], dtype=torch.int64, device="cuda")
+    M.loss(full, torch.zeros(1, dtype=torch.float32, device="cuda"))
     d_seg = torch.from_numpy(seg.astype(np.int64)).cuda()
     scores = M.set_scores(d_seg).cpu().numpy()
     sq = M.loss(d_seg, torch.from_numpy(target.astype(np.float32)).cuda()).cpu().numpy()
