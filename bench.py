@@ -164,7 +164,9 @@ def batched_form(P, torch, count=256, cpi=2, iters=10, gens=10, Np=128):
         pp.step(gens)
     torch.cuda.synchronize()
     t_brkga_b = time.perf_counter() - t0
-    zb_b = np.concatenate([st.state()["zb"].reshape(-1, cpi).min(axis=1) for st in states])
+    zb_b = np.zeros(count, np.int64)
+    for b, st in zip(buckets, states):
+        zb_b[b] = st.state()["zb"].reshape(-1, cpi).min(axis=1)
     # instance by instance, direct launches
     log("batched form: the same work instance by instance")
     plain, pl_pops = [], []

@@ -853,63 +853,77 @@ __global__ __launch_bounds__(256) void k_enum(AlnsDev a)
     block_sort_u64(key, npow);
     const int KD = a.KD[c], KP = a.KP[c];
     const int nd = (KD > 0 && KD < nslots) ? KD : nslots;
-    for (int k = threadIdx.x; k < nd; k += blockDim.x) dsel[k] = key[k];
+    // Pickup slots after the drop went in at (vD, pD): every other route's
+    // slots keep their drop-slot keys; route vD offers the slot right after
+    // the drop (detour 0) and its old slots p >= pD + 1, now at p + 1.  A
+    // uniform shift of p inside route vD keeps the (detour, vehicle,
+    // position) order, so each drop's ranked pickup list is the sorted
+    // drop-slot list with route vD's entries p <= pD dropped, the others of
+    // vD renumbered, and the new slot merged in: no sort per drop.  There are
+    // nslots - pD such slots.
+    int* tstart = reinterpret_cast<int*>(dsel);
+    for (int di = threadIdx.x; di < nd; di += blockDim.x) {
+        const int pD = (int)(key[di] & 0xFFFFu);
+        const int cnt = nslots - pD;
+        tstart[di] = (KP > 0 && KP < cnt) ? KP : cnt;
+    }
+    __syncthreads();
+    __shared__ int total;
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int di = 0; di < nd; ++di) {
+            const int np = tstart[di];
+            tstart[di] = t;
+            t += np;
+        }
+        total = t;
+    }
     __syncthreads();
     vrprpd_tuple* out = a.tuples + (int64_t)sidx * a.TPC;
-    int T = 0;
-    const int npslots = L + m;           // route vD keeps its len+1 slot indices, some unused
-    const int ppow = pow2_ge(npslots);
-    for (int di = 0; di < nd; ++di) {
-        const int vD = (int)((dsel[di] >> 16) & 0x3Fu), pD = (int)(dsel[di] & 0xFFFFu);
-        for (int k = threadIdx.x; k < ppow; k += blockDim.x) {
-            unsigned long long kv = ~0ull;
-            if (k < npslots) {
-                // slots of routes before vD, then vD's len+1 slots (after the drop), then the rest
-                int v = 0, p;
-                const int lenD = re[vD] - rs[vD];
-                const int startD = cum[vD];                  // slots before route vD
-                if (k < startD) {
-                    while (cum[v + 1] <= k) ++v;
-                    p = k - cum[v];
-                } else if (k < startD + lenD + 1) {
-                    v = vD;
-                    p = pD + 1 + (k - startD);
-                } else {
-                    v = vD + 1;
-                    while (cum[v + 1] <= k) ++v;
-                    p = k - cum[v];
+    for (int di = threadIdx.x; di < nd; di += blockDim.x) {
+        const unsigned long long kd = key[di];
+        const int vD = (int)((kd >> 16) & 0x3Fu), pD = (int)(kd & 0xFFFFu);
+        const int t0 = tstart[di];
+        const int np = (di + 1 < nd ? tstart[di + 1] : total) - t0;
+        const unsigned long long kw = slot_key(0, vD, pD + 1);
+        bool wait_out = false;
+        int k = 0;
+        for (int got = 0; got < np; ++got) {
+            unsigned long long kv = ~0ull;          // next slot of the sorted list that stays a pickup slot
+            while (k < nslots) {
+                const unsigned long long x = key[k];
+                const int v = (int)((x >> 16) & 0x3Fu), p = (int)(x & 0xFFFFu);
+                if (v != vD) {
+                    kv = x;
+                    break;
                 }
-                const int len = re[v] - rs[v];
-                int x, y;
-                if (v == vD) {
-                    if (p > lenD + 1) { key[k] = ~0ull; continue; }
-                    x = (p - 1 == pD) ? cust : cust_at(rs[v] + p - 2);
-                    y = (p <= lenD) ? cust_at(rs[v] + p - 1) : 0;
-                } else {
-                    x = p > 0 ? cust_at(rs[v] + p - 1) : 0;
-                    y = p < len ? cust_at(rs[v] + p) : 0;
+                if (p > pD) {
+                    kv = x + 1;                     // renumbered: position p + 1 (no carry: p < 2^16 - 1)
+                    break;
                 }
-                kv = slot_key(det(x, y), v, p);
+                ++k;                                // at or before the drop: not a pickup slot
             }
-            key[k] = kv;
+            unsigned long long pick;
+            if (!wait_out && kw < kv) {
+                pick = kw;
+                wait_out = true;
+            } else {
+                pick = kv;
+                ++k;
+            }
+            if (pick == ~0ull) break;
+            if (t0 + got < a.TPC) {
+                vrprpd_tuple t;
+                t.c = (uint16_t)cust;
+                t.vD = (uint8_t)vD;
+                t.pD = (uint16_t)pD;
+                t.vP = (uint8_t)((pick >> 16) & 0x3Fu);
+                t.pP = (uint16_t)(pick & 0xFFFFu);
+                out[t0 + got] = t;
+            }
         }
-        __syncthreads();
-        block_sort_u64(key, ppow);
-        int cntP = 0;
-        for (int k = 0; k < ppow && key[k] != ~0ull; ++k) ++cntP;
-        const int np = (KP > 0 && KP < cntP) ? KP : cntP;
-        for (int k = threadIdx.x; k < np && T + k < a.TPC; k += blockDim.x) {
-            vrprpd_tuple t;
-            t.c = (uint16_t)cust;
-            t.vD = (uint8_t)vD;
-            t.pD = (uint16_t)pD;
-            t.vP = (uint8_t)((key[k] >> 16) & 0x3Fu);
-            t.pP = (uint16_t)(key[k] & 0xFFFFu);
-            out[T + k] = t;
-        }
-        T += np;
-        __syncthreads();
     }
+    const int T = total;
     if (threadIdx.x == 0) a.seg_cnt[sidx] = T < a.TPC ? T : a.TPC;
 }
 
