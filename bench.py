@@ -43,6 +43,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_kernel_n1000_pmc_traffic.md")
+EVAL_SOURCES = ["paper_2602_23685_amd/csrc/eval.hip", "paper_2602_23685_amd/csrc/sweep.h",
+                "paper_2602_23685_amd/csrc/common.h"]
+
+
+def measured_traffic():
+    """HBM bytes per eval_kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in txt.splitlines() if l.startswith(("traffic_bytes", "kernel_sources")))
+    h = hashlib.sha256()
+    for src in EVAL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if vals.get("kernel_sources_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def make_workload(seed=3003, B=65536, T=16384, Np=4096):
     import synth
     inst = synth.make_instance(1000, 10, 10, 100, "1R20d10", seed=seed)
@@ -395,7 +418,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "traffic": None,
+            "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_bytes_per_launch": bytes_per_eval * B,
             "kernel": "eval_kernel", "kernel_ms": eval_ms, "bytes_per_unit": bytes_per_eval,
             "units_per_launch": B,
         },
