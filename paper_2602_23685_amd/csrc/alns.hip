@@ -406,12 +406,22 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a)
             key[x] = x < n ? (((unsigned long long)((1LL << 34) - gain[x + 1]) << 16) | (unsigned)(x + 1)) : ~0ull;
         __syncthreads();
         block_sort_u64(key, npow);
-        if (threadIdx.x == 0) {
-            unsigned long long tot = 0;
-            for (int i = 0; i < n && i < 1024; ++i) {
+        // total rank weight sum_{r <= min(n, 1024)} floor(2^60 / r^6): integer
+        // sums, so summing in parallel gives the same value
+        __shared__ unsigned long long wtot;
+        if (threadIdx.x == 0) wtot = 0;
+        __syncthreads();
+        {
+            unsigned long long part = 0;
+            for (int i = threadIdx.x; i < n && i < 1024; i += blockDim.x) {
                 const unsigned long long r = (unsigned long long)(i + 1);
-                tot += (1ULL << 60) / (r * r * r * r * r * r);
+                part += (1ULL << 60) / (r * r * r * r * r * r);
             }
+            atomicAdd(&wtot, part);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = wtot;
             int cnt = 0;
             for (int s2 = 0; s2 < q; ++s2) {
                 if (tot == 0) break;
@@ -592,13 +602,36 @@ __global__ __launch_bounds__(256) void k_apply(AlnsDev a, int use_scores)
     uint16_t* wrt = a.W_rt + ((int64_t)2 * c + 0) * a.M;
     const uint16_t* sops = a.S_ops + (int64_t)c * 2 * a.N;
     const uint16_t* srt = a.S_rt + (int64_t)c * a.M;
+    // W = S without the removed customers: kept-op counts per thread chunk,
+    // an exclusive scan over the chunks, then every thread copies its chunk
+    __shared__ int part[256];
+    const int L = srt[m - 1];
+    const int per = (L + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int j0 = threadIdx.x * per, j1 = min(L, j0 + per);
+    int kept = 0;
+    for (int j = j0; j < j1; ++j) kept += flag[sops[j] >> 1] ? 0 : 1;
+    part[threadIdx.x] = kept;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int w = part[threadIdx.x] - kept;
+    for (int j = j0; j < j1; ++j) {
+        const uint16_t x = sops[j];
+        if (!flag[x >> 1]) wops[w++] = x;
+    }
+    if (threadIdx.x < m) {
+        // kept ops before route end srt[v]
+        const int e = srt[threadIdx.x];
+        const int t = per > 0 ? min(e / per, (int)blockDim.x - 1) : 0;
+        int cntv = (t > 0 ? part[t - 1] : 0);
+        for (int j = t * per; j < e; ++j) cntv += flag[sops[j] >> 1] ? 0 : 1;
+        wrt[threadIdx.x] = (uint16_t)cntv;
+    }
     if (threadIdx.x == 0) {
-        int w = 0, j = 0;
-        for (int v = 0; v < m; ++v) {
-            for (; j < srt[v]; ++j)
-                if (!flag[sops[j] >> 1]) wops[w++] = sops[j];
-            wrt[v] = (uint16_t)w;
-        }
         a.W_cur[c] = 0;
         a.base_op_off[c] = ((int64_t)2 * c + 0) * 2 * a.N;
         a.base_rt_off[c] = ((int64_t)2 * c + 0) * a.M;

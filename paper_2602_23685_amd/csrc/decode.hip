@@ -159,6 +159,13 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     auto can_drop = [&]() { return veh && (q > 0 || (minpre && M < k && Lsum < R)); };
     auto can_pick = [&]() { return veh && q < k; };
     bool anyD = __ballot(can_drop()) != 0, anyP = __ballot(can_pick()) != 0;
+    // Per chunk of 64 ops in priority order each lane keeps its op's state in
+    // registers (unscheduled, and for a pickup whether its drop is scheduled),
+    // so scheduling an op needs no LDS round trip for feasibility.  The
+    // travel times to the predicted next op (the next feasible lane) are
+    // gathered while the current op is placed; lane m gathers the time from
+    // the current op's customer, which the moving vehicle will need.
+    const bool prefetch = m < 64;
     for (int pass = 0; pass < O; ++pass) {
         bool progressed = false;
         for (int base = 0; base < O; base += 64) {
@@ -167,6 +174,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
             bool unsched = j < O && !((sched[o >> 5] >> (o & 31)) & 1u);
             if (!__ballot(unsched)) continue;
             const int c = o / 2 + 1, isP = o & 1;
+            bool dropdone = isP && unsched && ((sched[(o - 1) >> 5] >> ((o - 1) & 31)) & 1u);
             int h = 0;
             if (hn && unsched) {
                 const float prod = (float)m * hn[o];
@@ -175,20 +183,40 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
             }
             const int pc = (unsched && !isP) ? P[c] : 0;
             int cursor = 0;
+            int pred_c = 0;        // customer whose travel times are prefetched (0: none)
+            int pd = 0;            // lane v < m: d[loc_v][pred_c]; lane m: d[last ci][pred_c]
+            int moved = -1;        // vehicle that moved since the prefetch
             for (;;) {
                 bool feas = false;
-                if (unsched && lane >= cursor) {
-                    if (isP) feas = anyP && ((sched[(o - 1) >> 5] >> ((o - 1) & 31)) & 1u);
-                    else feas = anyD;
-                }
+                if (unsched && lane >= cursor) feas = isP ? (anyP && dropdone) : anyD;
                 const unsigned long long mask = __ballot(feas);
                 if (!mask) break;
                 const int i = __ffsll((long long)mask) - 1;
                 const int oi = __shfl(o, i, 64), hi = __shfl(h, i, 64), pci = __shfl(pc, i, 64);
                 const int ci = oi / 2 + 1, isPi = oi & 1;
+                // travel time from each vehicle's position to ci
+                int dv;
+                if (pred_c == ci) {
+                    const int dm = __shfl(pd, m < 64 ? m : 0, 64);
+                    dv = lane == moved ? dm : pd;
+                } else {
+                    dv = veh ? (int)D[loc * N1 + ci] : 0;
+                }
+                // prefetch for the next feasible lane under the current state
+                const unsigned long long rest = i < 63 ? (mask & ~((2ull << i) - 1)) : 0ull;
+                int nc = 0;
+                if (prefetch && rest) {
+                    const int i2 = __ffsll((long long)rest) - 1;
+                    nc = __shfl(o, i2, 64) / 2 + 1;
+                }
+                int pd_next = 0;
+                if (nc) {
+                    if (veh) pd_next = (int)D[loc * N1 + nc];
+                    else if (lane == m) pd_next = (int)D[ci * N1 + nc];
+                }
                 unsigned long long pk = ~0ull;
                 if (veh) {
-                    const int arr = t + (int)D[loc * N1 + ci];
+                    const int arr = t + dv;
                     bool cand;
                     int key;
                     if (!isPi) {
@@ -227,12 +255,16 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 }
                 ++nsched;
                 if (lane == i) unsched = false;
+                if (!isPi && isP && o == oi + 1) dropdone = true;   // this pickup's drop just went in
                 cursor = i + 1;
                 progressed = true;
-                wave_lds_fence();
+                pred_c = nc;
+                pd = pd_next;
+                moved = vs;
                 anyD = __ballot(can_drop()) != 0;
                 anyP = __ballot(can_pick()) != 0;
             }
+            wave_lds_fence();   // sched[] bits of this chunk before the next chunk reads them
         }
         if (nsched == O || !progressed) break;
     }
