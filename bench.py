@@ -342,6 +342,8 @@ def main():
     init_rt = dev(w["pool_rt"][0])
     alns = P.AlnsState(S, [0], chains, P.alns_params(tuple_budget=16384), 7, init_ops, init_rt)
     stream = torch.cuda.current_stream()
+    log("autotuning the evaluation launch shape")
+    tuned = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)
     names = ["vrprpd_eval", "vrprpd_insert_scan", "brkga_decode_eval+evolve", "alns_step"]
     ev = {nm_: [] for nm_ in names}
 
@@ -409,6 +411,8 @@ def main():
             "explicit_candidates": B, "tuples": T, "population": Np, "alns_chains": chains,
             "evals_per_step": evals_per_step, "feasible_fraction": feasible,
         },
+        "eval_launch_shape": {"waves_per_block": tuned[0], "ops_per_step": tuned[1],
+                              "candidate_shapes_ms": [round(float(x), 4) for x in tuned[2]]},
         "components_ms": comp_ms,
         "component_evals_per_s": {
             "vrprpd_eval": B / (comp_ms["vrprpd_eval"] * 1e-3),

@@ -9,6 +9,8 @@
 //     turn, lanes v < m price it on vehicle v (completion time, hint-rotated
 //     tie index) and a 64-bit min-reduction picks the vehicle,
 //  4. scatters the schedule into per-vehicle sequences (optional output).
+#include <climits>
+
 #include "common.h"
 
 namespace vrprpd {
@@ -62,6 +64,16 @@ __device__ __forceinline__ bool key_ok(float x, uint32_t& bits)
     if (x == 0.0f) x = 0.0f;
     bits = __float_as_uint(x);
     return x >= 0.0f && x < 1.0f;
+}
+
+__device__ __forceinline__ int wave_min_i32(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
 }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
@@ -161,11 +173,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     bool anyD = __ballot(can_drop()) != 0, anyP = __ballot(can_pick()) != 0;
     // Per chunk of 64 ops in priority order each lane keeps its op's state in
     // registers (unscheduled, and for a pickup whether its drop is scheduled),
-    // so scheduling an op needs no LDS round trip for feasibility.  The
-    // travel times to the predicted next op (the next feasible lane) are
-    // gathered while the current op is placed; lane m gathers the time from
-    // the current op's customer, which the moving vehicle will need.
-    const bool prefetch = m < 64;
+    // so scheduling an op needs no LDS round trip for feasibility.
     for (int pass = 0; pass < O; ++pass) {
         bool progressed = false;
         for (int base = 0; base < O; base += 64) {
@@ -183,9 +191,6 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
             }
             const int pc = (unsched && !isP) ? P[c] : 0;
             int cursor = 0;
-            int pred_c = 0;        // customer whose travel times are prefetched (0: none)
-            int pd = 0;            // lane v < m: d[loc_v][pred_c]; lane m: d[last ci][pred_c]
-            int moved = -1;        // vehicle that moved since the prefetch
             for (;;) {
                 bool feas = false;
                 if (unsched && lane >= cursor) feas = isP ? (anyP && dropdone) : anyD;
@@ -194,27 +199,10 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 const int i = __ffsll((long long)mask) - 1;
                 const int oi = __shfl(o, i, 64), hi = __shfl(h, i, 64), pci = __shfl(pc, i, 64);
                 const int ci = oi / 2 + 1, isPi = oi & 1;
-                // travel time from each vehicle's position to ci
-                int dv;
-                if (pred_c == ci) {
-                    const int dm = __shfl(pd, m < 64 ? m : 0, 64);
-                    dv = lane == moved ? dm : pd;
-                } else {
-                    dv = veh ? (int)D[loc * N1 + ci] : 0;
-                }
-                // prefetch for the next feasible lane under the current state
-                const unsigned long long rest = i < 63 ? (mask & ~((2ull << i) - 1)) : 0ull;
-                int nc = 0;
-                if (prefetch && rest) {
-                    const int i2 = __ffsll((long long)rest) - 1;
-                    nc = __shfl(o, i2, 64) / 2 + 1;
-                }
-                int pd_next = 0;
-                if (nc) {
-                    if (veh) pd_next = (int)D[loc * N1 + nc];
-                    else if (lane == m) pd_next = (int)D[ci * N1 + nc];
-                }
-                unsigned long long pk = ~0ull;
+                const int dv = veh ? (int)D[loc * N1 + ci] : 0;
+                // SelectVehicle: least completion time, ties to the first
+                // vehicle at or after the hint vehicle (cyclically)
+                int kv = INT_MAX;
                 if (veh) {
                     const int arr = t + dv;
                     bool cand;
@@ -227,12 +215,12 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                         const int r = lds_load(&ready[ci]);
                         key = arr > r ? arr : r;
                     }
-                    const int rot = (lane - hi + m) % m;
-                    if (cand) pk = ((unsigned long long)(unsigned)key << 8) | (unsigned)rot;
+                    if (cand) kv = key;
                 }
-                const unsigned long long best = wave_min_u64(pk);
-                const int vs = (int)((best & 0xFFu) + hi) % m;
-                const int ks = (int)(best >> 8);
+                const int ks = wave_min_i32(kv);
+                const unsigned long long tie = __ballot(kv == ks && veh);
+                const unsigned long long upper = tie & (~0ull << hi);
+                const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
                 const int took_preload = __shfl((!isPi && q == 0) ? 1 : 0, vs, 64);
                 if (lane == vs) {
                     if (!isPi) {
@@ -258,9 +246,6 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 if (!isPi && isP && o == oi + 1) dropdone = true;   // this pickup's drop just went in
                 cursor = i + 1;
                 progressed = true;
-                pred_c = nc;
-                pd = pd_next;
-                moved = vs;
                 anyD = __ballot(can_drop()) != 0;
                 anyP = __ballot(can_pick()) != 0;
             }
