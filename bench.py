@@ -411,7 +411,7 @@ def main():
             "explicit_candidates": B, "tuples": T, "population": Np, "alns_chains": chains,
             "evals_per_step": evals_per_step, "feasible_fraction": feasible,
         },
-        "eval_launch_shape": {"waves_per_block": tuned[0], "ops_per_step": tuned[1],
+        "eval_launch_shape": {"candidates_per_wave": tuned[0], "ops_per_step": tuned[1],
                               "candidate_shapes_ms": [round(float(x), 4) for x in tuned[2]]},
         "components_ms": comp_ms,
         "component_evals_per_s": {

@@ -127,19 +127,22 @@ int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int
                 const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
                 int32_t* makespan, uint32_t* status, void* stream);
 
-/* Autotuner of vrprpd_eval's launch shape (waves per block 1, 2, 4 within
- * the LDS limit x ops per lane per sweep step 2, 4): runs every shape on the
- * caller's batch `reps` times, checks that each gives the default shape's
- * makespans and statuses bit for bit (EHIP otherwise), and keeps the fastest
- * in the set for later vrprpd_eval launches of the same (n, m) -- n, m of the
- * instance, or n_max, m_max when inst != NULL.  Arguments as vrprpd_eval;
- * outputs the chosen shape and, if ms_out != NULL, the mean milliseconds of
- * the six shapes in the order (1,2), (1,4), (2,2), (2,4), (4,2), (4,4)
- * (-1: over the LDS limit).  Synchronous; not concurrent with other calls
- * on the same set. */
+/* Autotuner of vrprpd_eval's launch shape: candidates per 64-lane wave (one
+ * wave per block; with 16-lane groups 2, 3 or 4, with 32-lane groups 1 or 2,
+ * with 64 lanes 1 -- fewer candidates per wave leave LDS room for more
+ * resident waves) x ops per lane per sweep step (2 or 4).  Runs every shape
+ * on the caller's batch `reps` times, checks that each gives the default
+ * shape's makespans and statuses bit for bit (EHIP otherwise), and keeps the
+ * fastest in the set for later vrprpd_eval launches of the same (n, m) -- n,
+ * m of the instance, or n_max, m_max when inst != NULL.  Arguments as
+ * vrprpd_eval; outputs the chosen shape and, if ms_out != NULL, the mean
+ * milliseconds of six shapes: option i of candidates per wave (i = 0..2, in
+ * the order listed) x step (2, 4), -1 where an option does not exist or its
+ * LDS does not fit.  Synchronous; not concurrent with other calls on the
+ * same set. */
 int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                          const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
-                         int32_t* makespan, uint32_t* status, int32_t reps, int32_t* wpb_out, int32_t* step_out,
+                         int32_t* makespan, uint32_t* status, int32_t reps, int32_t* ng_out, int32_t* step_out,
                          float* ms_out, void* stream);
 
 /* One way to put a removed customer back into a partial solution

@@ -186,8 +186,8 @@ def vrprpd_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None
 
 def vrprpd_autotune_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None, partial=False,
                          reps=3, stream=None):
-    """Tune vrprpd_eval's launch shape on this batch; returns (waves per
-    block, ops per step, mean ms of the six shapes)."""
+    """Tune vrprpd_eval's launch shape on this batch; returns (candidates
+    per wave, ops per step, mean ms of the six shapes)."""
     B = rt_end.shape[0]
     mk = torch.empty(B, dtype=torch.int32, device="cuda")
     st = torch.empty(B, dtype=torch.int32, device="cuda")

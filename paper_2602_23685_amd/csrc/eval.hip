@@ -1,7 +1,8 @@
 // vrprpd_eval: exact makespan of explicit candidates (Section 3, Eq. 1-23).
 //
 // Mapping: a group of GL lanes (GL = 16, 32 or 64, at least m) owns one
-// candidate; 64/GL groups share a wavefront and WPB waves form a block.
+// candidate; up to 64/GL groups share a one-wave block (candidates per wave
+// is a tuned launch parameter).
 // Phase 1 streams the candidate's ops from HBM once (coalesced, route by
 // route), checks cover with an LDS bitmap, and gathers every travel time
 // d[prev][c] in parallel into LDS, so the sweep that follows never waits on
@@ -76,21 +77,24 @@ __device__ __forceinline__ Staged stage_code(uint32_t* bits, uint32_t cd, uint32
     return Staged{ok ? cd : 0u, p * N1 + (ok ? c : 0)};
 }
 
+// One wave per block holding NG candidates (NG <= 64 / GL; lanes past NG
+// groups stay idle, so that the LDS of NG groups lets more waves reside).
 // kOneInst: every candidate uses instance 0 (no instance array), so the
 // instance's distance and processing rows are wave-uniform (scalar bases).
-template <typename DT, int GL, int WPB, int K, bool kOneInst>
-__global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
+template <typename DT, int GL, int NG, int K, bool kOneInst>
+__global__ __launch_bounds__(64) void eval_kernel(EvalArgs a)
 {
+    static_assert(NG * GL <= 64, "groups per wave");
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int G = 64 / GL;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int grp = lane / GL, li = lane % GL;
+    if (grp >= NG) return;
     const int blk = xcd_remap(blockIdx.x, a.nblocks);
-    const int64_t b = ((int64_t)blk * WPB + wave) * G + grp;
+    const int64_t b = (int64_t)blk * NG + grp;
     const bool live = b < a.B;
 
     const GroupLayout L = group_layout(a.n_max, OpStore<DT>::kBytesPerOp);
-    unsigned char* gs = smem + (size_t)(wave * G + grp) * a.group_bytes;
+    unsigned char* gs = smem + (size_t)grp * a.group_bytes;
     int* ready = reinterpret_cast<int*>(gs + L.ready_off);
     uint32_t* bits = reinterpret_cast<uint32_t*>(gs + L.bits_off);
     OpStore<DT> S;
@@ -245,72 +249,85 @@ __global__ __launch_bounds__(64 * WPB) void eval_kernel(EvalArgs a)
 constexpr int kEvalStep = 4;   // default ops per lane per sweep step
 
 struct LaunchShape {
-    int gl, wpb, group_bytes, lds, step;
+    int gl, ng, group_bytes, lds, step;
 };
 
-static int max_wpb(int n_max, int gl, int dist16)
+static int group_bytes_of(int n_max, int dist16)
 {
-    const int gb = group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
-    const int per_wave = (64 / gl) * gb;
-    int w = 4;
-    while (w > 1 && (size_t)w * per_wave > 64 * 1024) w >>= 1;
-    return w;
+    return group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
 }
 
-static LaunchShape eval_shape(int n_max, int m_max, int dist16, int wpb, int step)
+// Candidates per wave tried for a group width: 16 lanes -> 2, 3, 4; 32 -> 1, 2; 64 -> 1.
+static int ng_options(int gl, int* out)
+{
+    if (gl == 16) { out[0] = 2; out[1] = 3; out[2] = 4; return 3; }
+    if (gl == 32) { out[0] = 1; out[1] = 2; return 2; }
+    out[0] = 1;
+    return 1;
+}
+
+// Default: the most candidates per wave that still leave room for one wave
+// per SIMD (4 per CU) in LDS, else one wave per CU's worth.
+static int default_ng(int gl, int gb)
+{
+    int opts[3];
+    const int k = ng_options(gl, opts);
+    int best = opts[0];
+    for (int i = 0; i < k; ++i)
+        if ((size_t)opts[i] * gb * 4 <= kLdsPerCu) best = opts[i];
+    return best;
+}
+
+static LaunchShape eval_shape(int n_max, int m_max, int dist16, int ng, int step)
 {
     LaunchShape sh;
     sh.gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
-    sh.group_bytes = group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
-    const int per_wave = (64 / sh.gl) * sh.group_bytes;
-    sh.wpb = wpb > 0 ? wpb : max_wpb(n_max, sh.gl, dist16);
-    sh.lds = sh.wpb * per_wave;
+    sh.group_bytes = group_bytes_of(n_max, dist16);
+    sh.ng = ng > 0 ? ng : default_ng(sh.gl, sh.group_bytes);
+    sh.lds = sh.ng * sh.group_bytes;
     sh.step = step > 0 ? step : kEvalStep;
     return sh;
 }
 
-template <typename DT, int GL, int WPB, int K>
+template <typename DT, int GL, int NG, int K>
 static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
 {
-    auto* k = a.inst ? eval_kernel<DT, GL, WPB, K, false> : eval_kernel<DT, GL, WPB, K, true>;
+    auto* k = a.inst ? eval_kernel<DT, GL, NG, K, false> : eval_kernel<DT, GL, NG, K, true>;
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(64 * WPB), lds, stream, a);
+    hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(64), lds, stream, a);
     VRP_HIP(hipGetLastError());
     return VRPRPD_OK;
 }
 
-template <typename DT, int GL, int WPB>
+template <typename DT, int GL, int NG>
 static int dispatch_step(const EvalArgs& a, int step, int lds, hipStream_t st)
 {
-    return step == 2 ? launch_eval<DT, GL, WPB, 2>(a, lds, st) : launch_eval<DT, GL, WPB, 4>(a, lds, st);
-}
-
-template <typename DT, int GL>
-static int dispatch_wpb(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
-{
-    switch (sh.wpb) {
-    case 4: return dispatch_step<DT, GL, 4>(a, sh.step, sh.lds, st);
-    case 2: return dispatch_step<DT, GL, 2>(a, sh.step, sh.lds, st);
-    default: return dispatch_step<DT, GL, 1>(a, sh.step, sh.lds, st);
-    }
+    return step == 2 ? launch_eval<DT, GL, NG, 2>(a, lds, st) : launch_eval<DT, GL, NG, 4>(a, lds, st);
 }
 
 template <typename DT>
 static int dispatch_gl(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
 {
-    switch (sh.gl) {
-    case 16: return dispatch_wpb<DT, 16>(a, sh, st);
-    case 32: return dispatch_wpb<DT, 32>(a, sh, st);
-    default: return dispatch_wpb<DT, 64>(a, sh, st);
+    if (sh.gl == 16) {
+        switch (sh.ng) {
+        case 2: return dispatch_step<DT, 16, 2>(a, sh.step, sh.lds, st);
+        case 3: return dispatch_step<DT, 16, 3>(a, sh.step, sh.lds, st);
+        default: return dispatch_step<DT, 16, 4>(a, sh.step, sh.lds, st);
+        }
     }
+    if (sh.gl == 32) {
+        if (sh.ng == 1) return dispatch_step<DT, 32, 1>(a, sh.step, sh.lds, st);
+        return dispatch_step<DT, 32, 2>(a, sh.step, sh.lds, st);
+    }
+    return dispatch_step<DT, 64, 1>(a, sh.step, sh.lds, st);
 }
 
-// Validates the arguments and launches one shape (wpb, step <= 0: default).
+// Validates the arguments and launches one shape (ng, step <= 0: default).
 static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                        const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
-                       int32_t* makespan, uint32_t* status, hipStream_t st, int wpb, int step)
+                       int32_t* makespan, uint32_t* status, hipStream_t st, int ng, int step)
 {
     if (!set) return set_error(VRPRPD_EINVAL, "vrprpd_eval: set is NULL");
     if (B < 0) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B < 0");
@@ -322,17 +339,17 @@ static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, co
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: instances differ in n or m; pass op_off and rt_off");
     const int n_lds = inst ? set->n_max : set->host[0].n;
     const int m_max = inst ? set->m_max : set->host[0].m;
-    if (wpb <= 0 && step <= 0) {
+    if (ng <= 0 && step <= 0) {
         const auto it = set->eval_tuned.find({n_lds, m_max});
         if (it != set->eval_tuned.end()) {
-            wpb = it->second.first;
+            ng = it->second.first;
             step = it->second.second;
         }
     }
-    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16, wpb, step);
+    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16, ng, step);
     if ((size_t)sh.lds > kLdsPerCu)
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: n=%d needs %d B of LDS per candidate", n_lds, sh.lds);
-    const int64_t per_block = (int64_t)sh.wpb * (64 / sh.gl);
+    const int64_t per_block = sh.ng;
     const int64_t nb = (B + per_block - 1) / per_block;
     if (nb > INT32_MAX) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B too large");
     EvalArgs a{set->d_inst, set->d_dist, set->d_proc, inst, op_off, ops, rt_off, rt_end, makespan, status,
@@ -355,7 +372,7 @@ extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst
 
 extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                                     const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
-                                    int32_t* makespan, uint32_t* status, int32_t reps, int32_t* wpb_out,
+                                    int32_t* makespan, uint32_t* status, int32_t reps, int32_t* ng_out,
                                     int32_t* step_out, float* ms_out, void* stream)
 {
     if (!set || B < 1 || reps < 1 || !makespan || !status)
@@ -364,7 +381,7 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     const int n_lds = inst ? set->n_max : set->host[0].n;
     const int m_max = inst ? set->m_max : set->host[0].m;
     const int gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
-    const int wmax = max_wpb(n_lds, gl, set->dist16);
+    const int gb = group_bytes_of(n_lds, set->dist16);
     // reference outputs of the default shape, kept on the host
     int rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, -1, kEvalStep);
     if (rc) return rc;
@@ -377,14 +394,16 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     VRP_HIP(hipEventCreate(&e0));
     VRP_HIP(hipEventCreate(&e1));
     float best = 0.f;
-    int bw = wmax, bs = kEvalStep, v = 0;
-    const int wpbs[3] = {1, 2, 4}, steps[2] = {2, 4};
+    int bw = default_ng(gl, gb), bs = kEvalStep, v = 0;
+    int ngs[3];
+    const int nng = ng_options(gl, ngs);
+    const int steps[2] = {2, 4};
     for (int wi = 0; wi < 3; ++wi) {
-        const int w = wpbs[wi];
         for (int si = 0; si < 2; ++si, ++v) {
-            const int k = steps[si];
             float ms = -1.f;
-            if (w <= wmax) {
+            const int w = wi < nng ? ngs[wi] : 0;
+            const int k = steps[si];
+            if (w > 0 && (size_t)w * gb <= kLdsPerCu) {
                 rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, w, k);
                 if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = set_error(VRPRPD_EHIP, "event");
                 for (int r = 0; r < reps && !rc; ++r)
@@ -396,8 +415,8 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
                             hipMemcpy(st1.data(), status, B * 4, hipMemcpyDeviceToHost) != hipSuccess))
                     rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: copy failed");
                 if (!rc && (mk1 != mk0 || st1 != st0))
-                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: shape (%d waves, step %d) disagrees with "
-                                                "the default shape", w, k);
+                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: shape (%d candidates per wave, step %d) "
+                                                "disagrees with the default shape", w, k);
                 if (rc) {
                     (void)hipEventDestroy(e0);
                     (void)hipEventDestroy(e1);
@@ -416,7 +435,7 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set->eval_tuned[{n_lds, m_max}] = {bw, bs};
-    if (wpb_out) *wpb_out = bw;
+    if (ng_out) *ng_out = bw;
     if (step_out) *step_out = bs;
     return VRPRPD_OK;
 }

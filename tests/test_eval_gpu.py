@@ -175,9 +175,11 @@ def test_autotuned_shapes_agree_with_oracle(orc, P, n, m, B):
     S = P.InstanceSet([inst])
     d_ops, d_rt = torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda()
     w, k, ms = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)
-    assert w in (1, 2, 4) and k in (2, 4)
-    assert ms[{1: 0, 2: 2, 4: 4}[w] + (0 if k == 2 else 1)] > 0
-    assert ms[1] > 0                  # one wave per block, step 4: always fits
+    opts = [2, 3, 4] if m <= 16 else ([1, 2] if m <= 32 else [1])
+    assert w in opts and k in (2, 4)
+    assert ms[2 * opts.index(w) + (0 if k == 2 else 1)] > 0
+    assert ms[0] > 0 and ms[1] > 0    # the smallest option always fits
+    assert np.all(ms[2 * len(opts):] == -1)
     mk, st = gpu_eval(P, S, ops, rt)
     pick = synth.rng(n).choice(B, size=min(B, 300), replace=False)
     omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
