@@ -70,3 +70,28 @@ def test_product_path_never_touches_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, flags=re.M), f
                 assert "liboracle" not in txt and "oracle/" not in txt, f
+
+
+def test_host_argument_checks_of_the_newer_entry_points(lib):
+    """Argument errors are reported before any device work (no GPU needed)."""
+    import paper_2602_23685_amd as P
+    E = P._lib.EINVAL
+    h = C.c_void_p()
+    # scorer network: row capacity out of range
+    assert lib.vrprpd_mlp_create(C.byref(h), 0, None, 0) == E
+    assert b"max_rows" in lib.vrprpd_last_error()
+    assert lib.vrprpd_mlp_create(C.byref(h), (1 << 26) + 1, None, 0) == E
+    assert lib.vrprpd_mlp_forward(None, 1, None, None, None) == E
+    assert lib.vrprpd_mlp_backward(None, None, None) == E
+    assert lib.vrprpd_mlp_sgd_step(None, C.c_float(0.1), C.c_float(0.0), None) == E
+    # ALNS: learned proposal, recording, graph switch on a missing state
+    assert lib.alns_set_learned(None, None, 1, C.c_double(0.0), None) == E
+    assert lib.alns_record(None, 10, None) == E
+    assert lib.alns_record_batch(None, 1, 0, None, None, None, None) == E
+    assert lib.alns_set_graph(None, 1) == E
+    # batched BRKGA without a set; autotuner without a set
+    assert lib.brkga_state_create(C.byref(h), None, 1, None, 8, 1, 1, C.c_double(0.7), 0, None, None, None) == E
+    assert lib.brkga_state_step(None, 1, 1, None) == E
+    assert lib.vrprpd_autotune_eval(None, 1, None, None, None, None, None, 0, None, None, 1, None, None, None,
+                                    None) == E
+    assert b"autotune" in lib.vrprpd_last_error()
