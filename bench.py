@@ -133,6 +133,46 @@ def time_to_oracle_best(P, torch, iters_oracle=2000, chains=32, budget_iters=400
             "reached": bool(best is not None and best <= z_target)}
 
 
+TARGETS = os.path.join(ROOT, "tests", "golden", "oracle_targets.json")
+
+
+def race_to_oracle(P, torch, chains=32, limit_s=30.0, chunk=10):
+    """GPU ALNS (32 chains, the oracle's tuple budget per iteration) against
+    the best makespan the single-chain CPU oracle reached on the same
+    instance and start (stored by tests/golden/make_oracle_targets.py):
+    wall time until the GPU's best is at least as good."""
+    import synth
+    try:
+        targets = json.load(open(TARGETS))
+    except OSError:
+        return None
+    out = {}
+    for name, c in targets.items():
+        inst = synth.make_instance(c["n"], c["m"], c["k"], c["R"], c["rule"], seed=c["seed"])
+        ops, rt = synth.round_robin_solution(inst, vehicles=min(c["m"], c["R"]))
+        S = P.InstanceSet([inst])
+        st = P.AlnsState(S, [0], chains, P.alns_params(tuple_budget=c["budget"]), 99,
+                         torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
+        st.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, best = 1, None
+        while time.perf_counter() - t0 < limit_s:
+            st.step(chunk)
+            done += chunk
+            best = int(st.state()["zb"].min())
+            if best <= c["z_oracle"]:
+                break
+        t = time.perf_counter() - t0
+        out[name] = {"n": c["n"], "m": c["m"], "k": c["k"], "R": c["R"], "rule": c["rule"],
+                     "tuple_budget": c["budget"], "z_start": c["z_start"], "z_oracle": c["z_oracle"],
+                     "oracle_iterations": c["iterations"], "oracle_chains": 1,
+                     "oracle_seconds": c["oracle_seconds"], "gpu_chains": chains, "gpu_iterations": done,
+                     "gpu_seconds": t, "gpu_best": best, "reached": bool(best is not None and best <= c["z_oracle"])}
+        st.close()
+    return out
+
+
 def _multi_init(insts, ids, synth, torch):
     """Initial solutions of instances `ids` laid out for a multi-instance
     ALNS state (stride 2 n_max ops, m_max route ends)."""
@@ -432,6 +472,8 @@ def main():
     if not args.no_race:
         log("time to oracle-best (n=16)")
         out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
+        log("time to oracle-best (n=100, n=1000)")
+        out["time_to_oracle_best_large"] = race_to_oracle(P, torch)
     if not args.no_forms:
         out["batched_form"] = batched_form(P, torch)
         out["learned_form"] = learned_form(P, torch)

@@ -88,7 +88,8 @@ class AlnsParams(C.Structure):
                 ("stag_limit", C.c_int32), ("tau", C.c_int32), ("r", C.c_double),
                 ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
                 ("w_min", C.c_double), ("q_min", C.c_int32), ("q_max", C.c_int32),
-                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32)]
+                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32),
+                ("ls_repos_interval", C.c_int32), ("ls_reloc_interval", C.c_int32), ("ls_budget", C.c_int32)]
 
 
 def alns_params(**kw):
@@ -97,7 +98,8 @@ def alns_params(**kw):
     sigma = (33, 9, 13), minimum weight 0.1, intra-GPU import every 1000."""
     d = dict(T0=0.30, alpha=0.9998, reheat=0.50, gate=0.01, stag_limit=2000, tau=100, r=0.1,
              sigma1=33, sigma2=9, sigma3=13, w_min=0.1, q_min=0, q_max=0, tuple_budget=0,
-             import_interval=1000, op_mask=0x0F3F)
+             import_interval=1000, op_mask=0x0F3F,
+             ls_repos_interval=200, ls_reloc_interval=500, ls_budget=16384)
     d.update(kw)
     return AlnsParams(**d)
 
@@ -110,6 +112,8 @@ def _declare_alns(L):
     L.orc_det_exp.argtypes = [C.c_double]
     L.orc_alns_qrange.restype = None
     L.orc_alns_qrange.argtypes = [C.c_int, P, P]
+    L.orc_alns_local_search.restype = C.c_int32
+    L.orc_alns_local_search.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P]
     L.orc_alns_destroy.restype = C.c_int32
     L.orc_alns_destroy.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                    C.c_int32, P]
@@ -137,6 +141,21 @@ def alns_destroy(inst, op, ops, rt_end, q, q_min, seed, it, chain, cand=0):
     if cnt < 0:
         raise ValueError("solution is not feasible")
     return [int(x) for x in rem[:cnt]]
+
+
+def alns_local_search(inst, kind, ops, rt_end, budget=16384, passes=3):
+    """(improving passes, makespan, ops, rt_end) of the periodic local search
+    (kind 0 pickup repositioning, 1 cross-agent relocation)."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    oo = np.zeros(2 * oi.n, np.uint16)
+    orr = np.zeros(oi.m, np.uint16)
+    z = np.zeros(1, np.int32)
+    k = lib().orc_alns_local_search(oi.ref, kind, budget, passes, _ptr(ops), _ptr(rt), _ptr(oo), _ptr(orr), _ptr(z))
+    if k < 0:
+        raise ValueError("solution is not feasible")
+    return int(k), int(z[0]), oo[:int(orr[-1])], orr
 
 
 def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False):

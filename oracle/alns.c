@@ -416,6 +416,157 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
     return cnt;
 }
 
+/* ------------------------------------------------------------------ local search */
+/* One pass of a periodic local search (Section 4.2.5) on the current
+ * solution S.  kind 0, pickup repositioning: every pickup on a vehicle that
+ * returns within 5% of the makespan (20 f_v >= 19 z), in route order, may
+ * move to any pickup slot of any vehicle (after its drop on the drop's
+ * vehicle).  kind 1, cross-agent relocation: every customer with an op on
+ * the bottleneck vehicle (latest return, lowest index on ties), in order of
+ * first appearance, may move both ops to another vehicle.  Candidate slots
+ * are ranked by detour as in the repair (reading 22) with T = max(1, budget
+ * / #candidates) tuples per candidate (relocation: K_D = max(1, floor(sqrt
+ * T)) drop slots, K_P = max(1, T / K_D) pickup slots on the drop's vehicle).
+ * The exactly evaluated feasible move with the lowest makespan (ties: earlier
+ * candidate, then earlier tuple) replaces S if it is strictly better.
+ * Returns 1 if S improved. */
+static int ls_pass(const orc_inst* I, int kind, int budget, sol_t* S, int32_t* z, sol_t* base, sol_t* cand,
+                   slot_t* dbuf, slot_t* pbuf, int* cands, unsigned char* gone)
+{
+    const int n = I->n, m = I->m;
+    int64_t* times = malloc((size_t)(S->L + 1) * sizeof(int64_t));
+    int32_t zz;
+    sol_eval(I, S, &zz, times);
+    long long fin[64];
+    for (int v = 0; v < m; ++v) {
+        const int e = S->rt[v];
+        fin[v] = rlen(S, v) > 0 ? times[e - 1] + I->d[(S->ops[e - 1] >> 1) * (n + 1)] : 0;
+    }
+    free(times);
+    int nc = 0, b = 0;
+    for (int v = 1; v < m; ++v)
+        if (fin[v] > fin[b]) b = v;
+    memset(gone, 0, (size_t)n + 1);
+    if (kind == 0) {
+        for (int v = 0; v < m; ++v) {
+            if (20 * fin[v] < 19 * (long long)zz) continue;
+            for (int j = rstart(S, v); j < S->rt[v]; ++j)
+                if (S->ops[j] & 1) cands[nc++] = S->ops[j] >> 1;
+        }
+    } else {
+        for (int j = rstart(S, b); j < S->rt[b]; ++j) {
+            const int c = S->ops[j] >> 1;
+            if (!gone[c]) {
+                gone[c] = 1;
+                cands[nc++] = c;
+            }
+        }
+        memset(gone, 0, (size_t)n + 1);
+    }
+    if (nc == 0) return 0;
+    const long long T = budget / nc > 1 ? budget / nc : 1;
+    int32_t best_mk = zz;
+    int best_i = -1;
+    orc_tuple best_t = {0, 0, 0, 0, 0};
+    for (int i = 0; i < nc; ++i) {
+        const int c = cands[i];
+        gone[c] = 1;
+        sol_remove(S, gone, m, base);
+        gone[c] = 0;
+        int cnt = 0;
+        orc_tuple tl;
+        tl.c = (uint16_t)c;
+        if (kind == 0) {
+            /* the drop keeps its vehicle and position (removing the pickup,
+             * which follows it on its own route, shifts nothing before it) */
+            int vD = 0, pD = 0;
+            for (int v = 0; v < m; ++v)
+                for (int j = rstart(S, v); j < S->rt[v]; ++j)
+                    if (S->ops[j] == (uint16_t)(c << 1)) { vD = v; pD = j - rstart(S, v); }
+            int np = 0;
+            for (int v = 0; v < m; ++v) {
+                const int s0 = rstart(base, v), len = rlen(base, v);
+                if (v == vD) {
+                    for (int p = pD + 1; p <= len + 1; ++p) {
+                        int a = (p - 1 == pD) ? c : base->ops[s0 + p - 2] >> 1;
+                        int bb = (p <= len) ? base->ops[s0 + p - 1] >> 1 : 0;
+                        pbuf[np].det = detour(I, a, c, bb); pbuf[np].v = v; pbuf[np].p = p; ++np;
+                    }
+                } else {
+                    for (int p = 0; p <= len; ++p) {
+                        int a = p > 0 ? base->ops[s0 + p - 1] >> 1 : 0;
+                        int bb = p < len ? base->ops[s0 + p] >> 1 : 0;
+                        pbuf[np].det = detour(I, a, c, bb); pbuf[np].v = v; pbuf[np].p = p; ++np;
+                    }
+                }
+            }
+            qsort(pbuf, (size_t)np, sizeof(slot_t), cmp_slot);
+            if (np > T) np = (int)T;
+            for (int k = 0; k < np; ++k, ++cnt) {
+                tl.vD = (uint8_t)vD; tl.pD = (uint16_t)pD; tl.vP = (uint8_t)pbuf[k].v; tl.pP = (uint16_t)pbuf[k].p;
+                sol_insert(base, &tl, m, cand);
+                int32_t mk;
+                if (sol_eval(I, cand, &mk, NULL) == 0 && mk < best_mk) { best_mk = mk; best_i = i; best_t = tl; }
+            }
+        } else {
+            int KD = (int)floor(sqrt((double)T));
+            if (KD < 1) KD = 1;
+            int KP = (int)(T / KD);
+            if (KP < 1) KP = 1;
+            int nd = 0;
+            for (int v = 0; v < m; ++v) {
+                if (v == b) continue;
+                const int s0 = rstart(base, v), len = rlen(base, v);
+                for (int p = 0; p <= len; ++p) {
+                    int a = p > 0 ? base->ops[s0 + p - 1] >> 1 : 0;
+                    int bb = p < len ? base->ops[s0 + p] >> 1 : 0;
+                    dbuf[nd].det = detour(I, a, c, bb); dbuf[nd].v = v; dbuf[nd].p = p; ++nd;
+                }
+            }
+            qsort(dbuf, (size_t)nd, sizeof(slot_t), cmp_slot);
+            if (nd > KD) nd = KD;
+            for (int di = 0; di < nd; ++di) {
+                const int vD = dbuf[di].v, pD = dbuf[di].p;
+                const int s0 = rstart(base, vD), len = rlen(base, vD);
+                int np = 0;
+                for (int p = pD + 1; p <= len + 1; ++p) {
+                    int a = (p - 1 == pD) ? c : base->ops[s0 + p - 2] >> 1;
+                    int bb = (p <= len) ? base->ops[s0 + p - 1] >> 1 : 0;
+                    pbuf[np].det = detour(I, a, c, bb); pbuf[np].v = vD; pbuf[np].p = p; ++np;
+                }
+                qsort(pbuf, (size_t)np, sizeof(slot_t), cmp_slot);
+                if (np > KP) np = KP;
+                for (int k = 0; k < np; ++k, ++cnt) {
+                    tl.vD = (uint8_t)vD; tl.pD = (uint16_t)pD; tl.vP = (uint8_t)vD; tl.pP = (uint16_t)pbuf[k].p;
+                    sol_insert(base, &tl, m, cand);
+                    int32_t mk;
+                    if (sol_eval(I, cand, &mk, NULL) == 0 && mk < best_mk) { best_mk = mk; best_i = i; best_t = tl; }
+                }
+            }
+        }
+        (void)cnt;
+    }
+    if (best_i < 0) return 0;
+    gone[cands[best_i]] = 1;
+    sol_remove(S, gone, m, base);
+    gone[cands[best_i]] = 0;
+    sol_insert(base, &best_t, m, S);
+    *z = best_mk;
+    return 1;
+}
+
+/* Up to three passes of one kind; returns 1 if S improved. */
+static int local_search(const orc_inst* I, int kind, int budget, sol_t* S, int32_t* z, sol_t* base, sol_t* cand,
+                        slot_t* dbuf, slot_t* pbuf, int* cands, unsigned char* gone)
+{
+    int any = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        if (!ls_pass(I, kind, budget, S, z, base, cand, dbuf, pbuf, cands, gone)) break;
+        any = 1;
+    }
+    return any;
+}
+
 /* ------------------------------------------------------------------ repair */
 /* Returns 1 on success (S complete), 0 if some customer had no feasible tuple. */
 static int repair(const orc_inst* I, int op, sol_t* S, int* rem, int nrem, int KD, int KP,
@@ -637,6 +788,19 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
                 tr[2] = c->zb;
                 tr[3] = di | (ri << 8) | (accepted << 16) | ((int64_t)nrem << 24);
             }
+            /* periodic local search on the current solution (Section 4.2.5):
+             * repositioning before relocation when both fall due */
+            int ls_any = 0;
+            if (P->ls_repos_interval > 0 && (it + 1) % P->ls_repos_interval == 0)
+                ls_any |= local_search(I, 0, P->ls_budget, &c->S, &c->z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
+            if (P->ls_reloc_interval > 0 && (it + 1) % P->ls_reloc_interval == 0)
+                ls_any |= local_search(I, 1, P->ls_budget, &c->S, &c->z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
+            if (ls_any && c->z < c->zb) {
+                sol_copy(&c->B, &c->S, m);
+                c->zb = c->z;
+                c->stag = 0;
+            }
+            memset(gone, 0, (size_t)n + 1);
         }
         if (P->import_interval > 0 && (it + 1) % P->import_interval == 0) {
             int bc = 0;
@@ -693,5 +857,41 @@ int32_t orc_alns_destroy(const orc_inst* I, int32_t op, const uint16_t* ops, con
     }
     sol_free(&S);
     sol_free(&tmp);
+    return rc;
+}
+
+
+/* Periodic local search (kind 0 pickup repositioning, 1 cross-agent
+ * relocation) on a complete feasible solution, up to `passes` passes;
+ * writes the result to out_ops / out_rt and its makespan to *z.  Returns the
+ * number of improving passes, or -1 if the solution is not feasible. */
+int32_t orc_alns_local_search(const orc_inst* I, int32_t kind, int32_t budget, int32_t passes, const uint16_t* ops,
+                              const uint16_t* rt_end, uint16_t* out_ops, uint16_t* out_rt, int32_t* z)
+{
+    const int n = I->n, m = I->m;
+    sol_t S, base, cand;
+    sol_alloc(&S, n, m);
+    sol_alloc(&base, n, m);
+    sol_alloc(&cand, n, m);
+    S.L = rt_end[m - 1];
+    memcpy(S.ops, ops, (size_t)S.L * sizeof(uint16_t));
+    memcpy(S.rt, rt_end, (size_t)m * sizeof(uint16_t));
+    int rc = -1;
+    if (sol_eval(I, &S, z, NULL) == 0) {
+        const int maxslots = 2 * n + m + 2;
+        slot_t* dbuf = malloc((size_t)maxslots * sizeof(slot_t));
+        slot_t* pbuf = malloc((size_t)maxslots * sizeof(slot_t));
+        int* cands = malloc((size_t)(n + 1) * sizeof(int));
+        unsigned char* gone = calloc((size_t)n + 1, 1);
+        rc = 0;
+        for (int p = 0; p < passes; ++p) {
+            if (!ls_pass(I, kind, budget, &S, z, &base, &cand, dbuf, pbuf, cands, gone)) break;
+            ++rc;
+        }
+        free(dbuf); free(pbuf); free(cands); free(gone);
+    }
+    memcpy(out_ops, S.ops, (size_t)S.L * sizeof(uint16_t));
+    memcpy(out_rt, S.rt, (size_t)m * sizeof(uint16_t));
+    sol_free(&S); sol_free(&base); sol_free(&cand);
     return rc;
 }

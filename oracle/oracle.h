@@ -84,6 +84,9 @@ typedef struct {
     int32_t tuple_budget;      /* tuples per iteration; 0: every slot pair */
     int32_t import_interval;   /* 0: never */
     uint32_t op_mask;          /* destroy ops bits 0-5, repair ops bits 8-11 */
+    int32_t ls_repos_interval; /* pickup repositioning every this many iterations; 0: never */
+    int32_t ls_reloc_interval; /* cross-agent relocation every this many iterations; 0: never */
+    int32_t ls_budget;         /* tuples per local-search pass (> 0) */
 } orc_alns_params;
 
 double orc_det_exp(double x);
@@ -97,6 +100,11 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
  * written to rem, or -1 if the solution is infeasible. */
 int32_t orc_alns_destroy(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, int32_t q,
                          int32_t q_min, uint64_t seed, uint32_t it, uint32_t chain, int32_t cand, int32_t* rem);
+/* Periodic local search (Section 4.2.5) on a complete feasible solution: kind
+ * 0 pickup repositioning, 1 cross-agent relocation, up to `passes` passes of
+ * `budget` tuples.  Returns the number of improving passes (-1: infeasible). */
+int32_t orc_alns_local_search(const orc_inst* I, int32_t kind, int32_t budget, int32_t passes, const uint16_t* ops,
+                              const uint16_t* rt_end, uint16_t* out_ops, uint16_t* out_rt, int32_t* z);
 
 /* Warm-start population from one solution (Section 4.4.4). */
 void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,

@@ -335,13 +335,15 @@ class AlnsParams(C.Structure):
                 ("stag_limit", C.c_int32), ("tau", C.c_int32), ("r", C.c_double),
                 ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
                 ("w_min", C.c_double), ("q_min", C.c_int32), ("q_max", C.c_int32),
-                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32)]
+                ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32),
+                ("ls_repos_interval", C.c_int32), ("ls_reloc_interval", C.c_int32), ("ls_budget", C.c_int32)]
 
 
 def alns_params(**kw):
     d = dict(T0=0.30, alpha=0.9998, reheat=0.50, gate=0.01, stag_limit=2000, tau=100, r=0.1,
              sigma1=33, sigma2=9, sigma3=13, w_min=0.1, q_min=0, q_max=0, tuple_budget=0,
-             import_interval=1000, op_mask=0x0F3F)
+             import_interval=1000, op_mask=0x0F3F,
+             ls_repos_interval=200, ls_reloc_interval=500, ls_budget=16384)
     d.update(kw)
     return AlnsParams(**d)
 
