@@ -308,7 +308,25 @@ int brkga_state_destroy(brkga_state* st);
  * 13), w_min = 0.1, q_min = q_max = 0 (the rule of Section 4.2.2:
  * q_max = max(4, floor(0.05 n)), q_min = max(4, floor(q_max / 2))),
  * tuple_budget = 0 (every slot pair), import_interval = 1000,
- * op_mask = 0x0F3F (all six destroy and four repair operators).
+ * op_mask = 0x0F3F (all six destroy and four repair operators),
+ * ls_repos_interval = 200, ls_reloc_interval = 500, ls_budget = 16384.
+ *
+ * Periodic local search (Section 4.2.5), after the acceptance step of every
+ * ls_repos_interval-th (pickup repositioning) and ls_reloc_interval-th
+ * (cross-agent relocation) iteration, repositioning first; 0 turns one off.
+ * Up to three passes each, on the chain's current solution, no acceptance
+ * test: a pass takes the best strictly improving move.  Repositioning: every
+ * pickup on a vehicle returning within 5% of the makespan (20 f_v >= 19 z)
+ * may move to any pickup slot of any vehicle (after its drop on the drop's
+ * vehicle); relocation: every customer with an op on the bottleneck vehicle
+ * (latest return, lowest index on ties) may move both ops to one other
+ * vehicle.  At most the first 256 candidates (route order) are tried per
+ * pass.  Slots are ranked by detour as in the repair, T = max(1,
+ * ls_budget / candidates) tuples per candidate (relocation: K_D =
+ * max(1, floor(sqrt T)) drop slots x K_P = max(1, T / K_D) pickup slots);
+ * ties between moves go to the earlier candidate (route order), then the
+ * earlier tuple.  A new best resets the stagnation counter.  ls_budget must
+ * be >= 1 when either interval is on.
  *
  * One iteration of a chain (Algorithm 1): roulette-select a destroy and a
  * repair operator by weight; draw q in [q_min, q_max]; destroy (random,
@@ -335,6 +353,9 @@ typedef struct {
     int32_t tuple_budget;
     int32_t import_interval;
     uint32_t op_mask;
+    int32_t ls_repos_interval;
+    int32_t ls_reloc_interval;
+    int32_t ls_budget;
 } alns_params;
 
 typedef struct alns_state alns_state;

@@ -417,13 +417,15 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
 }
 
 /* ------------------------------------------------------------------ local search */
+#define LS_MAX_CAND 256   /* candidates per pass: the first 256 in order */
 /* One pass of a periodic local search (Section 4.2.5) on the current
  * solution S.  kind 0, pickup repositioning: every pickup on a vehicle that
  * returns within 5% of the makespan (20 f_v >= 19 z), in route order, may
  * move to any pickup slot of any vehicle (after its drop on the drop's
  * vehicle).  kind 1, cross-agent relocation: every customer with an op on
  * the bottleneck vehicle (latest return, lowest index on ties), in order of
- * first appearance, may move both ops to another vehicle.  Candidate slots
+ * first appearance, may move both ops to another vehicle.  Only the first
+ * 256 candidates are tried.  Candidate slots
  * are ranked by detour as in the repair (reading 22) with T = max(1, budget
  * / #candidates) tuples per candidate (relocation: K_D = max(1, floor(sqrt
  * T)) drop slots, K_P = max(1, T / K_D) pickup slots on the drop's vehicle).
@@ -463,6 +465,7 @@ static int ls_pass(const orc_inst* I, int kind, int budget, sol_t* S, int32_t* z
         }
         memset(gone, 0, (size_t)n + 1);
     }
+    if (nc > LS_MAX_CAND) nc = LS_MAX_CAND;
     if (nc == 0) return 0;
     const long long T = budget / nc > 1 ? budget / nc : 1;
     int32_t best_mk = zz;

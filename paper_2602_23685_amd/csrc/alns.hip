@@ -960,6 +960,45 @@ __global__ __launch_bounds__(256) void k_enum(AlnsDev a)
     if (threadIdx.x == 0) a.seg_cnt[sidx] = T < a.TPC ? T : a.TPC;
 }
 
+// dst = src with the tuple's drop and pickup spliced in (the insertion the
+// scan priced).  Called by every thread of a block.
+__device__ void splice_tuple(const uint16_t* src, const uint16_t* srt, int m, const vrprpd_tuple tp, uint16_t* dst,
+                             uint16_t* drt)
+{
+    __shared__ int nstart[kMaxM + 1];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int w = 0;
+        for (int v = 0; v < m; ++v) {
+            nstart[v] = w;
+            const int len = srt[v] - (v ? srt[v - 1] : 0);
+            w += len + (v == tp.vD) + (v == tp.vP);
+            drt[v] = (uint16_t)w;
+        }
+        nstart[m] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int v = threadIdx.x;
+        const int s = v ? srt[v - 1] : 0, len = srt[v] - s;
+        const int w = nstart[v];
+        // virtual positions of the inserted ops on this route
+        int x1 = kNoPos, x2 = kNoPos;
+        uint16_t k1 = 0, k2 = 0;
+        if (v == tp.vD && v == tp.vP) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); x2 = tp.pP; k2 = (uint16_t)((tp.c << 1) | 1); }
+        else if (v == tp.vD) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); }
+        else if (v == tp.vP) { x1 = tp.pP; k1 = (uint16_t)((tp.c << 1) | 1); }
+        const int vlen = len + (x1 != kNoPos) + (x2 != kNoPos);
+        for (int i = 0; i < vlen; ++i) {
+            uint16_t code;
+            if (i == x1) code = k1;
+            else if (i == x2) code = k2;
+            else code = src[s + i - (i > x1) - (i > x2)];
+            dst[w + i] = code;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- select
 // Block per chain: price every waiting customer from the scan results, pick
 // one by the repair operator's rule, insert it into W.
@@ -1039,41 +1078,8 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
     // insert the chosen tuple into the other W buffer
     const vrprpd_tuple tp = a.tuples[(uint32_t)(best_key & 0xFFFFFFFFll)];
     const int wb = a.W_cur[c];
-    const uint16_t* src = a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N;
-    const uint16_t* srt = a.W_rt + ((int64_t)2 * c + wb) * a.M;
-    uint16_t* dst = a.W_ops + ((int64_t)2 * c + (wb ^ 1)) * 2 * a.N;
-    uint16_t* drt = a.W_rt + ((int64_t)2 * c + (wb ^ 1)) * a.M;
-    __shared__ int nstart[kMaxM + 1];
-    if (threadIdx.x == 0) {
-        int w = 0;
-        for (int v = 0; v < m; ++v) {
-            nstart[v] = w;
-            const int len = srt[v] - (v ? srt[v - 1] : 0);
-            w += len + (v == tp.vD) + (v == tp.vP);
-            drt[v] = (uint16_t)w;
-        }
-        nstart[m] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < m) {
-        const int v = threadIdx.x;
-        const int s = v ? srt[v - 1] : 0, len = srt[v] - s;
-        int w = nstart[v];
-        // virtual positions of the inserted ops on this route
-        int x1 = kNoPos, x2 = kNoPos;
-        uint16_t k1 = 0, k2 = 0;
-        if (v == tp.vD && v == tp.vP) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); x2 = tp.pP; k2 = (uint16_t)((tp.c << 1) | 1); }
-        else if (v == tp.vD) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); }
-        else if (v == tp.vP) { x1 = tp.pP; k1 = (uint16_t)((tp.c << 1) | 1); }
-        const int vlen = len + (x1 != kNoPos) + (x2 != kNoPos);
-        for (int i = 0; i < vlen; ++i) {
-            uint16_t code;
-            if (i == x1) code = k1;
-            else if (i == x2) code = k2;
-            else code = src[s + i - (i > x1) - (i > x2)];
-            dst[w + i] = code;
-        }
-    }
+    splice_tuple(a.W_ops + ((int64_t)2 * c + wb) * 2 * a.N, a.W_rt + ((int64_t)2 * c + wb) * a.M, m, tp,
+                 a.W_ops + ((int64_t)2 * c + (wb ^ 1)) * 2 * a.N, a.W_rt + ((int64_t)2 * c + (wb ^ 1)) * a.M);
     __syncthreads();
     if (threadIdx.x == 0) {
         a.W_cur[c] = wb ^ 1;
