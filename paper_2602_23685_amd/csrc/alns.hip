@@ -79,6 +79,16 @@ struct AlnsDev {
     float* rec_t;                  // [rec_cap] (z' - z) / z
     int32_t* rec_n;                // [rec_cap] removed customers
     int64_t rec_cap, rec_base;     // capacity in sets; iteration of the first record
+    // periodic local search (Section 4.2.5); buffers exist when an interval is on
+    int32_t LQ;                    // candidates per pass at most
+    int64_t LB;                    // tuple slots per chain
+    uint16_t *ls_ops, *ls_rt;      // [C][LQ][2N], [C][LQ][M]: bases S without one candidate
+    int32_t *ls_cand, *ls_pd;      // [C][LQ]: customer; its drop's (vehicle << 16 | position) in S
+    int32_t *ls_nc, *ls_T, *ls_KD, *ls_KP, *ls_b, *ls_active, *ls_any;   // [C]
+    int32_t *ls_base_inst, *ls_seg_base, *ls_seg_cnt, *ls_tmk;          // [C][LQ] / [C][LB]
+    uint32_t* ls_tst;
+    int64_t *ls_seg_off, *ls_base_off, *ls_rt_off, *ls_top3;            // [C][LQ] (top3: x3)
+    vrprpd_tuple* ls_tuples;       // [C][LB]
 };
 
 __device__ __forceinline__ uint32_t adraw(uint64_t seed, uint32_t a, uint32_t it, uint32_t chain)
@@ -1093,6 +1103,330 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
     }
 }
 
+// ---------------------------------------------------------------- local search
+// Periodic local search on each chain's current solution (Section 4.2.5):
+// kind 0 pickup repositioning, kind 1 cross-agent relocation.  A pass is
+// setup (schedule, candidates, one base S without the candidate per
+// candidate), enumeration of ranked tuples per candidate, the insertion scan
+// over all (chain, candidate) segments, and apply (the best strictly
+// improving move replaces S).  A chain whose pass finds nothing stops.
+constexpr int kLsMaxCand = 256;
+
+__global__ void k_ls_begin(AlnsDev a, int reset_any)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    a.ls_active[c] = 1;
+    if (reset_any) a.ls_any[c] = 0;
+}
+
+template <typename DT>
+__global__ __launch_bounds__(256) void k_ls_setup(AlnsDev a, int kind)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x;
+    if (!a.ls_active[c]) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    Carve cv{smem};
+    int* times = cv.take<int>(2 * a.N + kAlnsStep);
+    int* pblk = cv.take<int>(a.N + 1);
+    uint16_t* posD = cv.take<uint16_t>(a.N + 2);
+    uint16_t* posP = cv.take<uint16_t>(a.N + 2);
+    int* rs = cv.take<int>(kMaxM);
+    int* re = cv.take<int>(kMaxM);
+    long long* fin = cv.take<long long>(kMaxM);
+    int* ready = cv.take<int>(a.N + 1);
+    unsigned char* seen = cv.take<unsigned char>(a.N + 1);
+    int* cand = cv.take<int>(kLsMaxCand);
+    unsigned char* ops_base = cv.take<unsigned char>((size_t)OpStore<DT>::kBytesPerOp * (2 * a.N + kAlnsStep));
+    __shared__ int sh_nc;
+    OpStore<DT> S;
+    S.init(ops_base, 2 * a.N + kAlnsStep);
+    const int L = stage_solution(S, a.S_ops + (int64_t)c * 2 * a.N, a.S_rt + (int64_t)c * a.M, m, D, N1, rs, re);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const uint32_t cd = S.code(j);
+        if (cd & 1u) posP[cd >> 1] = (uint16_t)j;
+        else posD[cd >> 1] = (uint16_t)j;
+    }
+    for (int x = threadIdx.x; x <= n; x += blockDim.x) {
+        pblk[x] = x ? P[x] : 0;
+        ready[x] = -1;
+        seen[x] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int ret;
+        const auto R = del_route<DT, true>(S, rs, re, threadIdx.x, m, posD, posP, 0, D, N1, times, ret);
+        (void)sweep_route<kAlnsStep, 64>(R, ready, pblk, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int v = threadIdx.x;
+        fin[v] = re[v] > rs[v] ? (long long)times[re[v] - 1] + (long long)D[(int)(S.code(re[v] - 1) >> 1) * N1] : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long z = 0;
+        int b = 0;
+        for (int v = 0; v < m; ++v) {
+            if (fin[v] > z) z = fin[v];
+            if (fin[v] > fin[b]) b = v;
+        }
+        int nc = 0;
+        if (kind == 0) {
+            for (int v = 0; v < m && nc < kLsMaxCand; ++v) {
+                if (20 * fin[v] < 19 * z) continue;
+                for (int j = rs[v]; j < re[v] && nc < kLsMaxCand; ++j)
+                    if (S.code(j) & 1u) cand[nc++] = (int)(S.code(j) >> 1);
+            }
+        } else {
+            for (int j = rs[b]; j < re[b] && nc < kLsMaxCand; ++j) {
+                const int cu = (int)(S.code(j) >> 1);
+                if (!seen[cu]) {
+                    seen[cu] = 1;
+                    cand[nc++] = cu;
+                }
+            }
+        }
+        sh_nc = nc;
+        a.ls_nc[c] = nc;
+        a.ls_b[c] = b;
+        if (nc == 0) {
+            a.ls_active[c] = 0;
+        } else {
+            long long T = (long long)a.prm.ls_budget / nc;
+            if (T < 1) T = 1;
+            int KD = (int)floor(sqrt((double)T));
+            if (KD < 1) KD = 1;
+            int KP = (int)(T / KD);
+            if (KP < 1) KP = 1;
+            a.ls_T[c] = (int)T;
+            a.ls_KD[c] = KD;
+            a.ls_KP[c] = KP;
+        }
+    }
+    __syncthreads();
+    const int nc = sh_nc;
+    const int T = nc ? a.ls_T[c] : 0;
+    for (int i = 0; i < a.LQ; ++i) {
+        const int64_t idx = (int64_t)c * a.LQ + i;
+        if (i >= nc) {
+            if (threadIdx.x == 0) {
+                a.ls_seg_cnt[idx] = 0;
+                a.ls_seg_off[idx] = (int64_t)c * a.LB;
+            }
+            continue;
+        }
+        const int cu = cand[i];
+        const int jd = posD[cu], jp = posP[cu];
+        const int lo = jd < jp ? jd : jp, hi = jd < jp ? jp : jd;
+        uint16_t* bo = a.ls_ops + idx * 2 * a.N;
+        uint16_t* br = a.ls_rt + idx * a.M;
+        for (int j = threadIdx.x; j < L - 2; j += blockDim.x) {
+            const int src = j + (j >= lo) + (j >= hi - 1);
+            bo[j] = (uint16_t)S.code(src);
+        }
+        if (threadIdx.x < m) {
+            const int e = re[threadIdx.x];
+            br[threadIdx.x] = (uint16_t)(e - (lo < e) - (hi < e));
+        }
+        if (threadIdx.x == 0) {
+            int vD = 0;
+            while (vD < m - 1 && jd >= re[vD]) ++vD;
+            a.ls_cand[idx] = cu;
+            a.ls_pd[idx] = (vD << 16) | (jd - rs[vD]);
+            a.ls_seg_off[idx] = (int64_t)c * a.LB + (int64_t)i * T;
+            a.ls_base_off[idx] = idx * 2 * a.N;
+            a.ls_rt_off[idx] = idx * a.M;
+            a.ls_base_inst[idx] = a.chain_inst[c];
+        }
+    }
+}
+
+// Block (chain, candidate): the candidate's ranked tuples against its base.
+template <typename DT>
+__global__ __launch_bounds__(256) void k_ls_enum(AlnsDev a, int kind)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int c = blockIdx.x, i = blockIdx.y;
+    const int64_t idx = (int64_t)c * a.LQ + i;
+    if (!a.ls_active[c] || i >= a.ls_nc[c]) return;   // ls_seg_cnt is 0 there (setup)
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int cust = a.ls_cand[idx];
+    const uint16_t* wops = a.ls_ops + idx * 2 * a.N;
+    const uint16_t* wrt = a.ls_rt + idx * a.M;
+    const int T = a.ls_T[c], KD = a.ls_KD[c], KP = a.ls_KP[c], bveh = a.ls_b[c];
+    __shared__ int rs[kMaxM], re[kMaxM], cum[kMaxM + 1];
+    if (threadIdx.x < m) {
+        rs[threadIdx.x] = threadIdx.x ? wrt[threadIdx.x - 1] : 0;
+        re[threadIdx.x] = wrt[threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cum[0] = 0;
+        for (int v = 0; v < m; ++v) cum[v + 1] = cum[v] + (re[v] - rs[v]) + 1;
+    }
+    __syncthreads();
+    const int L = re[m - 1];
+    const int nslots = L + m;
+    const int npow = pow2_ge(nslots + 1);
+    unsigned long long* key = reinterpret_cast<unsigned long long*>(smem);
+    int* dl = reinterpret_cast<int*>(key + npow);     // chosen drop slots (index into key[])
+    int* tstart = dl + npow;
+    auto cust_at = [&](int j) { return (int)(wops[j] >> 1); };
+    auto det = [&](int x, int y) { return (long long)D[x * N1 + cust] + D[cust * N1 + y] - D[x * N1 + y]; };
+    for (int k = threadIdx.x; k < npow; k += blockDim.x) {
+        unsigned long long kv = ~0ull;
+        if (k < nslots) {
+            int v = 0;
+            while (cum[v + 1] <= k) ++v;
+            const int p = k - cum[v], len = re[v] - rs[v];
+            const int x = p > 0 ? cust_at(rs[v] + p - 1) : 0;
+            const int y = p < len ? cust_at(rs[v] + p) : 0;
+            kv = slot_key(det(x, y), v, p);
+        }
+        key[k] = kv;
+    }
+    __syncthreads();
+    block_sort_u64(key, npow);
+    __shared__ int nd, total;
+    __shared__ unsigned long long fixed_drop;
+    if (threadIdx.x == 0) {
+        if (kind == 0) {
+            const int pd = a.ls_pd[idx];
+            fixed_drop = slot_key(0, pd >> 16, pd & 0xFFFF);   // only (vehicle, position) are read
+            nd = 1;
+        } else {
+            int cnt = 0;
+            for (int k = 0; k < nslots && cnt < KD; ++k)
+                if ((int)((key[k] >> 16) & 0x3Fu) != bveh) dl[cnt++] = k;
+            nd = cnt;
+        }
+        // tuples per drop, then their offsets
+        int t = 0;
+        for (int di = 0; di < nd; ++di) {
+            const unsigned long long kd = kind == 0 ? fixed_drop : key[dl[di]];
+            const int vD = (int)((kd >> 16) & 0x3Fu), pD = (int)(kd & 0xFFFFu);
+            int cnt;
+            if (kind == 0) {
+                cnt = nslots - pD;
+                if (cnt > T) cnt = T;
+            } else {
+                cnt = (re[vD] - rs[vD]) + 1 - pD;   // slots after the drop on its own route
+                if (cnt > KP) cnt = KP;
+            }
+            tstart[di] = t;
+            t += cnt;
+        }
+        total = t;
+    }
+    __syncthreads();
+    vrprpd_tuple* out = a.ls_tuples + a.ls_seg_off[idx];
+    for (int di = threadIdx.x; di < nd; di += blockDim.x) {
+        const unsigned long long kd = kind == 0 ? fixed_drop : key[dl[di]];
+        const int vD = (int)((kd >> 16) & 0x3Fu), pD = (int)(kd & 0xFFFFu);
+        const int t0 = tstart[di];
+        const int np = (di + 1 < nd ? tstart[di + 1] : total) - t0;
+        const unsigned long long kw = slot_key(0, vD, pD + 1);
+        bool wait_out = false;
+        int k = 0;
+        for (int got = 0; got < np; ++got) {
+            unsigned long long kv = ~0ull;
+            while (k < nslots) {
+                const unsigned long long x = key[k];
+                const int v = (int)((x >> 16) & 0x3Fu), p = (int)(x & 0xFFFFu);
+                if (v != vD) {
+                    if (kind == 0) {
+                        kv = x;
+                        break;
+                    }
+                } else if (p > pD) {
+                    kv = x + 1;
+                    break;
+                }
+                ++k;
+            }
+            unsigned long long pick;
+            if (!wait_out && kw < kv) {
+                pick = kw;
+                wait_out = true;
+            } else {
+                pick = kv;
+                ++k;
+            }
+            if (pick == ~0ull) break;
+            vrprpd_tuple tt;
+            tt.c = (uint16_t)cust;
+            tt.vD = (uint8_t)vD;
+            tt.pD = (uint16_t)pD;
+            tt.vP = (uint8_t)((pick >> 16) & 0x3Fu);
+            tt.pP = (uint16_t)(pick & 0xFFFFu);
+            out[t0 + got] = tt;
+        }
+    }
+    if (threadIdx.x == 0) a.ls_seg_cnt[idx] = total;
+}
+
+// Block per chain: the best strictly improving move of the pass replaces S.
+__global__ __launch_bounds__(256) void k_ls_apply(AlnsDev a)
+{
+    const int c = blockIdx.x;
+    if (!a.ls_active[c]) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int m = I.m;
+    __shared__ long long best;
+    __shared__ int take;
+    if (threadIdx.x == 0) {
+        const int nc = a.ls_nc[c];
+        long long b = INT64_MAX;
+        unsigned long long tot = 0;
+        for (int i = 0; i < nc; ++i) {
+            const int64_t idx = (int64_t)c * a.LQ + i;
+            const long long k0 = a.ls_top3[3 * idx];
+            b = k0 < b ? k0 : b;
+            tot += (unsigned long long)a.ls_seg_cnt[idx];
+        }
+        atomicAdd(a.evals, tot);
+        take = b != INT64_MAX && (b >> 32) < (long long)a.z[c];
+        best = b;
+        if (!take) a.ls_active[c] = 0;
+    }
+    __syncthreads();
+    if (!take) return;
+    const int64_t t = best & 0xFFFFFFFFll;
+    const int i = (int)((t - (int64_t)c * a.LB) / a.ls_T[c]);
+    const int64_t idx = (int64_t)c * a.LQ + i;
+    const vrprpd_tuple tp = a.ls_tuples[t];
+    splice_tuple(a.ls_ops + idx * 2 * a.N, a.ls_rt + idx * a.M, m, tp, a.S_ops + (int64_t)c * 2 * a.N,
+                 a.S_rt + (int64_t)c * a.M);
+    if (threadIdx.x == 0) {
+        a.z[c] = (int)(best >> 32);
+        a.ls_any[c] = 1;
+    }
+}
+
+// Block per chain: a local search that produced a new best keeps it.
+__global__ __launch_bounds__(256) void k_ls_finish(AlnsDev a)
+{
+    const int c = blockIdx.x;
+    if (!a.ls_any[c] || a.z[c] >= a.zb[c]) return;
+    const InstDev I = a.inst_tab[a.chain_inst[c]];
+    const int m = I.m;
+    const int L = a.S_rt[(int64_t)c * a.M + m - 1];
+    for (int j = threadIdx.x; j < L; j += blockDim.x) a.B_ops[(int64_t)c * 2 * a.N + j] = a.S_ops[(int64_t)c * 2 * a.N + j];
+    for (int v = threadIdx.x; v < m; v += blockDim.x) a.B_rt[(int64_t)c * a.M + v] = a.S_rt[(int64_t)c * a.M + v];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.zb[c] = a.z[c];
+        a.stag[c] = 0;
+    }
+}
+
 // ---------------------------------------------------------------- accept
 __global__ __launch_bounds__(256) void k_accept(AlnsDev a)
 {
@@ -1323,8 +1657,9 @@ struct alns_state {
     std::vector<void*> rec_allocs;     // record buffers (freed when recording restarts)
     bool use_graph = true;             // replay a captured iteration (alns_set_graph)
     hipStream_t cap = nullptr;         // capture stream (default priority)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;    // rebuilt after any change of the launch arguments
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};        // per local-search mask
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};    // rebuilt after any change of the launch arguments
+    int lds_ls = 0;
 };
 
 namespace vrprpd {
@@ -1389,8 +1724,10 @@ static void qrange(const alns_params& P, int n, int* qmin, int* qmax)
 extern "C" int alns_state_destroy(alns_state* s)
 {
     if (!s) return VRPRPD_OK;
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (int i = 0; i < 4; ++i) {
+        if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
+        if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
+    }
     if (s->cap) (void)hipStreamDestroy(s->cap);
     for (void* p : s->allocs) (void)hipFree(p);
     for (void* p : s->rec_allocs) (void)hipFree(p);
@@ -1411,6 +1748,10 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     if (P.tau < 1 || !(P.alpha > 0.0) || !(P.T0 > 0.0) || (P.op_mask & 0x3Fu) == 0 || ((P.op_mask >> 8) & 0xFu) == 0)
         return set_error(VRPRPD_EINVAL, "alns_state_create: tau >= 1, alpha > 0, T0 > 0 and at least one "
                                         "destroy and one repair operator are required");
+    if (P.ls_repos_interval < 0 || P.ls_reloc_interval < 0 ||
+        ((P.ls_repos_interval > 0 || P.ls_reloc_interval > 0) && P.ls_budget < 1))
+        return set_error(VRPRPD_EINVAL, "alns_state_create: local-search intervals must be >= 0 and ls_budget >= 1 "
+                                        "when one is on");
     int N = 0, M = 0, Q = 0, TPC = 0;
     for (int i = 0; i < n_inst; ++i) {
         if (inst_ids[i] < 0 || inst_ids[i] >= set->num_inst)
@@ -1459,6 +1800,16 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
     A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C); A(d.evals, 1);
     A(d.cand_rem, (size_t)C * Q); A(d.cand_cnt, C); A(d.chosen, C); A(d.it_dev, 1);
+    if (P.ls_repos_interval > 0 || P.ls_reloc_interval > 0) {
+        d.LQ = std::min(N, (int)kLsMaxCand);
+        d.LB = (int64_t)P.ls_budget + d.LQ;
+        const size_t CL = (size_t)C * d.LQ;
+        A(d.ls_ops, CL * 2 * N); A(d.ls_rt, CL * M); A(d.ls_cand, CL); A(d.ls_pd, CL);
+        A(d.ls_nc, C); A(d.ls_T, C); A(d.ls_KD, C); A(d.ls_KP, C); A(d.ls_b, C); A(d.ls_active, C); A(d.ls_any, C);
+        A(d.ls_base_inst, CL); A(d.ls_seg_base, CL); A(d.ls_seg_cnt, CL); A(d.ls_seg_off, CL + 1);
+        A(d.ls_base_off, CL); A(d.ls_rt_off, CL); A(d.ls_top3, 3 * CL);
+        A(d.ls_tuples, (size_t)C * d.LB); A(d.ls_tmk, (size_t)C * d.LB); A(d.ls_tst, (size_t)C * d.LB);
+    }
 #undef A
     d.K = 1;
     d.eps = 1.0;
@@ -1486,6 +1837,15 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
         (e = hipMemcpy(d.wR, w2.data(), w2.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
         alns_state_destroy(s);
         return hip_error(e, "alns_state_create: hipMemcpy");
+    }
+    if (d.ls_seg_base) {
+        std::vector<int32_t> ident((size_t)C * d.LQ);
+        for (size_t i = 0; i < ident.size(); ++i) ident[i] = (int32_t)i;
+        if ((e = hipMemcpy(d.ls_seg_base, ident.data(), ident.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+            alns_state_destroy(s);
+            return hip_error(e, "alns_state_create: hipMemcpy");
+        }
     }
     // initial solutions: instance i's solution at init_ops + i * 2N? no: the
     // caller gives one solution per instance, ops at [i * 2 n_max], route ends at [i * m_max]
@@ -1584,8 +1944,22 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
         f.take<int>(N + 1);
         f.take<unsigned char>(bpo * (2 * N + kAlnsStep));
         s->lds_feat = (int)f.bytes;
+        LdsSize l;
+        l.take<int>(2 * N + kAlnsStep);
+        l.take<int>(N + 1);
+        l.take<uint16_t>(N + 2);
+        l.take<uint16_t>(N + 2);
+        l.take<int>(kMaxM);
+        l.take<int>(kMaxM);
+        l.take<long long>(kMaxM);
+        l.take<int>(N + 1);
+        l.take<unsigned char>(N + 1);
+        l.take<int>(kLsMaxCand);
+        l.take<unsigned char>(bpo * (2 * N + kAlnsStep));
+        s->lds_ls = (int)l.bytes;
     }
-    if ((size_t)std::max(std::max(s->lds_gain, s->lds_feat), std::max(s->lds_destroy, s->lds_enum)) > kLdsPerCu) {
+    if ((size_t)std::max(std::max(std::max(s->lds_gain, s->lds_feat), s->lds_ls),
+                         std::max(s->lds_destroy, s->lds_enum)) > kLdsPerCu) {
         alns_state_destroy(s);
         return set_error(VRPRPD_EINVAL, "alns_state_create: n = %d needs too much LDS", N);
     }
@@ -1611,12 +1985,13 @@ static const void* gains_kernel()
 template <typename DT>
 static int set_attributes(alns_state* s)
 {
-    const void* ks[4] = {s->d.M <= 16 ? gains_kernel<DT, 16>() : (s->d.M <= 32 ? gains_kernel<DT, 32>()
+    const void* ks[6] = {s->d.M <= 16 ? gains_kernel<DT, 16>() : (s->d.M <= 32 ? gains_kernel<DT, 32>()
                                                                                 : gains_kernel<DT, 64>()),
                          reinterpret_cast<const void*>(k_destroy<DT>), reinterpret_cast<const void*>(k_enum<DT>),
-                         reinterpret_cast<const void*>(k_features<DT>)};
-    const int lds[4] = {s->lds_gain, s->lds_destroy, s->lds_enum, s->lds_feat};
-    for (int i = 0; i < 4; ++i)
+                         reinterpret_cast<const void*>(k_features<DT>), reinterpret_cast<const void*>(k_ls_setup<DT>),
+                         reinterpret_cast<const void*>(k_ls_enum<DT>)};
+    const int lds[6] = {s->lds_gain, s->lds_destroy, s->lds_enum, s->lds_feat, s->lds_ls, s->lds_enum};
+    for (int i = 0; i < 6; ++i)
         if (lds[i] > 64 * 1024) VRP_HIP(hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds[i]));
     return VRPRPD_OK;
 }
@@ -1637,7 +2012,7 @@ static int launch_gains(alns_state* s, hipStream_t st)
 // that changes between iterations (the iteration number lives on the
 // device), so the sequence can be captured once and replayed.
 template <typename DT>
-static int launch_iteration(alns_state* s, hipStream_t st)
+static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
 {
     AlnsDev& d = s->d;
     hipLaunchKernelGGL(k_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d);
@@ -1672,6 +2047,27 @@ static int launch_iteration(alns_state* s, hipStream_t st)
     }
     hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d);
     VRP_HIP(hipGetLastError());
+    if (ls_mask) {
+        ScanArgs la{d.inst_tab, d.dist, d.proc, d.ls_base_inst, d.ls_base_off, d.ls_ops, d.ls_rt_off, d.ls_rt,
+                    d.ls_seg_off, d.ls_seg_base, d.ls_tuples, d.ls_tmk, d.ls_tst, d.ls_top3, d.ls_seg_cnt,
+                    d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 4};
+        bool first = true;
+        for (int kind = 0; kind < 2; ++kind) {
+            if (!(ls_mask & (1 << kind))) continue;
+            hipLaunchKernelGGL(k_ls_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, first ? 1 : 0);
+            first = false;
+            for (int pass = 0; pass < 3; ++pass) {
+                hipLaunchKernelGGL(k_ls_setup<DT>, dim3(d.C), dim3(256), s->lds_ls, st, d, kind);
+                hipLaunchKernelGGL(k_ls_enum<DT>, dim3(d.C, d.LQ), dim3(256), s->lds_enum, st, d, kind);
+                VRP_HIP(hipGetLastError());
+                if ((rc = insert_scan_launch(la, d.M, s->dist16, st))) return rc;
+                hipLaunchKernelGGL(k_ls_apply, dim3(d.C), dim3(256), 0, st, d);
+                VRP_HIP(hipGetLastError());
+            }
+        }
+        hipLaunchKernelGGL(k_ls_finish, dim3(d.C), dim3(256), 0, st, d);
+        VRP_HIP(hipGetLastError());
+    }
     if (s->cpi > 1 && d.prm.import_interval > 0) {
         hipLaunchKernelGGL(k_import, dim3(s->n_inst), dim3(256), 0, st, d, s->cpi);
         VRP_HIP(hipGetLastError());
@@ -1681,26 +2077,39 @@ static int launch_iteration(alns_state* s, hipStream_t st)
     return VRPRPD_OK;
 }
 
-static int launch_iteration_any(alns_state* s, hipStream_t st)
+static int launch_iteration_any(alns_state* s, hipStream_t st, int ls_mask)
 {
-    return s->dist16 ? launch_iteration<uint16_t>(s, st) : launch_iteration<int32_t>(s, st);
+    return s->dist16 ? launch_iteration<uint16_t>(s, st, ls_mask) : launch_iteration<int32_t>(s, st, ls_mask);
+}
+
+// Local searches due after iteration `it` (0-based): bit 0 repositioning,
+// bit 1 relocation.
+static int ls_mask_of(const alns_state* s, int64_t it)
+{
+    const alns_params& P = s->d.prm;
+    int mask = 0;
+    if (P.ls_repos_interval > 0 && (it + 1) % P.ls_repos_interval == 0) mask |= 1;
+    if (P.ls_reloc_interval > 0 && (it + 1) % P.ls_reloc_interval == 0) mask |= 2;
+    return mask;
 }
 
 static void drop_graph(alns_state* s)
 {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->gexec = nullptr;
-    s->graph = nullptr;
+    for (int i = 0; i < 4; ++i) {
+        if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
+        if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
+        s->gexec[i] = nullptr;
+        s->graph[i] = nullptr;
+    }
 }
 
-// Captures one iteration's launches on the state's own stream.
-static int build_graph(alns_state* s)
+// Captures one iteration's launches (with the local searches of `mask`) on
+// the state's own stream.
+static int build_graph(alns_state* s, int mask)
 {
-    drop_graph(s);
     if (!s->cap) VRP_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
     VRP_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = launch_iteration_any(s, s->cap);
+    const int rc = launch_iteration_any(s, s->cap, mask);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s->cap, &g);
     if (rc) {
@@ -1708,8 +2117,8 @@ static int build_graph(alns_state* s)
         return rc;
     }
     if (e != hipSuccess) return hip_error(e, "alns_step: hipStreamEndCapture");
-    s->graph = g;
-    VRP_HIP(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+    s->graph[mask] = g;
+    VRP_HIP(hipGraphInstantiate(&s->gexec[mask], g, nullptr, nullptr, 0));
     return VRPRPD_OK;
 }
 
@@ -1720,20 +2129,18 @@ extern "C" int alns_step(alns_state* s, int32_t iterations, void* stream)
     using namespace vrprpd;
     if (!s || iterations < 0) return set_error(VRPRPD_EINVAL, "alns_step: bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (s->use_graph && iterations > 0) {
-        if (!s->gexec) {
-            const int rc = build_graph(s);
+    for (int i = 0; i < iterations; ++i) {
+        const int mask = ls_mask_of(s, s->it);
+        if (s->use_graph) {
+            if (!s->gexec[mask]) {
+                const int rc = build_graph(s, mask);
+                if (rc) return rc;
+            }
+            VRP_HIP(hipGraphLaunch(s->gexec[mask], st));
+        } else {
+            const int rc = launch_iteration_any(s, st, mask);
             if (rc) return rc;
         }
-        for (int i = 0; i < iterations; ++i) {
-            VRP_HIP(hipGraphLaunch(s->gexec, st));
-            s->it += 1;
-        }
-        return VRPRPD_OK;
-    }
-    for (int i = 0; i < iterations; ++i) {
-        const int rc = launch_iteration_any(s, st);
-        if (rc) return rc;
         s->it += 1;
     }
     return VRPRPD_OK;

@@ -107,3 +107,45 @@ def test_graph_replay_equals_eager_launches(orc, P):
     assert np.array_equal(tg.cpu().numpy(), te.cpu().numpy())
     ref = orc.alns_run(inst, orc.alns_params(tuple_budget=400, import_interval=5), 3, 24, 31, ops, rt, trace=True)
     assert np.array_equal(tg.cpu().numpy(), ref["trace"])
+
+
+LS_CASES = [
+    # n, m, k, R, rule, chains, iters, budget, repos, reloc, ls_budget
+    (30, 3, 3, 9, "base", 3, 25, 300, 4, 6, 400),
+    (100, 4, 5, 20, "2x", 2, 12, 2000, 3, 5, 3000),
+    (20, 17, 2, 40, "1R10", 2, 12, 500, 2, 3, 600),   # 32-lane groups
+    (16, 2, 2, 4, "base", 4, 30, 0, 5, 7, 100000),      # budget above every neighbourhood
+]
+
+
+@pytest.mark.parametrize("case", LS_CASES, ids=lambda c: f"n{c[0]}m{c[1]}r{c[8]}x{c[9]}")
+def test_alns_local_search_parity(orc, P, case):
+    """Periodic pickup repositioning and cross-agent relocation (Section
+    4.2.5) at short intervals: trajectories, best makespans and solutions
+    bit-identical to the oracle, with graph replay and with direct launches."""
+    n, m, k, R, rule, chains, iters, budget, repos, reloc, lsb = case
+    inst = synth.make_instance(n, m, k, R, rule, seed=9100 + n)
+    ops, rt = synth.round_robin_solution(inst, vehicles=min(m, R))
+    seed = 4321 + n
+    kw = dict(tuple_budget=budget, import_interval=0, ls_repos_interval=repos, ls_reloc_interval=reloc,
+              ls_budget=lsb)
+    ref = orc.alns_run(inst, orc.alns_params(**kw), chains, iters, seed, ops, rt, trace=True)
+    S = P.InstanceSet([inst])
+    for graph in (True, False):
+        st = P.AlnsState(S, [0], chains, P.alns_params(**kw), seed, torch.from_numpy(ops).cuda(),
+                         torch.from_numpy(rt).cuda())
+        st.set_graph(graph)
+        tr = st.set_trace(iters)
+        st.step(iters)
+        got = tr.cpu().numpy()
+        for ch in range(chains):
+            for it in range(iters):
+                assert np.array_equal(got[ch, it], ref["trace"][ch, it]), (graph, ch, it, got[ch, it],
+                                                                           ref["trace"][ch, it])
+        info = st.state()
+        assert np.array_equal(info["zb"], ref["best_mk"])
+        for ch in range(chains):
+            mk, bops, brt = st.best(ch)
+            assert np.array_equal(bops.cpu().numpy()[:2 * n], ref["best_ops"][ch])
+            assert orc.eval_one(inst, bops.cpu().numpy()[:2 * n], brt.cpu().numpy()[:m]) == (mk, 0)
+        st.close()
