@@ -2,8 +2,9 @@
 on the benchmark instances with a fixed seed and budget, and its wall time.
 Calls only oracle/ and synth/ (the seeded input generator).
 
-Protocol (one chain, Table 2 parameters, start = customers dealt round-robin
-as drop-then-pickup pairs):
+Protocol (one chain, Table 2 parameters including the periodic local search
+every 200 / 500 iterations with 16,384 tuples per pass, start = customers
+dealt round-robin as drop-then-pickup pairs):
   n=100:  m=4, k=5, R=20, rule 2x, tuple budget 2,000, 2,000 iterations
   n=1000: m=10, k=10, R=100, rule 1R20d10, tuple budget 16,384, 200 iterations
 Run from the repository root: python tests/golden/make_oracle_targets.py
