@@ -196,8 +196,9 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 if (unsched && lane >= cursor) feas = isP ? (anyP && dropdone) : anyD;
                 const unsigned long long mask = __ballot(feas);
                 if (!mask) break;
-                const int i = __ffsll((long long)mask) - 1;
-                const int oi = __shfl(o, i, 64), hi = __shfl(h, i, 64), pci = __shfl(pc, i, 64);
+                const int i = __ffsll((long long)mask) - 1;   // wave-uniform: read lanes directly
+                const int oi = __builtin_amdgcn_readlane(o, i), hi = __builtin_amdgcn_readlane(h, i);
+                const int pci = __builtin_amdgcn_readlane(pc, i);
                 const int ci = oi / 2 + 1, isPi = oi & 1;
                 const int dv = veh ? (int)D[loc * N1 + ci] : 0;
                 // SelectVehicle: least completion time, ties to the first
@@ -217,11 +218,16 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                     }
                     if (cand) kv = key;
                 }
-                const int ks = wave_min_i32(kv);
+                // minimum over the m vehicle lanes, read one by one (no LDS crossbar)
+                int ks = INT_MAX;
+                for (int v = 0; v < m; ++v) {
+                    const int x = __builtin_amdgcn_readlane(kv, v);
+                    ks = x < ks ? x : ks;
+                }
                 const unsigned long long tie = __ballot(kv == ks && veh);
                 const unsigned long long upper = tie & (~0ull << hi);
                 const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
-                const int took_preload = __shfl((!isPi && q == 0) ? 1 : 0, vs, 64);
+                const int took_preload = __builtin_amdgcn_readlane((!isPi && q == 0) ? 1 : 0, vs);
                 if (lane == vs) {
                     if (!isPi) {
                         if (q == 0) { ++M; ++q; }
