@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["eval.c", "decode.c", "scan.c", "brkga.c", "alns.c"]
+SOURCES = ["eval.c", "decode.c", "scan.c", "brkga.c", "alns.c", "construct.c"]
 
 BAD_COVER, LOAD, RES, DEADLOCK, BAD_KEY, BAD_TUPLE = 1, 2, 4, 8, 16, 32
 MIN_PRELOAD, FULL_START = 0, 1
@@ -78,6 +78,17 @@ def _declare(L):
                                    C.c_uint32, C.c_uint64, C.c_uint32, P, P, P]
     L.orc_brkga_warm_start.restype = None
     L.orc_brkga_warm_start.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, P, P]
+    L.orc_brkga_warm_start_multi.restype = None
+    L.orc_brkga_warm_start_multi.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, P, C.c_int32, C.c_int32,
+                                             C.c_uint64, P, P]
+    L.orc_construct.restype = C.c_int32
+    L.orc_construct.argtypes = [P, C.c_int32, P, P, P, P]
+    L.orc_cons_vehicles.restype = C.c_int32
+    L.orc_cons_vehicles.argtypes = [P]
+    L.orc_cons_angle_order.restype = None
+    L.orc_cons_angle_order.argtypes = [P, P]
+    L.orc_cons_sectors.restype = C.c_int32
+    L.orc_cons_sectors.argtypes = [P, P, P]
     if hasattr(L, "orc_alns_run"):
         _declare_alns(L)
 
@@ -327,6 +338,81 @@ def brkga_warm_start(inst, ops, rt_end, Np, n_warm, n_variants, seed):
     lib().orc_brkga_warm_start(oi.ref, _ptr(ops), _ptr(rt), Np, n_warm, n_variants,
                                seed & (2**64 - 1), _ptr(po), _ptr(ho))
     return po, ho
+
+
+def brkga_warm_start_multi(inst, sources, n_var, Np, n_warm, seed):
+    """Warm start from several solutions: sources = [(ops, rt_end), ...],
+    n_var[s] variants of source s (Section 4.4.4)."""
+    oi = _oinst(inst)
+    S = len(sources)
+    ops = np.zeros((S, 2 * oi.n), np.uint16)
+    rt = np.zeros((S, oi.m), np.uint16)
+    for s, (o, r) in enumerate(sources):
+        ops[s, :len(o)] = o
+        rt[s] = r
+    nv = np.ascontiguousarray(n_var, dtype=np.int32)
+    G = 2 * oi.n
+    po = np.zeros((Np, G), dtype=np.float32)
+    ho = np.zeros((Np, G), dtype=np.float32)
+    lib().orc_brkga_warm_start_multi(oi.ref, S, _ptr(ops), 2 * oi.n, _ptr(rt), oi.m, _ptr(nv), Np, n_warm,
+                                     seed & (2**64 - 1), _ptr(po), _ptr(ho))
+    return po, ho
+
+
+CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT = 0, 1, 2, 3
+
+
+def construct(inst, heuristic, order=False):
+    """One construction heuristic (0 sweep + balance + per-vehicle nearest
+    neighbour, 1 nearest neighbour, 2 load balanced, 3 shortest processing
+    time).  Returns (ops, rt_end), plus the placement order [(vehicle, op)]
+    when order is set."""
+    oi = _oinst(inst)
+    ops = np.zeros(2 * oi.n, np.uint16)
+    rt = np.zeros(oi.m, np.uint16)
+    sv = np.zeros(2 * oi.n, np.int32)
+    so = np.zeros(2 * oi.n, np.int32)
+    cnt = lib().orc_construct(oi.ref, heuristic, _ptr(ops), _ptr(rt), _ptr(sv), _ptr(so))
+    res = (ops[:cnt], rt)
+    if order:
+        return res + (list(zip(sv[:cnt].tolist(), so[:cnt].tolist())),)
+    return res
+
+
+def cons_vehicles(inst):
+    return int(lib().orc_cons_vehicles(_oinst(inst).ref))
+
+
+def cons_angle_order(inst):
+    oi = _oinst(inst)
+    order = np.zeros(oi.n, np.int32)
+    lib().orc_cons_angle_order(oi.ref, _ptr(order))
+    return order
+
+
+def cons_sectors(inst):
+    """(sectors before balancing, after balancing, moves); index 0 unused."""
+    oi = _oinst(inst)
+    s0 = np.zeros(oi.n + 1, np.int32)
+    s1 = np.zeros(oi.n + 1, np.int32)
+    moves = lib().orc_cons_sectors(oi.ref, _ptr(s0), _ptr(s1))
+    return s0, s1, int(moves)
+
+
+def refine(inst, ops, rt_end, budget=16384, max_rounds=1000):
+    """The construction's refinement (Section 4.2, initial solution, last
+    phase): rounds of pickup repositioning then cross-agent relocation (up
+    to three passes each, Section 4.2.5) until a round improves nothing.
+    Returns (rounds run, makespan, ops, rt_end)."""
+    z = eval_one(inst, ops, rt_end)[0]
+    rounds = 0
+    while rounds < max_rounds:
+        rounds += 1
+        k0, z, ops, rt_end = alns_local_search(inst, 0, ops, rt_end, budget=budget, passes=3)
+        k1, z, ops, rt_end = alns_local_search(inst, 1, ops, rt_end, budget=budget, passes=3)
+        if k0 == 0 and k1 == 0:
+            break
+    return rounds, int(z), ops, rt_end
 
 
 def int32_safe(inst) -> bool:

@@ -115,21 +115,20 @@ void orc_brkga_evolve(int32_t Np, int32_t genes, const float* prio, const float*
 }
 
 /*
- * Warm start (Section 4.4.4).  The solution is encoded by the seed encoding:
- * the op at 1-based position r of a route of L_v ops gets priority (r-1)/L_v,
- * and every op of vehicle v gets hint (v + 1/2)/m (the centre of the hint
- * interval that floor(m * alpha) maps to v).  Slots [0, n_warm) hold variants
- * of it, cycling through n_variants: variant 0 as encoded, variant t > 0 with
- * every gene moved by U(-0.03, 0.03) and clamped into [0, 1).  The remaining
- * slots are fresh U(0,1) individuals.
+ * Warm start (Section 4.4.4).  Each source solution is encoded by the seed
+ * encoding: the op at 1-based position r of a route of L_v ops gets priority
+ * (r-1)/L_v, and every op of vehicle v gets hint (v + 1/2)/m (the centre of
+ * the hint interval that floor(m * alpha) maps to v); ops absent from the
+ * solution get 0.  Source s contributes n_var[s] variants: variant 0 as
+ * encoded, variant t > 0 with every gene moved by U(-0.03, 0.03) and clamped
+ * into [0, 1).  Slots [0, n_warm) cycle through the variants of all sources
+ * in order (source 0's first); the remaining slots are fresh U(0,1)
+ * individuals.  The perturbation of gene j in variant t of source s draws
+ * from counter (j / 4, t, s, 'WARM').
  */
-void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
-                          int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed,
-                          float* prio_out, float* hint_out)
+static void encode(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end, float* ep, float* eh)
 {
     const int n = I->n, m = I->m, G = 2 * n;
-    float* ep = malloc((size_t)G * sizeof(float));
-    float* eh = malloc((size_t)G * sizeof(float));
     for (int o = 0; o < G; ++o) { ep[o] = 0.0f; eh[o] = 0.0f; }
     for (int v = 0, s = 0; v < m; s = rt_end[v], ++v) {
         int L = rt_end[v] - s;
@@ -140,15 +139,30 @@ void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t
             eh[o] = (float)(((double)v + 0.5) / (double)m);
         }
     }
+}
+
+void orc_brkga_warm_start_multi(const orc_inst* I, int32_t n_src, const uint16_t* ops, int64_t op_stride,
+                                const uint16_t* rt_end, int64_t rt_stride, const int32_t* n_var, int32_t Np,
+                                int32_t n_warm, uint64_t seed, float* prio_out, float* hint_out)
+{
+    const int n = I->n, G = 2 * n;
+    int total = 0;
+    for (int s = 0; s < n_src; ++s) total += n_var[s];
+    float* ep = malloc((size_t)n_src * G * sizeof(float));
+    float* eh = malloc((size_t)n_src * G * sizeof(float));
+    for (int s = 0; s < n_src; ++s)
+        encode(I, ops + (size_t)s * op_stride, rt_end + (size_t)s * rt_stride, ep + (size_t)s * G, eh + (size_t)s * G);
     for (int32_t i = 0; i < Np; ++i) {
         float* dp = prio_out + (size_t)i * G;
         float* dh = hint_out + (size_t)i * G;
-        if (i < n_warm) {
-            uint32_t var = (uint32_t)(i % n_variants);
+        if (i < n_warm && total > 0) {
+            int q = i % total, src = 0;
+            while (q >= n_var[src]) q -= n_var[src++];
+            const uint32_t var = (uint32_t)q;
             for (int j = 0; j < 2 * G; ++j) {
-                float g = j < G ? ep[j] : eh[j - G];
+                float g = j < G ? ep[(size_t)src * G + j] : eh[(size_t)src * G + j - G];
                 if (var) {
-                    double u = (double)(draw(seed, (uint32_t)j, var, 0, TAG_WARM) >> 8) * (1.0 / 16777216.0);
+                    double u = (double)(draw(seed, (uint32_t)j, var, (uint32_t)src, TAG_WARM) >> 8) * (1.0 / 16777216.0);
                     double x = (double)g + (u * 0.06 - 0.03);
                     if (x < 0.0) x = 0.0;
                     g = (float)x;
@@ -164,4 +178,11 @@ void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t
         }
     }
     free(ep); free(eh);
+}
+
+void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
+                          int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed,
+                          float* prio_out, float* hint_out)
+{
+    orc_brkga_warm_start_multi(I, 1, ops, 0, rt_end, 0, &n_variants, Np, n_warm, seed, prio_out, hint_out);
 }

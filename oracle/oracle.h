@@ -110,4 +110,20 @@ int32_t orc_alns_local_search(const orc_inst* I, int32_t kind, int32_t budget, i
 void orc_brkga_warm_start(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end,
                           int32_t Np, int32_t n_warm, int32_t n_variants, uint64_t seed,
                           float* prio_out, float* hint_out);
+/* The same from n_src solutions (source s at ops + s op_stride, rt_end +
+ * s rt_stride) with n_var[s] variants each. */
+void orc_brkga_warm_start_multi(const orc_inst* I, int32_t n_src, const uint16_t* ops, int64_t op_stride,
+                                const uint16_t* rt_end, int64_t rt_stride, const int32_t* n_var, int32_t Np,
+                                int32_t n_warm, uint64_t seed, float* prio_out, float* hint_out);
+
+/* Construction heuristics (initial solution of Section 4.2, phases 1-3;
+ * warm-start seeds of Section 4.4.4): heuristic 0 sweep + balance + nearest
+ * neighbour per vehicle, 1 nearest neighbour, 2 load balanced, 3 shortest
+ * processing time.  Writes ops (2n) and rt_end (m), the placement order to
+ * seq_v / seq_o (nullable); returns the number of ops placed. */
+int32_t orc_construct(const orc_inst* I, int32_t heuristic, uint16_t* ops, uint16_t* rt_end, int32_t* seq_v,
+                      int32_t* seq_o);
+int32_t orc_cons_vehicles(const orc_inst* I);
+void orc_cons_angle_order(const orc_inst* I, int32_t* order);
+int32_t orc_cons_sectors(const orc_inst* I, int32_t* sector0, int32_t* sector);
 #endif
