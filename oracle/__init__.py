@@ -119,6 +119,8 @@ def _declare_alns(L):
     P = C.c_void_p
     L.orc_alns_run.restype = C.c_int32
     L.orc_alns_run.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P]
+    L.orc_alns_run_from.restype = C.c_int32
+    L.orc_alns_run_from.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P, C.c_uint32]
     L.orc_det_exp.restype = C.c_double
     L.orc_det_exp.argtypes = [C.c_double]
     L.orc_alns_qrange.restype = None
@@ -169,9 +171,10 @@ def alns_local_search(inst, kind, ops, rt_end, budget=16384, passes=3):
     return int(k), int(z[0]), oo[:int(orr[-1])], orr
 
 
-def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False):
+def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False, chain0=0):
     """Run ALNS chains from one initial solution.  Returns dict(best_mk [chains],
-    best_ops [chains, 2n], best_rt [chains, m], trace [chains, iters, 4])."""
+    best_ops [chains, 2n], best_rt [chains, m], trace [chains, iters, 4]).
+    chain0: index of the first chain in the random-draw counters."""
     oi = _oinst(inst)
     init_ops = np.ascontiguousarray(init_ops, dtype=np.uint16)
     init_rt = np.ascontiguousarray(init_rt, dtype=np.uint16)
@@ -179,8 +182,8 @@ def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=Fa
     br = np.zeros((chains, oi.m), dtype=np.uint16)
     bm = np.zeros(chains, dtype=np.int32)
     tr = np.zeros((chains, iterations, 4), dtype=np.int64) if trace else None
-    lib().orc_alns_run(oi.ref, C.byref(params), chains, iterations, seed & (2**64 - 1), _ptr(init_ops),
-                       _ptr(init_rt), _ptr(bo), _ptr(br), _ptr(bm), _ptr(tr))
+    lib().orc_alns_run_from(oi.ref, C.byref(params), chains, iterations, seed & (2**64 - 1), _ptr(init_ops),
+                            _ptr(init_rt), _ptr(bo), _ptr(br), _ptr(bm), _ptr(tr), chain0)
     out = dict(best_mk=bm, best_ops=bo, best_rt=br)
     if trace:
         out["trace"] = tr

@@ -669,9 +669,12 @@ typedef struct {
     int stag;
 } chain_t;
 
-int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
-                     uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
-                     uint16_t* best_rt, int32_t* best_mk, int64_t* trace)
+/* chain0: the first chain's index in the random-draw counters (chains of
+ * one instance in a state that holds several instances are numbered on from
+ * the earlier instances' chains). */
+int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                          uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                          uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0)
 {
     const int n = I->n, m = I->m;
     int q_min = P->q_min, q_max = P->q_max;
@@ -710,7 +713,7 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
     for (int64_t it = 0; it < iterations; ++it) {
         for (int ch = 0; ch < chains; ++ch) {
             chain_t* c = &C[ch];
-            const uint32_t u_it = (uint32_t)it, u_ch = (uint32_t)ch;
+            const uint32_t u_it = (uint32_t)it, u_ch = chain0 + (uint32_t)ch;
             const int di = roulette(c->wD, ND, dmask, unit_d(adraw(seed, 0, u_it, u_ch)));
             const int ri = roulette(c->wR, NR, rmask, unit_d(adraw(seed, 1, u_it, u_ch)));
             const int q = q_min + uint_below(adraw(seed, 2, u_it, u_ch), q_max - q_min + 1);
@@ -833,6 +836,13 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
     return best;
 }
 
+
+int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                     uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                     uint16_t* best_rt, int32_t* best_mk, int64_t* trace)
+{
+    return orc_alns_run_from(I, P, chains, iterations, seed, init_ops, init_rt, best_ops, best_rt, best_mk, trace, 0);
+}
 
 /* One destroy operator applied to a complete solution (ops / rt_end) as
  * iteration `it` of chain `chain` would apply it, candidate `cand`; writes

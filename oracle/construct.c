@@ -34,7 +34,8 @@
  *    (10 (W_max - W_min) >= W_max), move from v_max to v_min the customer
  *    with 0 < w_c < W_max - W_min closest to half the gap (least
  *    |W_max - W_min - 2 w_c|, lowest index on ties); stop when no customer
- *    qualifies.  Every move lowers sum W_v^2, so the loop ends;
+ *    qualifies.  Every move lowers sum W_v^2, so the loop ends; it is also
+ *    cut at n m' moves;
  *  - per-vehicle nearest neighbour: vehicle v serves its sector alone,
  *    starting at the depot at time 0 with at most cap_v resources out at a
  *    time (cap_v = k under FULL_START; under MIN_PRELOAD R is split as
@@ -162,7 +163,7 @@ int32_t orc_cons_sectors(const orc_inst* I, int32_t* sector0, int32_t* sector)
     for (int v = 0; v < mv; ++v) W[v] = 0;
     for (int c = 1; c <= n; ++c) W[sector[c]] += 2 * dd(I, 0, c) + I->p[c];
     int moves = 0;
-    for (;;) {
+    while (moves < n * mv) {
         int hi = 0, lo = 0;
         for (int v = 1; v < mv; ++v) {
             if (W[v] > W[hi]) hi = v;

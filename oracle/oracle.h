@@ -94,6 +94,10 @@ void orc_alns_qrange(int n, int* q_min, int* q_max);
 int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
                      uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
                      uint16_t* best_rt, int32_t* best_mk, int64_t* trace);
+/* The same with the chains numbered chain0, chain0 + 1, ... in the draws. */
+int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                          uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                          uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0);
 /* One destroy operator on a complete feasible solution, as iteration `it` of
  * chain `chain` applies it, candidate `cand` of a learned proposal (draw
  * counters 16 + 4096 cand + i).  Returns the number of removed customers
