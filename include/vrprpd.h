@@ -275,6 +275,76 @@ int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint16_t* ops, c
                      float* prio_out, float* hint_out, void* stream);
 
 /*
+ * brkga_warm_start_multi — the warm start from several solutions (Section
+ * 4.4.4: the ALNS incumbent plus construction seeds, see vrprpd_construct).
+ * Source s (device ops + s op_stride, rt_end + s rt_stride) is encoded as
+ * above and contributes n_var[s] variants (host array; variant 0 the
+ * encoding itself, variant t > 0 perturbed with draws at counter (gene / 4,
+ * t, s, 'WARM')); slots [0, n_warm) cycle through all variants in source
+ * order, the other slots are fresh U(0,1) individuals as above.  With one
+ * source this equals brkga_warm_start.  1 <= n_src <= 16; n_var[s] >= 0 (all
+ * zero: every slot fresh).  Allocates a stream-ordered workspace of
+ * 8 n_src n bytes.  Errors: EINVAL, EHIP.
+ */
+int brkga_warm_start_multi(const vrprpd_set* set, int32_t inst, int32_t n_src, const uint16_t* ops,
+                           int64_t op_stride, const uint16_t* rt_end, int64_t rt_stride, const int32_t* n_var,
+                           int32_t Np, int32_t n_warm, uint64_t seed, int64_t key_stride, float* prio_out,
+                           float* hint_out, void* stream);
+
+/* ---- construction heuristics ------------------------------------------------
+ * vrprpd_construct — one solution per instance from a construction heuristic,
+ * one block per instance (B instances: inst[b], device, or b when NULL).
+ * VRPRPD_CONS_SWEEP is the initial solution of Section 4.2 ("Initial Solution
+ * Construction"), its first three phases; the fourth (refinement) is
+ * alns_refine.  NN, LB and SPT are the construction seeds of the BRKGA warm
+ * start (Section 4.4.4).  The paper names the phases and their aims; the
+ * library's readings, which a CPU implementation of the same readings
+ * reproduces exactly (integer arithmetic throughout):
+ *  - pseudo-angle: the depot is the origin, the customer r farthest from it
+ *    (lowest index on ties) gives angle 0; with a_c = d(0,c), b = d(0,r) and
+ *    X_c = a_c^2 + b^2 - d(r,c)^2 (the law of cosines: the coordinate along
+ *    the axis times 2b), the second reference r2 maximises 4 a^2 b^2 - X^2
+ *    (farthest from the axis, lowest index on ties) and fixes the positive
+ *    side: sign(y_c) = sign(2 b^2 (a_c^2 + a_r2^2 - d(r2,c)^2) - X_c X_r2).
+ *    Customers are ordered by (half-plane, cosine) with the cosine taken as
+ *    trunc(2^30 X_c / (2 a_c b)) clamped to [-2^30, 2^30], ties by index, all
+ *    on distances shifted right until the largest is below 2^14;
+ *  - sectors: m' = m under FULL_START, max(1, min(m, R)) under MIN_PRELOAD;
+ *    the order is cut into m' runs, the first n mod m' one longer;
+ *  - balancing (workload w_c = 2 d(0,c) + p_c): while 10 (W_max - W_min) >=
+ *    W_max (heaviest / lightest sector, lowest index on ties), the customer
+ *    of the heaviest sector with 0 < w_c < W_max - W_min closest to half the
+ *    gap (ties by index) moves to the lightest; stops when none qualifies
+ *    or after n m' moves;
+ *  - routes: each vehicle serves its sector alone with at most cap_v
+ *    resources out (k under FULL_START; under MIN_PRELOAD R split over the
+ *    m' vehicles, the first R mod m' one more, capped at k), each step the op
+ *    of earliest completion (a drop at arrival, a pickup at max(arrival,
+ *    drop time + p_c)), ties by op index 2(c-1) + isPickup;
+ *  - LB: whole customers, heaviest w_c first, each to the vehicle of least
+ *    assigned workload (ties by index), then routes as above;
+ *  - NN, SPT: one dispatch loop over all vehicles with the decoder's load
+ *    rules (Algorithm 2); NN: the vehicle free earliest among those with a
+ *    feasible op (ties by index) takes its nearest op (least d, ties by op);
+ *    SPT: drops only in ascending (p_c, c) order, the (vehicle, op) pair of
+ *    earliest completion among that drop and every pending pickup (ties by
+ *    op, then vehicle).
+ * Every op is placed unless no resource may move at all (R = 0 under
+ * MIN_PRELOAD): then the routes stay empty.
+ *   ops      [B][op_stride] out, op_stride >= 2 n_max; rt_end [B][rt_stride]
+ *            out, rt_stride >= m_max (route ends of the instance's m vehicles)
+ * A row whose instance index is out of range gets all-empty routes.
+ * Allocates a stream-ordered workspace (about 40 n_max bytes per instance).
+ * Errors: EINVAL, EHIP.
+ */
+#define VRPRPD_CONS_SWEEP 0
+#define VRPRPD_CONS_NN 1
+#define VRPRPD_CONS_LB 2
+#define VRPRPD_CONS_SPT 3
+int vrprpd_construct(const vrprpd_set* set, int32_t B, const int32_t* inst, int32_t heuristic, int64_t op_stride,
+                     uint16_t* ops, int64_t rt_stride, uint16_t* rt_end, void* stream);
+
+/*
  * brkga_state — many instances' BRKGA populations evolved together (the
  * batched form): each generation decodes and evaluates every individual of
  * every population in one brkga_decode_eval launch, then ranks, keeps each
@@ -394,6 +464,17 @@ int alns_get_best(const alns_state* st, int32_t chain, int32_t* mk, uint16_t* op
 int alns_get_state(const alns_state* st, int64_t* iterations, int64_t* evals, int32_t* z, int32_t* zb, double* T,
                    double* wD, double* wR);
 int alns_state_destroy(alns_state* st);
+/* The last phase of the initial construction (Section 4.2, "Initial Solution
+ * Construction": relocation and pickup reassignment until nothing improves),
+ * before the first iteration: rounds of the periodic local searches
+ * (repositioning, then relocation, up to three passes each, with the
+ * state's ls_budget) on every chain's current solution; a chain stops after
+ * a round that improved nothing, at most max_rounds rounds run.  Each chain's
+ * best becomes the refined solution and its temperature T0 times the refined
+ * makespan (the refined solution is the initial one).  rounds_out (host,
+ * nullable): rounds run.  Synchronous (reads the stop flags back after each
+ * round).  Errors: EINVAL (after alns_step, or ls_budget < 1), EHIP. */
+int alns_refine(alns_state* st, int32_t max_rounds, int32_t* rounds_out, void* stream);
 
 /* ---- ALNS with a learned destroy proposal ----------------------------------
  * (Section 6 names learned destroy operators as future work; this is the

@@ -9,5 +9,6 @@ from ._lib import (  # noqa: F401
     ALLOW_PARTIAL, FULL_START, MIN_PRELOAD, SIGNATURES, ST_BAD_COVER, ST_BAD_KEY, ST_BAD_TUPLE,
     ST_DEADLOCK, ST_LOAD, ST_RES, TUPLE_DTYPE, MLP_IN, MLP_HIDDEN, MLP_NUM_PARAMS, AlnsParams, AlnsState,
     InstanceSet, Mlp, VrpError, BrkgaState, pop_seed, alns_params, brkga_decode_eval, brkga_evolve, brkga_warm_start, load,
-    vrprpd_autotune_eval, vrprpd_eval, vrprpd_insert_scan,
+    vrprpd_autotune_eval, vrprpd_eval, vrprpd_insert_scan, CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT, vrprpd_construct,
+    brkga_warm_start_multi,
 )

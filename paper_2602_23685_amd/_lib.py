@@ -77,7 +77,13 @@ SIGNATURES = {
     "vrprpd_mlp_backward": (C.c_int, [_P, _P, _P]),
     "vrprpd_mlp_sgd_step": (C.c_int, [_P, C.c_float, C.c_float, _P]),
     "vrprpd_mlp_hidden": (C.c_int, [_P, _I32, _P, _P]),
+    "vrprpd_construct": (C.c_int, [_P, _I32, _P, _I32, _I64, _P, _I64, _P, _P]),
+    "brkga_warm_start_multi": (C.c_int, [_P, _I32, _I32, _P, _I64, _P, _I64, _P, _I32, _I32, _U64, _I64, _P, _P,
+                                         _P]),
+    "alns_refine": (C.c_int, [_P, _I32, _P, _P]),
 }
+
+CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT = 0, 1, 2, 3
 
 MLP_IN, MLP_HIDDEN, MLP_NUM_PARAMS = 64, 256, 148481
 
@@ -281,6 +287,38 @@ def brkga_warm_start(S: InstanceSet, ops, rt_end, Np, n_warm, n_variants, seed, 
     return po, ho
 
 
+def brkga_warm_start_multi(S: InstanceSet, ops, rt_end, n_var, Np, n_warm, seed, inst=0, stride=None,
+                           stream=None):
+    """Initial population seeded from several solutions (see
+    brkga_warm_start_multi): ops [n_src][>= 2n], rt_end [n_src][>= m] device
+    uint16, n_var a list of variants per source."""
+    G = 2 * S.instances[inst].n
+    stride = G if stride is None else stride
+    nv = (C.c_int32 * len(n_var))(*n_var)
+    po = torch.empty((Np, stride), dtype=torch.float32, device=ops.device)
+    ho = torch.empty((Np, stride), dtype=torch.float32, device=ops.device)
+    _check(load().brkga_warm_start_multi(
+        S.handle, inst, len(n_var), _dptr(ops, torch.uint16, "ops"), ops.shape[1],
+        _dptr(rt_end, torch.uint16, "rt_end"), rt_end.shape[1], nv, Np, n_warm, seed & (2**64 - 1), stride,
+        _dptr(po, torch.float32, "prio_out"), _dptr(ho, torch.float32, "hint_out"), _stream(stream)))
+    return po, ho
+
+
+def vrprpd_construct(S: InstanceSet, heuristic, inst=None, stream=None):
+    """One solution per instance from a construction heuristic (CONS_SWEEP,
+    CONS_NN, CONS_LB, CONS_SPT; see vrprpd_construct).  inst: device int32
+    instance indices, or None for every instance of the set in order.
+    Returns ops [B][2 n_max] and rt_end [B][m_max] (device uint16)."""
+    B = S.num_inst if inst is None else int(inst.numel())
+    dev = inst.device if inst is not None else torch.device("cuda", torch.cuda.current_device())
+    ops = torch.zeros((B, 2 * S.n_max), dtype=torch.uint16, device=dev)
+    rt = torch.zeros((B, S.m_max), dtype=torch.uint16, device=dev)
+    _check(load().vrprpd_construct(S.handle, B, _dptr(inst, torch.int32, "inst"), int(heuristic), 2 * S.n_max,
+                                   _dptr(ops, torch.uint16, "ops"), S.m_max, _dptr(rt, torch.uint16, "rt_end"),
+                                   _stream(stream)))
+    return ops, rt
+
+
 class BrkgaState:
     """Batched BRKGA over several instances (brkga_state_*)."""
 
@@ -399,6 +437,13 @@ class AlnsState:
         """Replay one captured iteration (True, the default) or launch every
         kernel of every iteration (False)."""
         _check(load().alns_set_graph(self.handle, 1 if enable else 0))
+
+    def refine(self, max_rounds=1000, stream=None):
+        """The construction's refinement rounds before the first iteration
+        (alns_refine); returns the number of rounds run."""
+        r = C.c_int32()
+        _check(load().alns_refine(self.handle, max_rounds, C.byref(r), _stream(stream)))
+        return r.value
 
     # ---- learned destroy proposal ------------------------------------------
     def set_learned(self, mlp, K=8, eps=0.1, stream=None):

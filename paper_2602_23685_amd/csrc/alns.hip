@@ -85,6 +85,7 @@ struct AlnsDev {
     uint16_t *ls_ops, *ls_rt;      // [C][LQ][2N], [C][LQ][M]: bases S without one candidate
     int32_t *ls_cand, *ls_pd;      // [C][LQ]: customer; its drop's (vehicle << 16 | position) in S
     int32_t *ls_nc, *ls_T, *ls_KD, *ls_KP, *ls_b, *ls_active, *ls_any;   // [C]
+    int32_t* ls_stop;              // [C] refinement: the chain's last round improved nothing
     int32_t *ls_base_inst, *ls_seg_base, *ls_seg_cnt, *ls_tmk;          // [C][LQ] / [C][LB]
     uint32_t* ls_tst;
     int64_t *ls_seg_off, *ls_base_off, *ls_rt_off, *ls_top3;            // [C][LQ] (top3: x3)
@@ -132,32 +133,6 @@ __device__ __forceinline__ int roulette(const double* w, int nops, uint32_t mask
     return last;
 }
 
-// Block-wide bitonic sort of n (power of two) u64 keys in LDS, ascending.
-__device__ void block_sort_u64(unsigned long long* key, int n)
-{
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const unsigned long long a = key[i], b = key[l];
-                    if ((a > b) == ((i & k) == 0)) {
-                        key[i] = b;
-                        key[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-__host__ __device__ inline int pow2_ge(int x)
-{
-    int p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
 
 // Sequential carving of dynamic LDS into 16-byte aligned arrays; the host
 // sizes the allocation with the same rounding (LdsSize).
@@ -1112,12 +1087,31 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
 // improving move replaces S).  A chain whose pass finds nothing stops.
 constexpr int kLsMaxCand = 256;
 
-__global__ void k_ls_begin(AlnsDev a, int reset_any)
+__global__ void k_ls_begin(AlnsDev a, int reset_any, int use_stop)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
-    a.ls_active[c] = 1;
+    a.ls_active[c] = use_stop ? !a.ls_stop[c] : 1;
     if (reset_any) a.ls_any[c] = 0;
+}
+
+// Refinement (the construction's last phase): a chain whose round improved
+// nothing stops; every chain starts its annealing at T0 times the refined
+// makespan.
+__global__ void k_refine_round_end(AlnsDev a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    if (!a.ls_any[c]) a.ls_stop[c] = 1;
+}
+
+__global__ void k_refine_temperature(AlnsDev a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    const double T = a.prm.T0 * (double)a.z[c];
+    a.T[c] = T;
+    a.T_init[c] = T;
 }
 
 template <typename DT>
@@ -1125,7 +1119,10 @@ __global__ __launch_bounds__(256) void k_ls_setup(AlnsDev a, int kind)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x;
-    if (!a.ls_active[c]) return;
+    if (!a.ls_active[c]) {              // nothing to scan for this chain
+        for (int i = threadIdx.x; i < a.LQ; i += blockDim.x) a.ls_seg_cnt[(int64_t)c * a.LQ + i] = 0;
+        return;
+    }
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int n = I.n, m = I.m, N1 = n + 1;
     const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
@@ -1800,12 +1797,13 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     A(d.seg_cnt, (size_t)C * Q); A(d.seg_base, (size_t)C * Q); A(d.seg_off, (size_t)C * Q + 1);
     A(d.seg_top3, (size_t)3 * C * Q); A(d.base_op_off, C); A(d.base_rt_off, C); A(d.evals, 1);
     A(d.cand_rem, (size_t)C * Q); A(d.cand_cnt, C); A(d.chosen, C); A(d.it_dev, 1);
-    if (P.ls_repos_interval > 0 || P.ls_reloc_interval > 0) {
+    if (P.ls_budget > 0) {   // periodic local search and refinement
         d.LQ = std::min(N, (int)kLsMaxCand);
         d.LB = (int64_t)P.ls_budget + d.LQ;
         const size_t CL = (size_t)C * d.LQ;
         A(d.ls_ops, CL * 2 * N); A(d.ls_rt, CL * M); A(d.ls_cand, CL); A(d.ls_pd, CL);
         A(d.ls_nc, C); A(d.ls_T, C); A(d.ls_KD, C); A(d.ls_KP, C); A(d.ls_b, C); A(d.ls_active, C); A(d.ls_any, C);
+        A(d.ls_stop, C);
         A(d.ls_base_inst, CL); A(d.ls_seg_base, CL); A(d.ls_seg_cnt, CL); A(d.ls_seg_off, CL + 1);
         A(d.ls_base_off, CL); A(d.ls_rt_off, CL); A(d.ls_top3, 3 * CL);
         A(d.ls_tuples, (size_t)C * d.LB); A(d.ls_tmk, (size_t)C * d.LB); A(d.ls_tst, (size_t)C * d.LB);
@@ -2008,6 +2006,43 @@ static int launch_gains(alns_state* s, hipStream_t st)
     return VRPRPD_OK;
 }
 
+// Up to three passes of one local search on every active chain.
+template <typename DT>
+static int launch_ls_passes(alns_state* s, hipStream_t st, int kind)
+{
+    AlnsDev& d = s->d;
+    ScanArgs la{d.inst_tab, d.dist, d.proc, d.ls_base_inst, d.ls_base_off, d.ls_ops, d.ls_rt_off, d.ls_rt,
+                d.ls_seg_off, d.ls_seg_base, d.ls_tuples, d.ls_tmk, d.ls_tst, d.ls_top3, d.ls_seg_cnt,
+                d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 4};
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_ls_setup<DT>, dim3(d.C), dim3(256), s->lds_ls, st, d, kind);
+        hipLaunchKernelGGL(k_ls_enum<DT>, dim3(d.C, d.LQ), dim3(256), s->lds_enum, st, d, kind);
+        VRP_HIP(hipGetLastError());
+        const int rc = insert_scan_launch(la, d.M, s->dist16, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_ls_apply, dim3(d.C), dim3(256), 0, st, d);
+        VRP_HIP(hipGetLastError());
+    }
+    return VRPRPD_OK;
+}
+
+// One refinement round on every chain not yet stopped: repositioning, then
+// relocation, then the stop flags.
+template <typename DT>
+static int launch_refine_round(alns_state* s, hipStream_t st)
+{
+    AlnsDev& d = s->d;
+    for (int kind = 0; kind < 2; ++kind) {
+        hipLaunchKernelGGL(k_ls_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, kind == 0 ? 1 : 0, 1);
+        const int rc = launch_ls_passes<DT>(s, st, kind);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_ls_finish, dim3(d.C), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_refine_round_end, dim3((d.C + 63) / 64), dim3(64), 0, st, d);
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
+}
+
 // The launches of one iteration.  Nothing here depends on host-side state
 // that changes between iterations (the iteration number lives on the
 // device), so the sequence can be captured once and replayed.
@@ -2048,22 +2083,12 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
     hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d);
     VRP_HIP(hipGetLastError());
     if (ls_mask) {
-        ScanArgs la{d.inst_tab, d.dist, d.proc, d.ls_base_inst, d.ls_base_off, d.ls_ops, d.ls_rt_off, d.ls_rt,
-                    d.ls_seg_off, d.ls_seg_base, d.ls_tuples, d.ls_tmk, d.ls_tst, d.ls_top3, d.ls_seg_cnt,
-                    d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 4};
         bool first = true;
         for (int kind = 0; kind < 2; ++kind) {
             if (!(ls_mask & (1 << kind))) continue;
-            hipLaunchKernelGGL(k_ls_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, first ? 1 : 0);
+            hipLaunchKernelGGL(k_ls_begin, dim3((d.C + 63) / 64), dim3(64), 0, st, d, first ? 1 : 0, 0);
             first = false;
-            for (int pass = 0; pass < 3; ++pass) {
-                hipLaunchKernelGGL(k_ls_setup<DT>, dim3(d.C), dim3(256), s->lds_ls, st, d, kind);
-                hipLaunchKernelGGL(k_ls_enum<DT>, dim3(d.C, d.LQ), dim3(256), s->lds_enum, st, d, kind);
-                VRP_HIP(hipGetLastError());
-                if ((rc = insert_scan_launch(la, d.M, s->dist16, st))) return rc;
-                hipLaunchKernelGGL(k_ls_apply, dim3(d.C), dim3(256), 0, st, d);
-                VRP_HIP(hipGetLastError());
-            }
+            if ((rc = launch_ls_passes<DT>(s, st, kind))) return rc;
         }
         hipLaunchKernelGGL(k_ls_finish, dim3(d.C), dim3(256), 0, st, d);
         VRP_HIP(hipGetLastError());
@@ -2143,6 +2168,33 @@ extern "C" int alns_step(alns_state* s, int32_t iterations, void* stream)
         }
         s->it += 1;
     }
+    return VRPRPD_OK;
+}
+
+extern "C" int alns_refine(alns_state* s, int32_t max_rounds, int32_t* rounds_out, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || max_rounds < 0) return set_error(VRPRPD_EINVAL, "alns_refine: bad arguments");
+    if (s->it != 0) return set_error(VRPRPD_EINVAL, "alns_refine: only before the first iteration");
+    if (!s->d.ls_stop) return set_error(VRPRPD_EINVAL, "alns_refine: the state was created with ls_budget < 1");
+    AlnsDev& d = s->d;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    VRP_HIP(hipMemsetAsync(d.ls_stop, 0, (size_t)d.C * sizeof(int32_t), st));
+    std::vector<int32_t> stop(d.C);
+    int rounds = 0;
+    while (rounds < max_rounds) {
+        const int rc = s->dist16 ? launch_refine_round<uint16_t>(s, st) : launch_refine_round<int32_t>(s, st);
+        if (rc) return rc;
+        ++rounds;
+        VRP_HIP(hipMemcpyAsync(stop.data(), d.ls_stop, (size_t)d.C * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        VRP_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int c = 0; c < d.C && all; ++c) all = stop[c] != 0;
+        if (all) break;
+    }
+    hipLaunchKernelGGL(k_refine_temperature, dim3((d.C + 63) / 64), dim3(64), 0, st, d);
+    VRP_HIP(hipGetLastError());
+    if (rounds_out) *rounds_out = rounds;
     return VRPRPD_OK;
 }
 

@@ -22,7 +22,8 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 
 // Per-instance description as the kernels see it.
 struct InstDev {
-    int32_t n, m, k, R, load_model, pad;
+    int32_t n, m, k, R, load_model;
+    int32_t ashift;  // right shift bringing every distance below 2^14 (pseudo-angles)
     int64_t d_off;  // element offset of d[0][0] in the packed distance buffer
     int64_t p_off;  // element offset of p[0] in the processing-time buffer
 };
@@ -118,6 +119,36 @@ __device__ __forceinline__ void lds_store(int* p, int v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
+
+// Least power of two >= x (x >= 1).
+__host__ __device__ inline int pow2_ge(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Block-wide bitonic sort of n (power of two) u64 keys, ascending; key may
+// point to LDS or to global memory private to the block.
+__device__ inline void block_sort_u64(unsigned long long* key, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __device__ __forceinline__ void wave_lds_fence()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

@@ -128,9 +128,17 @@ __global__ __launch_bounds__(256) void evolve_kernel(EvolveArgs a)
     }
 }
 
+// Block s encodes source s (ops + s * op_stride, rt + s * rt_stride) into
+// p0 / h0 + s * enc_stride.
 __global__ __launch_bounds__(256) void warm_encode_kernel(const InstDev* inst_tab, int32_t ii, const uint16_t* ops,
-                                                          const uint16_t* rt, float* p0, float* h0)
+                                                          const uint16_t* rt, float* p0, float* h0,
+                                                          int64_t op_stride = 0, int64_t rt_stride = 0,
+                                                          int64_t enc_stride = 0)
 {
+    ops += blockIdx.x * op_stride;
+    rt += blockIdx.x * rt_stride;
+    p0 += blockIdx.x * enc_stride;
+    h0 += blockIdx.x * enc_stride;
     const InstDev I = inst_tab[ii];
     const int G = 2 * I.n, m = I.m;
     for (int o = threadIdx.x; o < G; o += 256) {
@@ -147,6 +155,64 @@ __global__ __launch_bounds__(256) void warm_encode_kernel(const InstDev* inst_ta
             const int o = 2 * (c - 1) + isP;
             p0[o] = (float)((double)(j - s) / (double)L);
             h0[o] = (float)(((double)v + 0.5) / (double)m);
+        }
+    }
+}
+
+// A variant's gene: moved by U(-0.03, 0.03) (fp64) and clamped into [0, 1).
+__device__ inline float perturb(float g, uint32_t w)
+{
+    const double uu = (double)(w >> 8) * (1.0 / 16777216.0);
+    double x = (double)g + (uu * 0.06 - 0.03);
+    if (x < 0.0) x = 0.0;
+    g = (float)x;
+    return g >= 1.0f ? 0.99999994f : g;
+}
+
+constexpr int kMaxWarmSources = 16;
+struct WarmSources {
+    int32_t n_src, total;
+    int32_t cum[kMaxWarmSources + 1];   // first variant index of each source
+};
+
+// Slot i of a population warm-started from several sources: slots below
+// n_warm cycle through the sources' variants (source order), the rest are
+// fresh U(0,1) individuals.
+__global__ __launch_bounds__(256) void warm_multi_fill_kernel(int32_t G, int64_t stride, int32_t n_warm,
+                                                              WarmSources src, uint64_t seed, const float* enc_p,
+                                                              const float* enc_h, float* prio, float* hint)
+{
+    const int i = blockIdx.x;
+    float* dp = prio + (int64_t)i * stride;
+    float* dh = hint + (int64_t)i * stride;
+    const bool warm = i < n_warm && src.total > 0;
+    int s = 0;
+    uint32_t var = 0;
+    if (warm) {
+        const int q = i % src.total;
+        while (q >= src.cum[s + 1]) ++s;
+        var = (uint32_t)(q - src.cum[s]);
+    }
+    const float* p0 = enc_p + (int64_t)s * G;
+    const float* h0 = enc_h + (int64_t)s * G;
+    for (int blk = threadIdx.x; 4 * blk < 2 * G; blk += 256) {
+        const Philox4 r = warm ? philox4x32_10((uint32_t)blk, var, (uint32_t)s, kTagWarm, (uint32_t)seed,
+                                               (uint32_t)(seed >> 32))
+                               : philox4x32_10((uint32_t)blk, (uint32_t)i, 0u, kTagRandom, (uint32_t)seed,
+                                               (uint32_t)(seed >> 32));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * blk + u;
+            if (j >= 2 * G) break;
+            float g;
+            if (warm) {
+                g = j < G ? p0[j] : h0[j - G];
+                if (var) g = perturb(g, r.x[u]);
+            } else {
+                g = unit24(r.x[u]);
+            }
+            if (j < G) dp[j] = g;
+            else dh[j - G] = g;
         }
     }
 }
@@ -173,13 +239,7 @@ __global__ __launch_bounds__(256) void warm_fill_kernel(int32_t G, int64_t strid
             float g;
             if (i < n_warm) {
                 g = j < G ? p0[j] : h0[j - G];
-                if (var) {
-                    const double uu = (double)(r.x[u] >> 8) * (1.0 / 16777216.0);
-                    double x = (double)g + (uu * 0.06 - 0.03);
-                    if (x < 0.0) x = 0.0;
-                    g = (float)x;
-                    if (g >= 1.0f) g = 0.99999994f;
-                }
+                if (var) g = perturb(g, r.x[u]);
             } else {
                 g = unit24(r.x[u]);
             }
@@ -237,6 +297,44 @@ extern "C" int brkga_warm_start(const vrprpd_set* set, int32_t inst, const uint1
                            seed, prio_out, hint_out);
         VRP_HIP(hipGetLastError());
     }
+    return VRPRPD_OK;
+}
+
+extern "C" int brkga_warm_start_multi(const vrprpd_set* set, int32_t inst, int32_t n_src, const uint16_t* ops,
+                                      int64_t op_stride, const uint16_t* rt_end, int64_t rt_stride,
+                                      const int32_t* n_var, int32_t Np, int32_t n_warm, uint64_t seed,
+                                      int64_t key_stride, float* prio_out, float* hint_out, void* stream)
+{
+    if (!set || inst < 0 || inst >= set->num_inst || n_src < 1 || n_src > kMaxWarmSources || !ops || !rt_end ||
+        !n_var || !prio_out || !hint_out || Np < 1 || n_warm < 0 || n_warm > Np)
+        return set_error(VRPRPD_EINVAL, "brkga_warm_start_multi: bad arguments");
+    const InstDev& I = set->host[inst];
+    const int G = 2 * I.n;
+    if (key_stride < G || op_stride < G || rt_stride < I.m)
+        return set_error(VRPRPD_EINVAL, "brkga_warm_start_multi: need key_stride, op_stride >= 2n and rt_stride >= m");
+    WarmSources src{};
+    src.n_src = n_src;
+    for (int s = 0; s < n_src; ++s) {
+        if (n_var[s] < 0) return set_error(VRPRPD_EINVAL, "brkga_warm_start_multi: n_var[%d] < 0", s);
+        src.cum[s + 1] = src.cum[s] + n_var[s];
+    }
+    for (int s = n_src + 1; s <= kMaxWarmSources; ++s) src.cum[s] = src.cum[n_src];
+    src.total = src.cum[n_src];
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    void* enc = nullptr;
+    VRP_HIP(hipMallocAsync(&enc, (size_t)2 * n_src * G * sizeof(float), st));
+    float* ep = static_cast<float*>(enc);
+    float* eh = ep + (size_t)n_src * G;
+    hipLaunchKernelGGL(warm_encode_kernel, dim3(n_src), dim3(256), 0, st, set->d_inst, inst, ops, rt_end, ep, eh,
+                       op_stride, rt_stride, (int64_t)G);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(warm_multi_fill_kernel, dim3(Np), dim3(256), 0, st, G, key_stride, n_warm, src, seed, ep,
+                           eh, prio_out, hint_out);
+        e = hipGetLastError();
+    }
+    (void)hipFreeAsync(enc, st);
+    if (e != hipSuccess) return hip_error(e, "brkga_warm_start_multi: launch");
     return VRPRPD_OK;
 }
 

@@ -83,8 +83,10 @@ extern "C" int vrprpd_set_create(vrprpd_set** out, int32_t num_inst, const vrprp
                              (long long)((2 * (int64_t)D.n + 1) * dmax + psum));
         }
         if (dmax > 65535) s->dist16 = 0;
+        int ashift = 0;
+        while ((dmax >> ashift) >= (1 << 14)) ++ashift;
         InstDev& h = s->host[i];
-        h = InstDev{D.n, D.m, D.k, D.R, D.load_model, 0, dsz, psz};
+        h = InstDev{D.n, D.m, D.k, D.R, D.load_model, ashift, dsz, psz};
         dsz += N1 * N1;
         psz += (N1 + 3) & ~int64_t(3);   // 16-byte aligned rows: kernels read p in int4 vectors
         if (D.n > s->n_max) s->n_max = D.n;

@@ -95,3 +95,9 @@ def test_host_argument_checks_of_the_newer_entry_points(lib):
     assert lib.vrprpd_autotune_eval(None, 1, None, None, None, None, None, 0, None, None, 1, None, None, None,
                                     None) == E
     assert b"autotune" in lib.vrprpd_last_error()
+    # construction heuristics, several-source warm start, refinement
+    assert lib.vrprpd_construct(None, 1, None, 0, 2, None, 1, None, None) == E
+    assert b"vrprpd_construct" in lib.vrprpd_last_error()
+    nv = (C.c_int32 * 1)(1)
+    assert lib.brkga_warm_start_multi(None, 0, 1, None, 2, None, 1, nv, 8, 1, 0, 2, None, None, None) == E
+    assert lib.alns_refine(None, 5, None, None) == E
