@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["eval.c", "decode.c", "scan.c", "brkga.c", "alns.c", "construct.c"]
+SOURCES = ["eval.c", "decode.c", "scan.c", "brkga.c", "alns.c", "construct.c", "stats.c"]
 
 BAD_COVER, LOAD, RES, DEADLOCK, BAD_KEY, BAD_TUPLE = 1, 2, 4, 8, 16, 32
 MIN_PRELOAD, FULL_START = 0, 1
@@ -89,12 +89,14 @@ def _declare(L):
     L.orc_cons_angle_order.argtypes = [P, P]
     L.orc_cons_sectors.restype = C.c_int32
     L.orc_cons_sectors.argtypes = [P, P, P]
+    L.orc_solution_stats.restype = C.c_int32
+    L.orc_solution_stats.argtypes = [P, P, P, P, P]
     if hasattr(L, "orc_alns_run"):
         _declare_alns(L)
 
 
 class AlnsParams(C.Structure):
-    """Table 2 hyper-parameters (Section 4.2.6) plus this build's repair budget."""
+    """Table 2 hyper-parameters (Section 4.2.7) plus this build's repair budget."""
     _fields_ = [("T0", C.c_double), ("alpha", C.c_double), ("reheat", C.c_double), ("gate", C.c_double),
                 ("stag_limit", C.c_int32), ("tau", C.c_int32), ("r", C.c_double),
                 ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
@@ -405,7 +407,7 @@ def cons_sectors(inst):
 def refine(inst, ops, rt_end, budget=16384, max_rounds=1000):
     """The construction's refinement (Section 4.2, initial solution, last
     phase): rounds of pickup repositioning then cross-agent relocation (up
-    to three passes each, Section 4.2.5) until a round improves nothing.
+    to three passes each, Section 4.2.6) until a round improves nothing.
     Returns (rounds run, makespan, ops, rt_end)."""
     z = eval_one(inst, ops, rt_end)[0]
     rounds = 0
@@ -416,6 +418,17 @@ def refine(inst, ops, rt_end, budget=16384, max_rounds=1000):
         if k0 == 0 and k1 == 0:
             break
     return rounds, int(z), ops, rt_end
+
+
+def solution_stats(inst, ops, rt_end):
+    """(cross-vehicle customers, interleaved customers) of a solution
+    (Section 5.2), or None when its cover is incomplete or it deadlocks."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    x = np.zeros(2, np.int32)
+    rc = lib().orc_solution_stats(oi.ref, _ptr(ops), _ptr(rt), _ptr(x[:1]), _ptr(x[1:]))
+    return None if rc < 0 else (int(x[0]), int(x[1]))
 
 
 def int32_safe(inst) -> bool:

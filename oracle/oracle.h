@@ -104,7 +104,7 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
  * written to rem, or -1 if the solution is infeasible. */
 int32_t orc_alns_destroy(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, int32_t q,
                          int32_t q_min, uint64_t seed, uint32_t it, uint32_t chain, int32_t cand, int32_t* rem);
-/* Periodic local search (Section 4.2.5) on a complete feasible solution: kind
+/* Periodic local search (Section 4.2.6) on a complete feasible solution: kind
  * 0 pickup repositioning, 1 cross-agent relocation, up to `passes` passes of
  * `budget` tuples.  Returns the number of improving passes (-1: infeasible). */
 int32_t orc_alns_local_search(const orc_inst* I, int32_t kind, int32_t budget, int32_t passes, const uint16_t* ops,
@@ -130,4 +130,10 @@ int32_t orc_construct(const orc_inst* I, int32_t heuristic, uint16_t* ops, uint1
 int32_t orc_cons_vehicles(const orc_inst* I);
 void orc_cons_angle_order(const orc_inst* I, int32_t* order);
 int32_t orc_cons_sectors(const orc_inst* I, int32_t* sector0, int32_t* sector);
+
+/* Coordination statistics of a solution (Section 5.2): customers served
+ * cross-vehicle and customers interleaved.  Returns 0, or -1 when the cover
+ * is incomplete or the schedule deadlocks. */
+int32_t orc_solution_stats(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end, int32_t* cross,
+                           int32_t* interleaved);
 #endif
