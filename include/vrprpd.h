@@ -372,7 +372,7 @@ int brkga_state_get(const brkga_state* st, int64_t* generations, int64_t* best_f
 int brkga_state_destroy(brkga_state* st);
 
 /* ---- ALNS (Section 4.2) ----------------------------------------------------
- * alns_params: the hyper-parameters of Table 2 (Section 4.2.6) plus this
+ * alns_params: the hyper-parameters of Table 2 (Section 4.2.7) plus this
  * library's repair budget.  Defaults: T0 = 0.30, alpha = 0.9998, reheat =
  * 0.50, gate = 0.01, stag_limit = 2000, tau = 100, r = 0.1, sigma = (33, 9,
  * 13), w_min = 0.1, q_min = q_max = 0 (the rule of Section 4.2.2:
@@ -381,7 +381,7 @@ int brkga_state_destroy(brkga_state* st);
  * op_mask = 0x0F3F (all six destroy and four repair operators),
  * ls_repos_interval = 200, ls_reloc_interval = 500, ls_budget = 16384.
  *
- * Periodic local search (Section 4.2.5), after the acceptance step of every
+ * Periodic local search (Section 4.2.6), after the acceptance step of every
  * ls_repos_interval-th (pickup repositioning) and ls_reloc_interval-th
  * (cross-agent relocation) iteration, repositioning first; 0 turns one off.
  * Up to three passes each, on the chain's current solution, no acceptance
@@ -477,7 +477,7 @@ int alns_state_destroy(alns_state* st);
 int alns_refine(alns_state* st, int32_t max_rounds, int32_t* rounds_out, void* stream);
 
 /* ---- ALNS with a learned destroy proposal ----------------------------------
- * (Section 6 names learned destroy operators as future work; this is the
+ * (Section 7.4 names learned destroy operators as future work; this is the
  * library's form.)  Each iteration every chain builds K candidate removal
  * sets with the roulette-selected destroy operator, candidate j drawing its
  * random words at counters 16 + 4096 j + i (candidate 0 is the plain
@@ -527,7 +527,7 @@ int alns_get_learned(const alns_state* st, uint16_t* feat, int32_t* cand_rem, in
                      void* stream);
 
 /* ---- Learned destroy proposal: the scorer network --------------------------
- * The paper names learned destroy operators as future work (Section 6) and
+ * The paper names learned destroy operators as future work (Section 7.4) and
  * fixes no model.  This library's: per-customer features (VRPRPD_MLP_IN =
  * 64) -> 256 -> 256 -> 256 -> 1, ReLU after each hidden layer.  A removal
  * set's score is the sum of its customers' scores; training fits it to the

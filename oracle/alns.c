@@ -418,7 +418,7 @@ static int destroy(const orc_inst* I, int op, const sol_t* S, int32_t z, int q, 
 
 /* ------------------------------------------------------------------ local search */
 #define LS_MAX_CAND 256   /* candidates per pass: the first 256 in order */
-/* One pass of a periodic local search (Section 4.2.5) on the current
+/* One pass of a periodic local search (Section 4.2.6) on the current
  * solution S.  kind 0, pickup repositioning: every pickup on a vehicle that
  * returns within 5% of the makespan (20 f_v >= 19 z), in route order, may
  * move to any pickup slot of any vehicle (after its drop on the drop's
@@ -794,7 +794,7 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
                 tr[2] = c->zb;
                 tr[3] = di | (ri << 8) | (accepted << 16) | ((int64_t)nrem << 24);
             }
-            /* periodic local search on the current solution (Section 4.2.5):
+            /* periodic local search on the current solution (Section 4.2.6):
              * repositioning before relocation when both fall due */
             int ls_any = 0;
             if (P->ls_repos_interval > 0 && (it + 1) % P->ls_repos_interval == 0)

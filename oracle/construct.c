@@ -7,7 +7,7 @@
  *    workload estimate w_c = 2 d(0,c) + p_c, and a nearest-neighbour route
  *    per vehicle.  The fourth phase (refinement by relocation and pickup
  *    reassignment until nothing improves) is the local search of Section
- *    4.2.5 run to a fixed point; oracle/__init__.py composes it.
+ *    4.2.6 run to a fixed point; oracle/__init__.py composes it.
  * 2. The three construction seeds of the BRKGA warm start (Section 4.4.4):
  *    nearest neighbour, load balanced, shortest processing time.
  *

@@ -1,7 +1,7 @@
 """Oracle for the learned destroy proposal's per-customer features (test
 infrastructure only).
 
-The paper leaves learned destroy operators to future work (Section 6); the
+The paper leaves learned destroy operators to future work (Section 7.4); the
 feature set is this project's.  For a complete, feasible solution S with its
 earliest-start schedule (Section 3, Eq. 7-12) every customer c gets 64 fp32
 features: 32 base features and the same 32 gated by "c's drop or pickup

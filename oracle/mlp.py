@@ -1,7 +1,7 @@
 """Oracle for the learned destroy proposal's scorer network (test
 infrastructure only: only tests, the smoke check and the CPU baseline use it).
 
-The paper names learned destroy operators as future work (Section 6) and fixes
+The paper names learned destroy operators as future work (Section 7.4) and fixes
 no network; the one here is this project's: per-customer features (64) ->
 256 -> 256 -> 256 -> 1 with ReLU after the hidden layers.  The score of a
 removal set is the sum of its customers' scores, fitted by mean squared error

@@ -62,7 +62,7 @@ struct AlnsDev {
     int64_t trace_cap, trace_base; // capacity; iteration of trace row 0
     uint32_t* it_dev;              // iteration counter (advanced by k_tick at the end of an iteration)
     unsigned long long* evals;     // exact evaluations performed (tuples and removal gains)
-    // learned destroy proposal (Section 6 names learned operators as future
+    // learned destroy proposal (Section 7.4 names learned operators as future
     // work; this library's form): K candidate removal sets per chain, scored
     // by the network from per-customer features
     int32_t K;                     // candidates per chain (1: the plain operator's set only)
@@ -79,7 +79,7 @@ struct AlnsDev {
     float* rec_t;                  // [rec_cap] (z' - z) / z
     int32_t* rec_n;                // [rec_cap] removed customers
     int64_t rec_cap, rec_base;     // capacity in sets; iteration of the first record
-    // periodic local search (Section 4.2.5); buffers exist when an interval is on
+    // periodic local search (Section 4.2.6); buffers exist when ls_budget > 0
     int32_t LQ;                    // candidates per pass at most
     int64_t LB;                    // tuple slots per chain
     uint16_t *ls_ops, *ls_rt;      // [C][LQ][2N], [C][LQ][M]: bases S without one candidate
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
 }
 
 // ---------------------------------------------------------------- local search
-// Periodic local search on each chain's current solution (Section 4.2.5):
+// Periodic local search on each chain's current solution (Section 4.2.6):
 // kind 0 pickup repositioning, kind 1 cross-agent relocation.  A pass is
 // setup (schedule, candidates, one base S without the candidate per
 // candidate), enumeration of ranked tuples per candidate, the insertion scan

@@ -1,7 +1,7 @@
 // The learned destroy proposal's scorer network on the GPU: forward,
 // backward and a momentum SGD step, all in this file's kernels.
 //
-// The paper lists learned destroy operators as future work (Section 6); the
+// The paper lists learned destroy operators as future work (Section 7.4); the
 // network is this library's: per-customer features (64) -> 256 -> 256 -> 256
 // -> 1, ReLU after each hidden layer.  A removal set's score is the sum of
 // its customers' scores, fitted to the makespan change by mean squared error.

@@ -121,7 +121,7 @@ LS_CASES = [
 @pytest.mark.parametrize("case", LS_CASES, ids=lambda c: f"n{c[0]}m{c[1]}r{c[8]}x{c[9]}")
 def test_alns_local_search_parity(orc, P, case):
     """Periodic pickup repositioning and cross-agent relocation (Section
-    4.2.5) at short intervals: trajectories, best makespans and solutions
+    4.2.6) at short intervals: trajectories, best makespans and solutions
     bit-identical to the oracle, with graph replay and with direct launches."""
     n, m, k, R, rule, chains, iters, budget, repos, reloc, lsb = case
     inst = synth.make_instance(n, m, k, R, rule, seed=9100 + n)

@@ -1,4 +1,4 @@
-"""Pins for the periodic local search of the ALNS oracle (Section 4.2.5):
+"""Pins for the periodic local search of the ALNS oracle (Section 4.2.6):
 with a budget above every neighbourhood's size, one pass equals the best move
 found by brute force over the moves the paper describes (CPU only)."""
 import numpy as np
