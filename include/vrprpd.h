@@ -337,6 +337,25 @@ int brkga_warm_start_multi(const vrprpd_set* set, int32_t inst, int32_t n_src, c
  * Allocates a stream-ordered workspace (about 40 n_max bytes per instance).
  * Errors: EINVAL, EHIP.
  */
+/*
+ * vrprpd_solution_stats — the coordination measures of Section 5.2 per
+ * solution: cross[b] = customers whose drop and pickup are on different
+ * vehicles; interleaved[b] = customers for which the drop vehicle does
+ * another operation between the drop and the pickup (same vehicle: an
+ * operation between the two in its route; another vehicle: the drop
+ * vehicle's next operation, if its time -- arrival for a drop, departure for
+ * a pickup, in the earliest-start schedule -- is before the pickup's time).
+ * Both -1 when the cover is incomplete (every customer needs exactly one drop
+ * and one pickup), the route ends are invalid, the instance index is out of
+ * range, or the waits form a cycle.  Arguments as vrprpd_eval (inst, op_off,
+ * rt_off NULL-able the same way); cross, interleaved [B] int32 out.
+ * Allocates a stream-ordered workspace (about 24 n_max bytes for each of at
+ * most 2048 blocks).  Errors: EINVAL, EHIP.
+ */
+int vrprpd_solution_stats(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
+                          const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t* cross,
+                          int32_t* interleaved, void* stream);
+
 #define VRPRPD_CONS_SWEEP 0
 #define VRPRPD_CONS_NN 1
 #define VRPRPD_CONS_LB 2

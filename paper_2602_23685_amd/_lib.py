@@ -81,6 +81,7 @@ SIGNATURES = {
     "brkga_warm_start_multi": (C.c_int, [_P, _I32, _I32, _P, _I64, _P, _I64, _P, _I32, _I32, _U64, _I64, _P, _P,
                                          _P]),
     "alns_refine": (C.c_int, [_P, _I32, _P, _P]),
+    "vrprpd_solution_stats": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT = 0, 1, 2, 3
@@ -302,6 +303,21 @@ def brkga_warm_start_multi(S: InstanceSet, ops, rt_end, n_var, Np, n_warm, seed,
         _dptr(rt_end, torch.uint16, "rt_end"), rt_end.shape[1], nv, Np, n_warm, seed & (2**64 - 1), stride,
         _dptr(po, torch.float32, "prio_out"), _dptr(ho, torch.float32, "hint_out"), _stream(stream)))
     return po, ho
+
+
+def vrprpd_solution_stats(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None, stream=None):
+    """Cross-vehicle and interleaved customer counts per solution (see
+    vrprpd_solution_stats): ops [B][>= 2n], rt_end [B][>= m] device uint16
+    (strides 2 n(0) and m(0) unless offsets are given).  Returns two [B]
+    int32 device tensors (-1 where a solution has no schedule)."""
+    B = ops.shape[0] if ops.dim() == 2 else 1
+    cross = torch.empty(B, dtype=torch.int32, device=ops.device)
+    inter = torch.empty(B, dtype=torch.int32, device=ops.device)
+    _check(load().vrprpd_solution_stats(
+        S.handle, B, _dptr(inst, torch.int32, "inst"), _dptr(op_off, torch.int64, "op_off"),
+        _dptr(ops, torch.uint16, "ops"), _dptr(rt_off, torch.int64, "rt_off"), _dptr(rt_end, torch.uint16, "rt_end"),
+        _dptr(cross, torch.int32, "cross"), _dptr(inter, torch.int32, "interleaved"), _stream(stream)))
+    return cross, inter
 
 
 def vrprpd_construct(S: InstanceSet, heuristic, inst=None, stream=None):

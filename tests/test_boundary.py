@@ -101,3 +101,4 @@ def test_host_argument_checks_of_the_newer_entry_points(lib):
     nv = (C.c_int32 * 1)(1)
     assert lib.brkga_warm_start_multi(None, 0, 1, None, 2, None, 1, nv, 8, 1, 0, 2, None, None, None) == E
     assert lib.alns_refine(None, 5, None, None) == E
+    assert lib.vrprpd_solution_stats(None, 1, None, None, None, None, None, None, None, None) == E
