@@ -1,14 +1,20 @@
 // brkga_decode_eval: the multi-pass decoder of Section 4.4.2 (Algorithm 2)
 // and the makespan / penalised fitness of the schedule it builds.
 //
-// Mapping: one wavefront per chromosome.  The wave
-//  1. loads and checks the 2n priority keys (and hints),
-//  2. sorts (key, op index) pairs with a bitonic network in LDS,
-//  3. runs the passes: the ops in priority order are scanned in chunks of 64
-//     lanes; a ballot finds the next unscheduled op that is feasible at its
-//     turn, lanes v < m price it on vehicle v (completion time, hint-rotated
-//     tie index) and a 64-bit min-reduction picks the vehicle,
-//  4. scatters the schedule into per-vehicle sequences (optional output).
+// Mapping: one wavefront per chromosome, in two launches.
+//  decode_sort_kernel: loads and checks the 2n priority keys (and hints) and
+//     sorts (key, op index) pairs with a bitonic network in LDS; the op order
+//     goes to a workspace in global memory.
+//  decode_kernel: runs the passes: the ops in priority order are read in
+//     chunks of 64 lanes (the next chunk's load in flight); a ballot finds the
+//     next unscheduled op that is feasible at its turn, lanes v < m price it
+//     on vehicle v (completion time, hint-rotated tie index) and the least
+//     key picks the vehicle; then optionally scatters the schedule into
+//     per-vehicle sequences.
+// The passes, a long chain of dependent wave-wide decisions, keep only
+// ready[] and the scheduled-op bits in LDS (about 4n bytes), so many more
+// chromosomes are in flight per CU than if the sort's 6 bytes per op stayed
+// allocated through them.
 #include <climits>
 
 #include "common.h"
@@ -32,21 +38,24 @@ struct DecodeArgs {
     int64_t ops_stride, rt_stride;
     int64_t B;
     int32_t num_inst, n_max, cap, nblocks;
-};
-
-struct DecodeLayout {
-    int keys_off, idx_off, ready_off, bits_off, bytes;
+    uint16_t* order;       // [B][cap] op indices in priority order (workspace)
+    uint8_t* badkey;       // [B] 1: the chromosome's keys failed the check (workspace)
+    uint32_t* log;         // [B][cap] schedule log, code | vehicle << 16 (workspace, with ops_out)
 };
 
 __host__ __device__ inline int d16(int x) { return (x + 15) & ~15; }
 
+// LDS of the sort launch: keys, op indices.
+__host__ __device__ inline int sort_lds_bytes(int cap) { return d16(4 * cap) + d16(2 * cap); }
+// LDS of the pass launch: ready[], scheduled bits.
+struct DecodeLayout {
+    int ready_off, bits_off, bytes;
+};
 __host__ __device__ inline DecodeLayout decode_layout(int n_max, int cap)
 {
     DecodeLayout L;
-    L.keys_off = 0;                                   // later reused for the schedule log
-    L.idx_off = d16(4 * cap);
-    L.ready_off = L.idx_off + d16(2 * cap);
-    L.bits_off = L.ready_off + d16(4 * (n_max + 1));
+    L.ready_off = 0;
+    L.bits_off = d16(4 * (n_max + 1));
     L.bytes = L.bits_off + d16(4 * ((cap + 31) / 32));
     return L;
 }
@@ -86,30 +95,19 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
     return x;
 }
 
-template <typename DT>
-__global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
+__global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
     if (b >= a.B) return;
-    const DecodeLayout L = decode_layout(a.n_max, a.cap);
-    uint32_t* keys = reinterpret_cast<uint32_t*>(smem + L.keys_off);
-    uint16_t* idx = reinterpret_cast<uint16_t*>(smem + L.idx_off);
-    int* ready = reinterpret_cast<int*>(smem + L.ready_off);
-    uint32_t* sched = reinterpret_cast<uint32_t*>(smem + L.bits_off);
-    // schedule log, written after the sort no longer needs keys[]
-    uint16_t* log_code = reinterpret_cast<uint16_t*>(smem + L.keys_off);
-    uint8_t* log_veh = reinterpret_cast<uint8_t*>(smem + L.keys_off + 2 * a.cap);
-
+    uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
+    uint16_t* idx = reinterpret_cast<uint16_t*>(smem + d16(4 * a.cap));
     int ii = a.inst ? a.inst[b] : 0;
     const bool bad_inst = ii < 0 || ii >= a.num_inst;
     if (bad_inst) ii = 0;
     const InstDev I = a.inst_tab[ii];
-    const int n = I.n, m = I.m, k = I.k, R = I.R, N1 = n + 1, O = 2 * n;
-    const bool minpre = I.load_model != VRPRPD_FULL_START;
-    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
-    const int32_t* P = a.proc + I.p_off;
+    const int n = I.n, m = I.m, O = 2 * n;
     const float* pr = a.prio + b * a.key_stride;
     const float* hn = a.hint ? a.hint + b * a.key_stride : nullptr;
     int cap = 64;
@@ -127,10 +125,9 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
         keys[o] = kb;
         idx[o] = (uint16_t)(o < O ? o : 0xFFFF);
     }
-    for (int w = lane; w < (cap + 31) / 32; w += 64) sched[w] = 0u;
-    for (int c = lane; c <= n; c += 64) ready[c] = 0;
     if (__ballot(bad)) {
         if (lane == 0) {
+            a.badkey[b] = 1;
             a.fitness[b] = INT64_MAX;
             a.makespan[b] = INT32_MAX;
             a.unscheduled[b] = O;
@@ -162,6 +159,63 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
             wave_lds_fence();
         }
     }
+    uint16_t* ord = a.order + b * a.cap;
+    for (int j = lane; j < O; j += 64) ord[j] = idx[j];
+    if (lane == 0) a.badkey[b] = 0;
+}
+
+// Minima by DPP row shifts (VALU only, no LDS crossbar, no scalar chain):
+// after shifts by 1, 2, 4, 8 within each row of 16 lanes, lane 15 of a row
+// holds the row's minimum; row broadcasts fold rows 0-3 into lane 63.
+// Lanes a shift reads from outside the row keep INT_MAX.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_min_step(int x)
+{
+    const int y = __builtin_amdgcn_update_dpp(INT_MAX, x, CTRL, ROWS, 0xF, false);
+    return y < x ? y : x;
+}
+__device__ __forceinline__ int row0_min(int x)   // minimum over lanes 0-15
+{
+    x = dpp_min_step<0x111, 0xF>(x);   // row_shr:1
+    x = dpp_min_step<0x112, 0xF>(x);   // row_shr:2
+    x = dpp_min_step<0x114, 0xF>(x);   // row_shr:4
+    x = dpp_min_step<0x118, 0xF>(x);   // row_shr:8
+    return __builtin_amdgcn_readlane(x, 15);
+}
+__device__ __forceinline__ int wave_min_dpp(int x)   // minimum over all 64 lanes
+{
+    x = dpp_min_step<0x111, 0xF>(x);
+    x = dpp_min_step<0x112, 0xF>(x);
+    x = dpp_min_step<0x114, 0xF>(x);
+    x = dpp_min_step<0x118, 0xF>(x);
+    x = dpp_min_step<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_min_step<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+template <typename DT>
+__global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
+    if (b >= a.B || a.badkey[b]) return;
+    const DecodeLayout L = decode_layout(a.n_max, a.cap);
+    int* ready = reinterpret_cast<int*>(smem + L.ready_off);
+    uint32_t* sched = reinterpret_cast<uint32_t*>(smem + L.bits_off);
+    const uint16_t* ord = a.order + b * a.cap;
+    uint32_t* log = a.log ? a.log + b * a.cap : nullptr;
+
+    const int ii = a.inst ? a.inst[b] : 0;    // in range: the sort launch checked it
+    const InstDev I = a.inst_tab[ii];
+    const int n = I.n, m = I.m, k = I.k, R = I.R, N1 = n + 1, O = 2 * n;
+    const bool minpre = I.load_model != VRPRPD_FULL_START;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    const float* hn = a.hint ? a.hint + b * a.key_stride : nullptr;
+    for (int w = lane; w < (O + 31) / 32; w += 64) sched[w] = 0u;
+    for (int c = lane; c <= n; c += 64) ready[c] = 0;
+    wave_lds_fence();
 
     // ---- 3. passes -------------------------------------------------------------
     const bool veh = lane < m;
@@ -176,9 +230,11 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     // so scheduling an op needs no LDS round trip for feasibility.
     for (int pass = 0; pass < O; ++pass) {
         bool progressed = false;
+        int o_next = lane < O ? ord[lane] : 0;
         for (int base = 0; base < O; base += 64) {
             const int j = base + lane;
-            const int o = j < O ? idx[j] : 0;
+            const int o = o_next;
+            if (base + 64 < O) o_next = j + 64 < O ? ord[j + 64] : 0;   // next chunk's load in flight
             bool unsched = j < O && !((sched[o >> 5] >> (o & 31)) & 1u);
             if (!__ballot(unsched)) continue;
             const int c = o / 2 + 1, isP = o & 1;
@@ -218,12 +274,8 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                     }
                     if (cand) kv = key;
                 }
-                // minimum over the m vehicle lanes, read one by one (no LDS crossbar)
-                int ks = INT_MAX;
-                for (int v = 0; v < m; ++v) {
-                    const int x = __builtin_amdgcn_readlane(kv, v);
-                    ks = x < ks ? x : ks;
-                }
+                // minimum over the vehicle lanes (lanes >= m hold INT_MAX)
+                const int ks = m <= 16 ? row0_min(kv) : wave_min_dpp(kv);
                 const unsigned long long tie = __ballot(kv == ks && veh);
                 const unsigned long long upper = tie & (~0ull << hi);
                 const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
@@ -244,8 +296,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 Lsum += took_preload;
                 if (lane == 0) {
                     atomicOr(&sched[oi >> 5], 1u << (oi & 31));
-                    log_code[nsched] = (uint16_t)((ci << 1) | isPi);
-                    log_veh[nsched] = (uint8_t)vs;
+                    if (log) log[nsched] = (uint32_t)((ci << 1) | isPi) | ((uint32_t)vs << 16);
                 }
                 ++nsched;
                 if (lane == i) unsched = false;
@@ -270,13 +321,13 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
         a.fitness[b] = (int64_t)ret + 1000000LL * (O - nsched);
         a.status[b] = (!minpre && (long long)m * k > R) ? VRPRPD_ST_RES : 0u;
     }
-    if (a.ops_out && a.rt_out) {
-        wave_lds_fence();
+    if (log && a.ops_out && a.rt_out) {
+        __threadfence_block();   // the log written by lane 0, read by every lane
         // per-vehicle counts, then a stable scatter in schedule order
         int cnt = 0;
         for (int j0 = 0; j0 < nsched; j0 += 64) {
             const int j = j0 + lane;
-            const int v = j < nsched ? log_veh[j] : -1;
+            const int v = j < nsched ? (int)(log[j] >> 16) : -1;
             for (int u = 0; u < m; ++u) {
                 const unsigned long long mk = __ballot(v == u);
                 if (lane == u) cnt += __popcll(mk);
@@ -293,7 +344,8 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
         uint16_t* dst = a.ops_out + b * a.ops_stride;
         for (int j0 = 0; j0 < nsched; j0 += 64) {
             const int j = j0 + lane;
-            const int v = j < nsched ? log_veh[j] : -1;
+            const uint32_t e = j < nsched ? log[j] : 0u;
+            const int v = j < nsched ? (int)(e >> 16) : -1;
             int pos = 0;
             for (int u = 0; u < m; ++u) {
                 const unsigned long long mk = __ballot(v == u);
@@ -301,9 +353,70 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 if (v == u) pos = start + __popcll(mk & ((1ull << lane) - 1));
                 if (lane == u) off += __popcll(mk);
             }
-            if (v >= 0) dst[pos] = log_code[j];
+            if (v >= 0) dst[pos] = (uint16_t)(e & 0xFFFFu);
         }
     }
+}
+
+// Workspace of one launch over B chromosomes: op orders, key flags and, when
+// the sequences are wanted, the schedule logs.
+int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool want_ops)
+{
+    const int n_lds = by_inst ? set->n_max : set->host[0].n;
+    const int64_t cap = pow2_at_least(2 * n_lds);
+    auto up = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    return up(2 * cap * B) + up(B) + (want_ops ? up(4 * cap * B) : 0);
+}
+
+int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio, const float* hint,
+                  int64_t key_stride, int64_t* fitness, int32_t* makespan, int32_t* unscheduled, uint32_t* status,
+                  uint16_t* ops_out, uint16_t* rt_end_out, void* ws, hipStream_t st)
+{
+    if (!set) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: set is NULL");
+    if (B < 0) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: B < 0");
+    if (B == 0) return VRPRPD_OK;
+    if (!prio || !fitness || !makespan || !unscheduled || !status)
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: prio, fitness, makespan, unscheduled and status "
+                                        "are required");
+    if ((ops_out == nullptr) != (rt_end_out == nullptr))
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: pass both ops_out and rt_end_out or neither");
+    const int n_lds = inst ? set->n_max : set->host[0].n;
+    if (key_stride < 2 * (int64_t)n_lds)
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: key_stride %lld < 2n = %d", (long long)key_stride,
+                         2 * n_lds);
+    if (2 * n_lds > 8192)
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: 2n = %d exceeds the 8192 ops one CU can sort",
+                         2 * n_lds);
+    if (B > INT32_MAX) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: B too large");
+    const int cap = pow2_at_least(2 * n_lds);
+    const DecodeLayout L = decode_layout(n_lds, cap);
+    const int sort_lds = sort_lds_bytes(cap);
+    auto up = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    uint16_t* order = reinterpret_cast<uint16_t*>(w);
+    uint8_t* badkey = w + up(2 * (int64_t)cap * B);
+    uint32_t* log = ops_out ? reinterpret_cast<uint32_t*>(w + up(2 * (int64_t)cap * B) + up(B)) : nullptr;
+    DecodeArgs a{set->d_inst, set->d_dist, set->d_proc, inst, prio, hint, key_stride, fitness, makespan,
+                 unscheduled, status, ops_out, rt_end_out, 2 * (int64_t)n_lds, (int64_t)(inst ? set->m_max
+                                                                                             : set->host[0].m),
+                 B, set->num_inst, n_lds, cap, (int32_t)B, order, badkey, log};
+    auto launch = [&](const void* k, int lds) -> int {
+        if (lds > 64 * 1024) VRP_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        return VRPRPD_OK;
+    };
+    int rc = launch(reinterpret_cast<const void*>(decode_sort_kernel), sort_lds);
+    if (rc) return rc;
+    hipLaunchKernelGGL(decode_sort_kernel, dim3((unsigned)B), dim3(64), sort_lds, st, a);
+    VRP_HIP(hipGetLastError());
+    if (set->dist16) {
+        if ((rc = launch(reinterpret_cast<const void*>(decode_kernel<uint16_t>), L.bytes))) return rc;
+        hipLaunchKernelGGL(decode_kernel<uint16_t>, dim3((unsigned)B), dim3(64), L.bytes, st, a);
+    } else {
+        if ((rc = launch(reinterpret_cast<const void*>(decode_kernel<int32_t>), L.bytes))) return rc;
+        hipLaunchKernelGGL(decode_kernel<int32_t>, dim3((unsigned)B), dim3(64), L.bytes, st, a);
+    }
+    VRP_HIP(hipGetLastError());
+    return VRPRPD_OK;
 }
 
 }  // namespace vrprpd
@@ -315,38 +428,14 @@ extern "C" int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t
                                  int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
                                  void* stream)
 {
-    if (!set) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: set is NULL");
-    if (B < 0) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: B < 0");
-    if (B == 0) return VRPRPD_OK;
-    if (!prio || !fitness || !makespan || !unscheduled || !status)
-        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: prio, fitness, makespan, unscheduled and status "
-                                        "are required");
-    if ((ops_out == nullptr) != (rt_end_out == nullptr))
-        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: pass both ops_out and rt_end_out or neither");
-    const int n_lds = inst ? set->n_max : set->host[0].n;
-    const int m_max = inst ? set->m_max : set->host[0].m;
-    if (key_stride < 2 * (int64_t)n_lds)
-        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: key_stride %lld < 2n = %d", (long long)key_stride,
-                         2 * n_lds);
-    if (2 * n_lds > 8192)
-        return set_error(VRPRPD_EINVAL, "brkga_decode_eval: 2n = %d exceeds the 8192 ops one CU can sort",
-                         2 * n_lds);
-    (void)m_max;
-    const int cap = pow2_at_least(2 * n_lds);
-    const DecodeLayout L = decode_layout(n_lds, cap);
-    if (B > INT32_MAX) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: B too large");
-    DecodeArgs a{set->d_inst, set->d_dist, set->d_proc, inst, prio, hint, key_stride, fitness, makespan,
-                 unscheduled, status, ops_out, rt_end_out, 2 * (int64_t)n_lds, (int64_t)(inst ? set->m_max
-                                                                                             : set->host[0].m),
-                 B, set->num_inst, n_lds, cap, (int32_t)B};
+    if (!set || B <= 0)   // argument errors and the empty batch: no workspace
+        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+                             rt_end_out, nullptr, reinterpret_cast<hipStream_t>(stream));
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    auto launch = [&](auto* k) -> int {
-        if (L.bytes > 64 * 1024)
-            VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes));
-        hipLaunchKernelGGL(k, dim3((unsigned)B), dim3(64), L.bytes, st, a);
-        VRP_HIP(hipGetLastError());
-        return VRPRPD_OK;
-    };
-    return set->dist16 ? launch(decode_kernel<uint16_t>) : launch(decode_kernel<int32_t>);
+    void* ws = nullptr;
+    VRP_HIP(hipMallocAsync(&ws, (size_t)decode_ws_bytes(set, B, inst != nullptr, ops_out != nullptr), st));
+    const int rc = decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status,
+                                 ops_out, rt_end_out, ws, st);
+    (void)hipFreeAsync(ws, st);
+    return rc;
 }

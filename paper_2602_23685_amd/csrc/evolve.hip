@@ -408,6 +408,7 @@ struct brkga_state {
     int64_t *fit = nullptr, *best_fit = nullptr;
     float *best_prio = nullptr, *best_hint = nullptr;
     uint32_t* gen_dev = nullptr;
+    void* dec_ws = nullptr;        // decoder workspace (orders, key flags)
     hipStream_t cap = nullptr;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -421,8 +422,8 @@ namespace vrprpd {
 static int brkga_generation(brkga_state* s, int from, hipStream_t st)
 {
     const int64_t B = (int64_t)s->P * s->Np;
-    int rc = brkga_decode_eval(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->fit, s->mk,
-                               s->unsch, s->status, nullptr, nullptr, st);
+    int rc = decode_launch(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->fit, s->mk,
+                           s->unsch, s->status, nullptr, nullptr, s->dec_ws, st);
     if (rc) return rc;
     hipLaunchKernelGGL(rank_kernel, dim3((s->Np + 255) / 256, s->P), dim3(256), 0, st, s->fit, s->Np, s->order);
     hipLaunchKernelGGL(best_kernel, dim3(s->P), dim3(256), 0, st, s->Np, s->stride, s->order, s->fit, s->prio[from],
@@ -503,6 +504,7 @@ extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int3
     A((void**)&s->best_prio, n_inst * s->stride * 4);
     A((void**)&s->best_hint, n_inst * s->stride * 4);
     A((void**)&s->gen_dev, 4);
+    A(&s->dec_ws, (size_t)decode_ws_bytes(set, B, true, false));
     if (e != hipSuccess) {
         brkga_state_destroy(s);
         return set_error(VRPRPD_ENOMEM, "brkga_state_create: %s", hipGetErrorString(e));
