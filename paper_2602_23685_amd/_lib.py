@@ -220,8 +220,8 @@ def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_b
     mk = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
     st = torch.empty(T, dtype=torch.int32, device=dev) if want_each else None
     top = torch.empty((max(S_, 0), 3), dtype=torch.int64, device=dev)
-    if blocks_per_seg is None:      # about 64 tuples per workgroup
-        blocks_per_seg = max(1, min(65535, -(-T // max(1, S_ * 64))))
+    if blocks_per_seg is None:      # about 16 tuples per workgroup
+        blocks_per_seg = max(1, min(65535, -(-T // max(1, S_ * 16))))
     _check(load().vrprpd_insert_scan(
         S.handle, num_bases, _dptr(base_inst, torch.int32, "base_inst"),
         _dptr(base_op_off, torch.int64, "base_op_off"), _dptr(base_ops, torch.uint16, "base_ops"),

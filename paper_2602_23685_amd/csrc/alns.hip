@@ -30,6 +30,10 @@ constexpr uint32_t kTagAlns = 0x414C4E53u;
 constexpr int kND = 6, kNR = 4;
 constexpr long long kBigC = 1LL << 40;
 constexpr int kAlnsStep = 4;
+// Insertion-scan workgroups take about this many tuples of a segment each:
+// more, smaller workgroups spread a round's few thousand tuples over the CUs
+// (each stages the base solution once).
+constexpr int kScanTuplesPerBlock = 16;
 constexpr int kGainWaves = 4;   // gains kernel: 4 waves of 16-lane groups (m <= 16)
 constexpr int kGainGroups = 16;
 
@@ -2013,7 +2017,7 @@ static int launch_ls_passes(alns_state* s, hipStream_t st, int kind)
     AlnsDev& d = s->d;
     ScanArgs la{d.inst_tab, d.dist, d.proc, d.ls_base_inst, d.ls_base_off, d.ls_ops, d.ls_rt_off, d.ls_rt,
                 d.ls_seg_off, d.ls_seg_base, d.ls_tuples, d.ls_tmk, d.ls_tst, d.ls_top3, d.ls_seg_cnt,
-                d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 4};
+                d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 8};
     for (int pass = 0; pass < 3; ++pass) {
         hipLaunchKernelGGL(k_ls_setup<DT>, dim3(d.C), dim3(256), s->lds_ls, st, d, kind);
         hipLaunchKernelGGL(k_ls_enum<DT>, dim3(d.C, d.LQ), dim3(256), s->lds_enum, st, d, kind);
@@ -2072,7 +2076,7 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
     VRP_HIP(hipGetLastError());
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
-                d.C * d.Q, std::max(1, (d.TPC + 63) / 64)};
+                d.C * d.Q, std::max(1, (d.TPC + kScanTuplesPerBlock - 1) / kScanTuplesPerBlock)};
     for (int r = 0; r < d.Q; ++r) {
         hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
         VRP_HIP(hipGetLastError());
