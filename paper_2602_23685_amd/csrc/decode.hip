@@ -45,8 +45,8 @@ struct DecodeArgs {
 
 __host__ __device__ inline int d16(int x) { return (x + 15) & ~15; }
 
-// LDS of the sort launch: keys, op indices.
-__host__ __device__ inline int sort_lds_bytes(int cap) { return d16(4 * cap) + d16(2 * cap); }
+// LDS of the sort launch: (key << 16 | op index) pairs.
+__host__ __device__ inline int sort_lds_bytes(int cap) { return 8 * cap; }
 // LDS of the pass launch: ready[], scheduled bits.
 struct DecodeLayout {
     int ready_off, bits_off, bytes;
@@ -101,8 +101,7 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
     const int lane = threadIdx.x;
     const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
     if (b >= a.B) return;
-    uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
-    uint16_t* idx = reinterpret_cast<uint16_t*>(smem + d16(4 * a.cap));
+    unsigned long long* kx = reinterpret_cast<unsigned long long*>(smem);
     int ii = a.inst ? a.inst[b] : 0;
     const bool bad_inst = ii < 0 || ii >= a.num_inst;
     if (bad_inst) ii = 0;
@@ -115,6 +114,8 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
 
     // ---- 1. keys ------------------------------------------------------------
     bool bad = bad_inst;
+    // A valid key is a non-negative float, so its bits order like the value;
+    // the op index in the low 16 bits breaks ties (padding sorts last).
     for (int o = lane; o < cap; o += 64) {
         uint32_t kb = 0xFFFFFFFFu;
         if (o < O) {
@@ -122,8 +123,7 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
             uint32_t hb;
             if (hn && !key_ok(hn[o], hb)) bad = true;
         }
-        keys[o] = kb;
-        idx[o] = (uint16_t)(o < O ? o : 0xFFFF);
+        kx[o] = ((unsigned long long)kb << 16) | (unsigned)(o < O ? o : 0xFFFF);
     }
     if (__ballot(bad)) {
         if (lane == 0) {
@@ -140,27 +140,9 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
     wave_lds_fence();
 
     // ---- 2. bitonic sort of (key, op) pairs ----------------------------------
-    for (int kk = 2; kk <= cap; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < cap; i += 64) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t ki = keys[i], kl = keys[l];
-                    const uint16_t xi = idx[i], xl = idx[l];
-                    const bool gt = ki > kl || (ki == kl && xi > xl);
-                    if (gt == ((i & kk) == 0)) {
-                        keys[i] = kl;
-                        keys[l] = ki;
-                        idx[i] = xl;
-                        idx[l] = xi;
-                    }
-                }
-            }
-            wave_lds_fence();
-        }
-    }
+    block_sort_u64(kx, cap);
     uint16_t* ord = a.order + b * a.cap;
-    for (int j = lane; j < O; j += 64) ord[j] = idx[j];
+    for (int j = lane; j < O; j += 64) ord[j] = (uint16_t)(kx[j] & 0xFFFFu);
     if (lane == 0) a.badkey[b] = 0;
 }
 

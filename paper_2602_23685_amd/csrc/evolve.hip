@@ -44,6 +44,55 @@ __global__ __launch_bounds__(256) void rank_kernel(const int64_t* __restrict__ f
     if (i < Np) order[rank] = i;
 }
 
+// The same order by sorting: one block per population (Np <= kSortRankMax),
+// a bitonic network over (fitness, index) pairs in LDS; the pair order is
+// the rank order, so order[r] is the index in place r.
+constexpr int kSortRankMax = 4096;
+__global__ __launch_bounds__(1024) void rank_sort_kernel(const int64_t* __restrict__ fit, int32_t Np,
+                                                         int32_t* __restrict__ order)
+{
+    __shared__ int64_t f[kSortRankMax];
+    __shared__ uint16_t x[kSortRankMax];
+    fit += (int64_t)blockIdx.y * Np;
+    order += (int64_t)blockIdx.y * Np;
+    int np = 1;
+    while (np < Np) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        f[i] = i < Np ? fit[i] : INT64_MAX;
+        x[i] = (uint16_t)i;                   // padding sorts after every real entry
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int64_t fi = f[i], fl = f[l];
+                    const uint16_t xi = x[i], xl = x[l];
+                    const bool gt = fi > fl || (fi == fl && xi > xl);
+                    if (gt == ((i & k) == 0)) {
+                        f[i] = fl;
+                        f[l] = fi;
+                        x[i] = xl;
+                        x[l] = xi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = threadIdx.x; r < Np; r += blockDim.x) order[r] = x[r];
+}
+
+// Ranks each of P populations of Np individuals (fitness [P][Np]) into order.
+static void launch_rank(const int64_t* fit, int32_t Np, int32_t P, int32_t* order, hipStream_t st)
+{
+    if (Np <= kSortRankMax)
+        hipLaunchKernelGGL(rank_sort_kernel, dim3(1, P), dim3(1024), 0, st, fit, Np, order);
+    else
+        hipLaunchKernelGGL(rank_kernel, dim3((Np + 255) / 256, P), dim3(256), 0, st, fit, Np, order);
+}
+
 struct EvolveArgs {
     const float* prio;
     const float* hint;
@@ -269,7 +318,7 @@ extern "C" int brkga_evolve(int32_t Np, int32_t genes, int64_t key_stride, const
     if (prio == prio_out || (hint && hint == hint_out))
         return set_error(VRPRPD_EINVAL, "brkga_evolve: output must not alias the input population");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(rank_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, fitness, Np, rank_out);
+    launch_rank(fitness, Np, 1, rank_out, st);
     VRP_HIP(hipGetLastError());
     const uint32_t thr = (uint32_t)std::floor(rho_e * 16777216.0);
     EvolveArgs a{prio, hint, rank_out, prio_out, hint_out, key_stride, seed, Np, genes, n_elite, n_mutant,
@@ -425,7 +474,7 @@ static int brkga_generation(brkga_state* s, int from, hipStream_t st)
     int rc = decode_launch(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->fit, s->mk,
                            s->unsch, s->status, nullptr, nullptr, s->dec_ws, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(rank_kernel, dim3((s->Np + 255) / 256, s->P), dim3(256), 0, st, s->fit, s->Np, s->order);
+    launch_rank(s->fit, s->Np, s->P, s->order, st);
     hipLaunchKernelGGL(best_kernel, dim3(s->P), dim3(256), 0, st, s->Np, s->stride, s->order, s->fit, s->prio[from],
                        s->hint[from], s->best_fit, s->best_prio, s->best_hint);
     EvolveArgs a{s->prio[from], s->hint[from], s->order, s->prio[from ^ 1], s->hint[from ^ 1], s->stride, s->seed,

@@ -61,13 +61,16 @@ def test_decode_parity(orc, P, case):
                 assert np.array_equal(ops[b][:L], r["ops"]), b
 
 
-def test_evolve_parity(orc, P):
-    n, Np = 100, 1024
+@pytest.mark.parametrize("Np", [1024, 4096, 5000], ids=lambda x: f"Np{x}")
+def test_evolve_parity(orc, P, Np):
+    """Ranking by the block-wide sort (Np <= 4096) and by counting (larger)."""
+    n = 100
     ne, nm = orc.brkga_sizes(Np)
     prio, hint = synth.random_keys(Np, n, seed=3)
     fit = synth.rng(4).integers(0, 10**6, size=Np).astype(np.int64)
     fit[::7] = fit[0]                                       # ties resolved by index
     fit[5] = 2**63 - 1
+    fit[3] = -(2**40)                                       # any int64 orders
     for gen in (0, 17):
         po, ho, rank = P.brkga_evolve(dev(prio), dev(hint), dev(fit), ne, nm, 0.7, 0xC0FFEE, gen)
         torch.cuda.synchronize()
