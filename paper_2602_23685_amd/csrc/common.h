@@ -135,8 +135,9 @@ __host__ __device__ inline int pow2_ge(int x)
 }
 
 // Block-wide bitonic sort of n (power of two) u64 keys, ascending; key may
-// point to LDS or to global memory private to the block.
-__device__ inline void block_sort_u64(unsigned long long* key, int n)
+// point to LDS or to global memory private to the block.  Every stage goes
+// through memory.
+__device__ inline void block_sort_u64_mem(unsigned long long* key, int n)
 {
     for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -152,6 +153,77 @@ __device__ inline void block_sort_u64(unsigned long long* key, int n)
             }
             __syncthreads();
         }
+    }
+}
+
+// One compare-exchange stage with partner distance J < 8 on the 8 keys
+// r[0..7] = key[8t .. 8t+8) that thread t holds in registers.
+template <int J>
+__device__ __forceinline__ void sort8_stage(unsigned long long (&r)[8], int base, int k)
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int f = e ^ J;
+        if (f > e) {
+            const unsigned long long a = r[e], b = r[f];
+            if ((a > b) == (((base + e) & k) == 0)) {
+                r[e] = b;
+                r[f] = a;
+            }
+        }
+    }
+}
+
+// The same sort with the stages of partner distance below 8 done in
+// registers: a thread loads 8 consecutive keys, runs those stages and stores
+// them back, so they need a third of the memory traffic and one barrier
+// instead of three.  n >= 16; smaller n uses the memory-only network.
+__device__ inline void block_sort_u64(unsigned long long* key, int n)
+{
+    if (n < 16) {
+        block_sort_u64_mem(key, n);
+        return;
+    }
+    const int T = blockDim.x;
+    for (int base = 8 * threadIdx.x; base < n; base += 8 * T) {
+        unsigned long long r[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r[e] = key[base + e];
+        sort8_stage<1>(r, base, 2);
+        sort8_stage<2>(r, base, 4);
+        sort8_stage<1>(r, base, 4);
+        sort8_stage<4>(r, base, 8);
+        sort8_stage<2>(r, base, 8);
+        sort8_stage<1>(r, base, 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) key[base + e] = r[e];
+    }
+    __syncthreads();
+    for (int k = 16; k <= n; k <<= 1) {
+        for (int j = k >> 1; j >= 8; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += T) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int base = 8 * threadIdx.x; base < n; base += 8 * T) {
+            unsigned long long r[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r[e] = key[base + e];
+            sort8_stage<4>(r, base, k);
+            sort8_stage<2>(r, base, k);
+            sort8_stage<1>(r, base, k);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) key[base + e] = r[e];
+        }
+        __syncthreads();
     }
 }
 
