@@ -830,6 +830,7 @@ __global__ __launch_bounds__(256) void k_enum(AlnsDev a)
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x, slot = blockIdx.y;
     const int sidx = c * a.Q + slot;
+    if (threadIdx.x < 3) a.seg_top3[3 * (int64_t)sidx + threadIdx.x] = INT64_MAX;   // the scan merges into it
     if (a.rstate[c] != 0 || slot >= a.nleft[c]) {
         if (threadIdx.x == 0) a.seg_cnt[sidx] = 0;
         return;
@@ -1254,6 +1255,7 @@ __global__ __launch_bounds__(256) void k_ls_enum(AlnsDev a, int kind)
     extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x, i = blockIdx.y;
     const int64_t idx = (int64_t)c * a.LQ + i;
+    if (threadIdx.x < 3) a.ls_top3[3 * idx + threadIdx.x] = INT64_MAX;   // the scan merges into it
     if (!a.ls_active[c] || i >= a.ls_nc[c]) return;   // ls_seg_cnt is 0 there (setup)
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int n = I.n, m = I.m, N1 = n + 1;
@@ -2017,7 +2019,7 @@ static int launch_ls_passes(alns_state* s, hipStream_t st, int kind)
     AlnsDev& d = s->d;
     ScanArgs la{d.inst_tab, d.dist, d.proc, d.ls_base_inst, d.ls_base_off, d.ls_ops, d.ls_rt_off, d.ls_rt,
                 d.ls_seg_off, d.ls_seg_base, d.ls_tuples, d.ls_tmk, d.ls_tst, d.ls_top3, d.ls_seg_cnt,
-                d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 8};
+                d.C * d.LQ, s->set->num_inst, d.N, d.C * d.LQ, 8, 1};
     for (int pass = 0; pass < 3; ++pass) {
         hipLaunchKernelGGL(k_ls_setup<DT>, dim3(d.C), dim3(256), s->lds_ls, st, d, kind);
         hipLaunchKernelGGL(k_ls_enum<DT>, dim3(d.C, d.LQ), dim3(256), s->lds_enum, st, d, kind);
@@ -2076,7 +2078,7 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
     VRP_HIP(hipGetLastError());
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
-                d.C * d.Q, std::max(1, (d.TPC + kScanTuplesPerBlock - 1) / kScanTuplesPerBlock)};
+                d.C * d.Q, std::max(1, (d.TPC + kScanTuplesPerBlock - 1) / kScanTuplesPerBlock), 1};
     for (int r = 0; r < d.Q; ++r) {
         hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
         VRP_HIP(hipGetLastError());

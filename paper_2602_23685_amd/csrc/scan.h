@@ -23,6 +23,7 @@ struct ScanArgs {
     const int32_t* seg_cnt;   // internal: segment s covers [seg_off[s], seg_off[s] + seg_cnt[s])
     int32_t num_bases, num_inst, n_max, num_seg;
     int32_t blocks_per_seg;   // blocks sharing one segment's tuples (>= 1)
+    int32_t top3_ready = 0;   // internal: seg_top3 already holds INT64_MAX (no fill launch)
 };
 
 // Launches the insertion-scan kernel for the arguments above.

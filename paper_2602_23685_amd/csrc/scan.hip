@@ -281,9 +281,12 @@ int launch_scan(const ScanArgs& a, hipStream_t stream)
     if (L.bytes > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     L.bytes));
-    const int64_t cnt = 3 * (int64_t)a.num_seg;
-    hipLaunchKernelGGL(top3_fill_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.seg_top3, cnt);
-    VRP_HIP(hipGetLastError());
+    if (!a.top3_ready) {
+        const int64_t cnt = 3 * (int64_t)a.num_seg;
+        hipLaunchKernelGGL(top3_fill_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.seg_top3,
+                           cnt);
+        VRP_HIP(hipGetLastError());
+    }
     const int ny = a.blocks_per_seg > 0 ? a.blocks_per_seg : 1;
     hipLaunchKernelGGL(k, dim3(a.num_seg, ny), dim3(64 * WPB), L.bytes, stream, a);
     VRP_HIP(hipGetLastError());
