@@ -994,68 +994,81 @@ __device__ void splice_tuple(const uint16_t* src, const uint16_t* srt, int m, co
 // one by the repair operator's rule, insert it into W.
 __global__ __launch_bounds__(256) void k_select(AlnsDev a)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int c = blockIdx.x;
     if (a.rstate[c] != 0) return;
     const InstDev I = a.inst_tab[a.chain_inst[c]];
     const int m = I.m;
     const int nl = a.nleft[c], ri = a.ri[c];
     const int kreg = ri == 1 ? 2 : ri == 2 ? 3 : m;
-    __shared__ long long opt[kMaxM];
-    __shared__ long long best_c1, best_reg;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    // per waiting customer: its best makespan c1 and regret (LDS, [Q] each)
+    long long* c1s = reinterpret_cast<long long*>(smem);
+    long long* regs = c1s + a.Q;
+    __shared__ long long opt[4][kMaxM];
+    __shared__ unsigned long long evals;
     __shared__ int best_i, fail;
     __shared__ long long best_key;
     if (threadIdx.x == 0) {
-        best_i = -1;
         fail = 0;
+        evals = 0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long tot = 0;
-        for (int i = 0; i < nl; ++i) tot += (unsigned long long)a.seg_cnt[c * a.Q + i];
-        atomicAdd(a.evals, tot);
+    {
+        unsigned long long part = 0;
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) part += (unsigned long long)a.seg_cnt[c * a.Q + i];
+        atomicAdd(&evals, part);
     }
-    for (int i = 0; i < nl; ++i) {
+    // One wave per customer: the best tuple of each drop vehicle (for the
+    // regret), then the regret over the kreg best vehicles.
+    for (int i = wave; i < nl; i += nw) {
         const int sidx = c * a.Q + i;
         const long long key0 = a.seg_top3[3 * sidx];
         if (key0 == INT64_MAX) {
-            if (threadIdx.x == 0) fail = 1;
-            break;
+            if (lane == 0) fail = 1;
+            continue;
         }
-        if (threadIdx.x < m) opt[threadIdx.x] = kBigC;
-        __syncthreads();
+        c1s[i] = key0 >> 32;
+        if (ri == 0) continue;
+        long long* o = opt[wave];
+        if (lane < m) o[lane] = kBigC;
+        wave_lds_fence();
         const int cnt = a.seg_cnt[sidx];
         const int64_t t0 = a.seg_off[sidx];
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        for (int k = lane; k < cnt; k += 64) {
             if (a.tst[t0 + k] != 0) continue;
-            atomicMin((unsigned long long*)&opt[a.tuples[t0 + k].vD], (unsigned long long)a.tmk[t0 + k]);
+            atomicMin((unsigned long long*)&o[a.tuples[t0 + k].vD], (unsigned long long)a.tmk[t0 + k]);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const long long c1 = key0 >> 32;
+        wave_lds_fence();
+        if (lane == 0) {
+            for (int x = 1; x < m; ++x)   // ascending, in place
+                for (int y = x; y > 0 && o[y] < o[y - 1]; --y) {
+                    const long long t = o[y];
+                    o[y] = o[y - 1];
+                    o[y - 1] = t;
+                }
             long long reg = 0;
-            if (ri != 0) {
-                long long* o = opt;   // sorted in place (LDS), ascending
-                for (int x = 1; x < m; ++x)
-                    for (int y = x; y > 0 && o[y] < o[y - 1]; --y) {
-                        const long long t = o[y];
-                        o[y] = o[y - 1];
-                        o[y - 1] = t;
-                    }
-                for (int h = 1; h < kreg && h < m; ++h) reg += o[h] - o[0];
-                for (int h = m; h < kreg; ++h) reg += kBigC - o[0];
-            }
-            bool better;
-            if (best_i < 0) better = true;
-            else if (ri == 0) better = c1 < best_c1;
-            else better = reg > best_reg || (reg == best_reg && c1 < best_c1);
-            if (better) {
-                best_i = i;
-                best_c1 = c1;
-                best_reg = reg;
-                best_key = key0;
-            }
+            for (int h = 1; h < kreg && h < m; ++h) reg += o[h] - o[0];
+            for (int h = m; h < kreg; ++h) reg += kBigC - o[0];
+            regs[i] = reg;
         }
-        __syncthreads();
+        wave_lds_fence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(a.evals, evals);
+        // greedy: the lowest best makespan; regret: the largest regret, then
+        // the lower best makespan; ties to the earlier customer
+        int bi = -1;
+        for (int i = 0; i < nl && !fail; ++i) {
+            bool better;
+            if (bi < 0) better = true;
+            else if (ri == 0) better = c1s[i] < c1s[bi];
+            else better = regs[i] > regs[bi] || (regs[i] == regs[bi] && c1s[i] < c1s[bi]);
+            if (better) bi = i;
+        }
+        best_i = bi;
+        if (bi >= 0) best_key = a.seg_top3[3 * (c * a.Q + bi)];
     }
     __syncthreads();
     if (fail) {
@@ -2083,7 +2096,7 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
         hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
         VRP_HIP(hipGetLastError());
         if ((rc = insert_scan_launch(sa, d.M, s->dist16, st))) return rc;
-        hipLaunchKernelGGL(k_select, dim3(d.C), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_select, dim3(d.C), dim3(256), (size_t)16 * d.Q, st, d);
         VRP_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_accept, dim3(d.C), dim3(256), 0, st, d);
