@@ -201,15 +201,20 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 
     // ---- 3. passes -------------------------------------------------------------
     const bool veh = lane < m;
+    const unsigned long long VEH = m >= 64 ? ~0ull : (1ull << m) - 1ull;   // vehicle lanes
     int t = 0, loc = 0, q = minpre ? 0 : k, M = 0;
     bool used = false;
     int Lsum = 0, nsched = 0;
-    auto can_drop = [&]() { return veh && (q > 0 || (minpre && M < k && Lsum < R)); };
-    auto can_pick = [&]() { return veh && q < k; };
-    bool anyD = __ballot(can_drop()) != 0, anyP = __ballot(can_pick()) != 0;
-    // Per chunk of 64 ops in priority order each lane keeps its op's state in
-    // registers (unscheduled, and for a pickup whether its drop is scheduled),
-    // so scheduling an op needs no LDS round trip for feasibility.
+    // vehicle lanes that can take a drop (hold a resource, or may preload
+    // one) / a pickup; bitwise forms keep the tests free of branches
+    auto drop_ok = [&](bool preok) { return (q > 0) | (preok & (M < k)); };
+    auto drop_lanes = [&]() { return __ballot(drop_ok(minpre & (Lsum < R))) & VEH; };
+    auto pick_lanes = [&]() { return __ballot(q < k) & VEH; };
+    unsigned long long anyD = drop_lanes(), anyP = pick_lanes();
+    // Per chunk of 64 ops in priority order the wave keeps the chunk's state
+    // as lane masks (unscheduled, pickup, pickup whose drop is scheduled), so
+    // finding the next feasible op is a few scalar operations.  Every lane
+    // runs the vehicle arithmetic; vehicle lanes differ only in their data.
     for (int pass = 0; pass < O; ++pass) {
         bool progressed = false;
         int o_next = lane < O ? ord[lane] : 0;
@@ -217,78 +222,73 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
             const int j = base + lane;
             const int o = o_next;
             if (base + 64 < O) o_next = j + 64 < O ? ord[j + 64] : 0;   // next chunk's load in flight
-            bool unsched = j < O && !((sched[o >> 5] >> (o & 31)) & 1u);
-            if (!__ballot(unsched)) continue;
+            const bool uns = j < O && !((sched[o >> 5] >> (o & 31)) & 1u);
+            unsigned long long U = __ballot(uns);
+            if (!U) continue;
+            const unsigned long long U0 = U;
             const int c = o / 2 + 1, isP = o & 1;
-            bool dropdone = isP && unsched && ((sched[(o - 1) >> 5] >> ((o - 1) & 31)) & 1u);
+            const unsigned long long PM = __ballot(isP);
+            unsigned long long DD = __ballot(isP && uns && ((sched[(o - 1) >> 5] >> ((o - 1) & 31)) & 1u));
             int h = 0;
-            if (hn && unsched) {
+            if (hn && uns) {
                 const float prod = (float)m * hn[o];
                 h = (int)floorf(prod);
                 h = h < m - 1 ? h : m - 1;
             }
-            const int pc = (unsched && !isP) ? P[c] : 0;
-            int cursor = 0;
+            const int pc = (uns && !isP) ? P[c] : 0;
+            unsigned long long avail = ~0ull;   // lanes after the last op taken in this chunk
             for (;;) {
-                bool feas = false;
-                if (unsched && lane >= cursor) feas = isP ? (anyP && dropdone) : anyD;
-                const unsigned long long mask = __ballot(feas);
+                const unsigned long long mask =
+                    avail & U & ((anyD ? ~PM : 0ull) | (anyP ? (PM & DD) : 0ull));
                 if (!mask) break;
-                const int i = __ffsll((long long)mask) - 1;   // wave-uniform: read lanes directly
+                const int i = __ffsll((long long)mask) - 1;
                 const int oi = __builtin_amdgcn_readlane(o, i), hi = __builtin_amdgcn_readlane(h, i);
                 const int pci = __builtin_amdgcn_readlane(pc, i);
-                const int ci = oi / 2 + 1, isPi = oi & 1;
-                const int dv = veh ? (int)D[loc * N1 + ci] : 0;
+                const int ci = oi / 2 + 1;
+                const bool isPi = oi & 1;
                 // SelectVehicle: least completion time, ties to the first
-                // vehicle at or after the hint vehicle (cyclically)
-                int kv = INT_MAX;
-                if (veh) {
-                    const int arr = t + dv;
-                    bool cand;
-                    int key;
-                    if (!isPi) {
-                        cand = q > 0 || (minpre && M < k && Lsum < R);
-                        key = arr;
-                    } else {
-                        cand = q < k;
-                        const int r = lds_load(&ready[ci]);
-                        key = arr > r ? arr : r;
-                    }
-                    if (cand) kv = key;
+                // vehicle at or after the hint vehicle (cyclically).  Lanes
+                // past m keep loc = 0 and read a valid entry.
+                const int arr = t + (int)D[loc * N1 + ci];
+                int kv;
+                if (isPi) {
+                    const int r = lds_load(&ready[ci]);
+                    kv = q < k ? (arr > r ? arr : r) : INT_MAX;
+                } else {
+                    kv = drop_ok(minpre & (Lsum < R)) ? arr : INT_MAX;
                 }
-                // minimum over the vehicle lanes (lanes >= m hold INT_MAX)
+                kv = veh ? kv : INT_MAX;
                 const int ks = m <= 16 ? row0_min(kv) : wave_min_dpp(kv);
-                const unsigned long long tie = __ballot(kv == ks && veh);
+                const unsigned long long tie = __ballot(kv == ks) & VEH;
                 const unsigned long long upper = tie & (~0ull << hi);
                 const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
-                const int took_preload = __builtin_amdgcn_readlane((!isPi && q == 0) ? 1 : 0, vs);
-                if (lane == vs) {
-                    if (!isPi) {
-                        if (q == 0) { ++M; ++q; }
-                        --q;
-                        lds_store(&ready[ci], ks + pci);
-                    } else {
-                        ++q;
-                        M = q > M ? q : M;
-                    }
-                    t = ks;
-                    loc = ci;
-                    used = true;
+                const bool me = lane == vs;
+                if (isPi) {
+                    q += me ? 1 : 0;
+                    M = (me && q > M) ? q : M;
+                } else {
+                    // an empty vehicle preloads one resource for the drop
+                    const int pre = __builtin_amdgcn_readlane(q, vs) == 0 ? 1 : 0;
+                    Lsum += pre;
+                    M += me ? pre : 0;
+                    q += me ? pre - 1 : 0;
+                    lds_store(&ready[ci], ks + pci);   // same address and value in every lane
+                    DD |= __ballot(o == oi + 1);        // this drop's pickup, if in the chunk
                 }
-                Lsum += took_preload;
-                if (lane == 0) {
-                    atomicOr(&sched[oi >> 5], 1u << (oi & 31));
-                    if (log) log[nsched] = (uint32_t)((ci << 1) | isPi) | ((uint32_t)vs << 16);
-                }
+                t = me ? ks : t;
+                loc = me ? ci : loc;
+                used = used || me;
+                if (log) log[nsched] = (uint32_t)((ci << 1) | (int)isPi) | ((uint32_t)vs << 16);
                 ++nsched;
-                if (lane == i) unsched = false;
-                if (!isPi && isP && o == oi + 1) dropdone = true;   // this pickup's drop just went in
-                cursor = i + 1;
+                U &= ~(1ull << i);
+                avail = ~((2ull << i) - 1ull);
                 progressed = true;
-                anyD = __ballot(can_drop()) != 0;
-                anyP = __ballot(can_pick()) != 0;
+                anyD = drop_lanes();
+                anyP = pick_lanes();
             }
-            wave_lds_fence();   // sched[] bits of this chunk before the next chunk reads them
+            // the chunk's newly scheduled ops, published before the next chunk reads them
+            if (((U0 & ~U) >> lane) & 1ull) atomicOr(&sched[o >> 5], 1u << (o & 31));
+            wave_lds_fence();
         }
         if (nsched == O || !progressed) break;
     }
