@@ -175,7 +175,9 @@ __device__ __forceinline__ int wave_min_dpp(int x)   // minimum over all 64 lane
     return __builtin_amdgcn_readlane(x, 63);
 }
 
-template <typename DT>
+// kSmallM: every instance has m <= 16 (vehicle minimum within one DPP row).
+// kLog: the schedule is logged for the op sequences (ops_out).
+template <typename DT, bool kSmallM, bool kLog>
 __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     int* ready = reinterpret_cast<int*>(smem + L.ready_off);
     uint32_t* sched = reinterpret_cast<uint32_t*>(smem + L.bits_off);
     const uint16_t* ord = a.order + b * a.cap;
-    uint32_t* log = a.log ? a.log + b * a.cap : nullptr;
+    uint32_t* log = kLog ? a.log + b * a.cap : nullptr;
 
     const int ii = a.inst ? a.inst[b] : 0;    // in range: the sort launch checked it
     const InstDev I = a.inst_tab[ii];
@@ -203,14 +205,20 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     const bool veh = lane < m;
     const unsigned long long VEH = m >= 64 ? ~0ull : (1ull << m) - 1ull;   // vehicle lanes
     int t = 0, loc = 0, q = minpre ? 0 : k, M = 0;
-    bool used = false;
+    int used = 0;
     int Lsum = 0, nsched = 0;
-    // vehicle lanes that can take a drop (hold a resource, or may preload
-    // one) / a pickup; bitwise forms keep the tests free of branches
-    auto drop_ok = [&](bool preok) { return (q > 0) | (preok & (M < k)); };
-    auto drop_lanes = [&]() { return __ballot(drop_ok(minpre & (Lsum < R))) & VEH; };
-    auto pick_lanes = [&]() { return __ballot(q < k) & VEH; };
-    unsigned long long anyD = drop_lanes(), anyP = pick_lanes();
+    // dok / pok: this lane's vehicle can take a drop (holds a resource, or
+    // may preload one) / a pickup; anyD / anyP: the lanes where it holds.
+    // Bitwise forms keep the tests free of branches.
+    bool dok, pok;
+    unsigned long long anyD, anyP;
+    auto vehicle_tests = [&]() {
+        dok = veh & ((q > 0) | (minpre & (Lsum < R) & (M < k)));
+        pok = veh & (q < k);
+        anyD = __builtin_amdgcn_ballot_w64(dok);
+        anyP = __builtin_amdgcn_ballot_w64(pok);
+    };
+    vehicle_tests();
     // Per chunk of 64 ops in priority order the wave keeps the chunk's state
     // as lane masks (unscheduled, pickup, pickup whose drop is scheduled), so
     // finding the next feasible op is a few scalar operations.  Every lane
@@ -244,47 +252,41 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 const int i = __ffsll((long long)mask) - 1;
                 const int oi = __builtin_amdgcn_readlane(o, i), hi = __builtin_amdgcn_readlane(h, i);
                 const int pci = __builtin_amdgcn_readlane(pc, i);
-                const int ci = oi / 2 + 1;
+                const int ci = (int)((unsigned)oi >> 1) + 1;
                 const bool isPi = oi & 1;
                 // SelectVehicle: least completion time, ties to the first
                 // vehicle at or after the hint vehicle (cyclically).  Lanes
-                // past m keep loc = 0 and read a valid entry.
+                // past m keep loc = 0 and read a valid entry; a drop reads
+                // ready[] too and ignores it.
                 const int arr = t + (int)D[loc * N1 + ci];
-                int kv;
-                if (isPi) {
-                    const int r = lds_load(&ready[ci]);
-                    kv = q < k ? (arr > r ? arr : r) : INT_MAX;
-                } else {
-                    kv = drop_ok(minpre & (Lsum < R)) ? arr : INT_MAX;
-                }
-                kv = veh ? kv : INT_MAX;
-                const int ks = m <= 16 ? row0_min(kv) : wave_min_dpp(kv);
-                const unsigned long long tie = __ballot(kv == ks) & VEH;
+                const int r = lds_load(&ready[ci]);
+                const int key = isPi ? (arr > r ? arr : r) : arr;
+                const int kv = (isPi ? pok : dok) ? key : INT_MAX;
+                const int ks = kSmallM ? row0_min(kv) : wave_min_dpp(kv);
+                const unsigned long long tie = __builtin_amdgcn_ballot_w64(kv == ks) & VEH;
                 const unsigned long long upper = tie & (~0ull << hi);
                 const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
                 const bool me = lane == vs;
-                if (isPi) {
-                    q += me ? 1 : 0;
-                    M = (me && q > M) ? q : M;
-                } else {
-                    // an empty vehicle preloads one resource for the drop
-                    const int pre = __builtin_amdgcn_readlane(q, vs) == 0 ? 1 : 0;
-                    Lsum += pre;
-                    M += me ? pre : 0;
-                    q += me ? pre - 1 : 0;
-                    lds_store(&ready[ci], ks + pci);   // same address and value in every lane
-                    DD |= __ballot(o == oi + 1);        // this drop's pickup, if in the chunk
-                }
+                // a drop on an empty vehicle preloads one resource
+                const int pre = (!isPi && __builtin_amdgcn_readlane(q, vs) == 0) ? 1 : 0;
+                Lsum += pre;
+                q += me ? (isPi ? 1 : pre - 1) : 0;
+                M = me ? (isPi ? (q > M ? q : M) : M + pre) : M;
+                // a drop publishes its ready time; a pickup writes the unused
+                // depot slot (same address and value in every lane)
+                lds_store(&ready[isPi ? 0 : ci], ks + pci);
+                // this drop's pickup, if in the chunk (after a pickup the
+                // match is a drop lane, whose bit is never read)
+                DD |= __builtin_amdgcn_ballot_w64(o == oi + 1);
                 t = me ? ks : t;
                 loc = me ? ci : loc;
-                used = used || me;
-                if (log) log[nsched] = (uint32_t)((ci << 1) | (int)isPi) | ((uint32_t)vs << 16);
+                used |= me ? 1 : 0;
+                if constexpr (kLog) log[nsched] = (uint32_t)((ci << 1) | (int)isPi) | ((uint32_t)vs << 16);
                 ++nsched;
                 U &= ~(1ull << i);
                 avail = ~((2ull << i) - 1ull);
                 progressed = true;
-                anyD = drop_lanes();
-                anyP = pick_lanes();
+                vehicle_tests();
             }
             // the chunk's newly scheduled ops, published before the next chunk reads them
             if (((U0 & ~U) >> lane) & 1ull) atomicOr(&sched[o >> 5], 1u << (o & 31));
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
         a.fitness[b] = (int64_t)ret + 1000000LL * (O - nsched);
         a.status[b] = (!minpre && (long long)m * k > R) ? VRPRPD_ST_RES : 0u;
     }
-    if (log && a.ops_out && a.rt_out) {
+    if constexpr (kLog) {
         __threadfence_block();   // the log written by lane 0, read by every lane
         // per-vehicle counts, then a stable scatter in schedule order
         int cnt = 0;
@@ -342,6 +344,14 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 
 // Workspace of one launch over B chromosomes: op orders, key flags and, when
 // the sequences are wanted, the schedule logs.
+template <typename DT>
+static const void* decode_kernel_for(bool small_m, bool log)
+{
+    if (small_m)
+        return log ? (const void*)decode_kernel<DT, true, true> : (const void*)decode_kernel<DT, true, false>;
+    return log ? (const void*)decode_kernel<DT, false, true> : (const void*)decode_kernel<DT, false, false>;
+}
+
 int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool want_ops)
 {
     const int n_lds = by_inst ? set->n_max : set->host[0].n;
@@ -390,13 +400,12 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     if (rc) return rc;
     hipLaunchKernelGGL(decode_sort_kernel, dim3((unsigned)B), dim3(64), sort_lds, st, a);
     VRP_HIP(hipGetLastError());
-    if (set->dist16) {
-        if ((rc = launch(reinterpret_cast<const void*>(decode_kernel<uint16_t>), L.bytes))) return rc;
-        hipLaunchKernelGGL(decode_kernel<uint16_t>, dim3((unsigned)B), dim3(64), L.bytes, st, a);
-    } else {
-        if ((rc = launch(reinterpret_cast<const void*>(decode_kernel<int32_t>), L.bytes))) return rc;
-        hipLaunchKernelGGL(decode_kernel<int32_t>, dim3((unsigned)B), dim3(64), L.bytes, st, a);
-    }
+    const bool small_m = (inst ? set->m_max : set->host[0].m) <= 16;
+    const void* kern = set->dist16 ? decode_kernel_for<uint16_t>(small_m, log != nullptr)
+                                   : decode_kernel_for<int32_t>(small_m, log != nullptr);
+    if ((rc = launch(kern, L.bytes))) return rc;
+    void* kargs[] = {&a};
+    VRP_HIP(hipLaunchKernel(kern, dim3((unsigned)B), dim3(64), kargs, (size_t)L.bytes, st));
     VRP_HIP(hipGetLastError());
     return VRPRPD_OK;
 }
