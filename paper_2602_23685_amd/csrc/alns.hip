@@ -198,6 +198,8 @@ __device__ int stage_solution(OpStore<DT>& S, const uint16_t* ops, const uint16_
     __syncthreads();
     const int L = re[m - 1];
     for (int j = threadIdx.x; j < L; j += blockDim.x) S.set_code(j, ops[j]);
+    // padding past the last route for the sweeps' unguarded fetches
+    for (int j = L + threadIdx.x; j < L + kAlnsStep; j += blockDim.x) S.set(j, 0u, 0);
     __syncthreads();
     for (int j = threadIdx.x; j < L; j += blockDim.x) {
         const int c = (int)(S.code(j) >> 1);

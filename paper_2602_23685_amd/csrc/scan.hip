@@ -123,6 +123,8 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
         }
         S.set_code(j, cd);
     }
+    // padding past the last route for the sweep's unguarded fetches
+    for (int j = total + tid; j < total + kScanStep; j += NT) S.set(j, 0u, 0);
     __syncthreads();
     if (!rt_bad && !seg_bad) {
         for (int c = 1 + tid; c <= n; c += NT) {

@@ -165,6 +165,10 @@ __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready
 // ---------------------------------------------------------------------------
 // Sweep over "virtual" routes: a staged base solution seen through a Route
 // object that splices ops in or out (Route::vlen, Route::fetch(i, code, leg)).
+// A step fetches its K ops without testing the route's end: the op store
+// holds valid codes past every route (the next route's ops, then K padding
+// entries of code 0), so every fetch and ready[] read stays in range and the
+// ops past the end are never taken.
 // ready[] keeps no per-evaluation initialisation: its sign convention flips
 // with `pol` after every completed evaluation (see the insertion scan).
 // pblk[c] = p_c for the drop's ready time.  Route::record(i, t) may keep the
@@ -181,11 +185,7 @@ __device__ __forceinline__ SweepOut sweep_route(const Route& R, int* ready, cons
             uint32_t cd[K];
             int leg[K], r[K];
 #pragma unroll
-            for (int u = 0; u < K; ++u) {
-                cd[u] = 0;
-                leg[u] = 0;
-                if (ptr + u < e) R.fetch(ptr + u, cd[u], leg[u]);
-            }
+            for (int u = 0; u < K; ++u) R.fetch(ptr + u, cd[u], leg[u]);
 #pragma unroll
             for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);
             const int t_before = o.t;
@@ -238,20 +238,15 @@ struct InsRoute {
     uint32_t k1, k2;
     int lg1, lg2, la1, la2;
     int ret;
+    // Branch-free: the base op is loaded in every case and replaced by
+    // selects (at i = x1 or x2 the load reads a neighbouring base op).
     __device__ __forceinline__ void fetch(int i, uint32_t& cd, int& leg) const
     {
-        if (i == x1) {
-            cd = k1;
-            leg = lg1;
-        } else if (i == x2) {
-            cd = k2;
-            leg = lg2;
-        } else {
-            const int j = bs + i - (i > x1) - (i > x2);
-            S->load(j, cd, leg);
-            if (i == x1 + 1) leg = la1;
-            else if (i == x2 + 1) leg = la2;
-        }
+        uint32_t c0;
+        int l0;
+        S->load(bs + i - (i > x1) - (i > x2), c0, l0);
+        cd = i == x1 ? k1 : (i == x2 ? k2 : c0);
+        leg = i == x1 ? lg1 : (i == x2 ? lg2 : (i == x1 + 1 ? la1 : (i == x2 + 1 ? la2 : l0)));
     }
     __device__ __forceinline__ void record(int, int) const {}
 };
@@ -271,9 +266,9 @@ struct DelRouteT {
     __device__ __forceinline__ int base_index(int i) const { return bs + i + (i >= y1) + (i >= y2); }
     __device__ __forceinline__ void fetch(int i, uint32_t& cd, int& leg) const
     {
-        S->load(base_index(i), cd, leg);
-        if (i == y2) leg = lb2;
-        else if (i == y1) leg = lb1;
+        int l0;
+        S->load(base_index(i), cd, l0);
+        leg = i == y2 ? lb2 : (i == y1 ? lb1 : l0);
     }
     __device__ __forceinline__ void record(int i, int t) const
     {
