@@ -85,6 +85,7 @@ template <typename DT, int GL, int NG, int K, bool kOneInst>
 __global__ __launch_bounds__(64) void eval_kernel(EvalArgs a)
 {
     static_assert(NG * GL <= 64, "groups per wave");
+    static_assert(K <= kStepOps && K <= GL, "sweep step within the op padding");
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int grp = lane / GL, li = lane % GL;
@@ -209,6 +210,9 @@ __global__ __launch_bounds__(64) void eval_kernel(EvalArgs a)
             }
         }
     }
+    // padding past the last route: the sweep reads ready[] for its next K ops
+    // without testing the route's end
+    if (!gbad && li < K) S.set(total + li, 0u, 0);
     wave_lds_fence();
     if (!gbad) {
         for (int c = 1 + li; c <= n; c += GL) {

@@ -127,6 +127,7 @@ __device__ __forceinline__ int sweep_step(SweepOut& o, const uint32_t* cd, const
     return took;
 }
 
+// The op store must hold valid codes for K entries past the last route.
 template <int GL, int K, typename DT>
 __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready, int s, int e)
 {
@@ -140,7 +141,7 @@ __device__ __forceinline__ SweepOut sweep_group(const OpStore<DT>& S, int* ready
 #pragma unroll
             for (int u = 0; u < K; ++u) S.load(ptr + u, cd[u], leg[u]);
 #pragma unroll
-            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[(ptr + u < e) ? (int)(cd[u] >> 1) : 0]);
+            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);   // valid codes past e (padding)
             took = sweep_step<K, false>(o, cd, leg, r, e - ptr, ready, nullptr, 0);
             ptr += took;
         }
