@@ -78,15 +78,16 @@ struct SweepOut {
     bool dead;          // group deadlocked
 };
 
-// One lane's attempt at its next K ops (branch-free except the drop's
-// store).  cd/leg: the ops; r: ready[] entries read at the start of the step;
-// n_left: ops left on the route.  Returns the number of ops taken.
-// pol selects the sign convention of ready[] (see sweep_route); the explicit
-// evaluation uses pol = 0 with ready[c] = ~p_c before the drop, so the drop's
-// ready time is arr + p_c with p_c = ~r.
+// One lane's attempt at its next K ops (branch-free).  cd/leg: the ops; r:
+// ready[] entries read at the start of the step; n_left: ops left on the
+// route.  Returns the number of ops taken.
+// kPolarity: ready[] entries are stored XOR pm (pm = 0 or -1, the sign
+// convention of the evaluation, see sweep_route) and pv[u] = p_c of op u,
+// read beside r[u]; otherwise (the explicit evaluation) ready[c] = ~p_c
+// before the drop, so the drop's ready time is arr + p_c with p_c = ~r.
 template <int K, bool kPolarity>
 __device__ __forceinline__ int sweep_step(SweepOut& o, const uint32_t* cd, const int* leg, const int* r,
-                                          int n_left, int* ready, const int* pblk, int pol)
+                                          int n_left, int* ready, const int* pv, int pm)
 {
     bool go = true;
     int took = 0;
@@ -95,27 +96,14 @@ __device__ __forceinline__ int sweep_step(SweepOut& o, const uint32_t* cd, const
         const bool isP = cd[u] & 1u;
         const int c = (int)(cd[u] >> 1);
         const int arr = o.t + leg[u];
-        bool rdy;
-        int rv;
-        if constexpr (kPolarity) {
-            rdy = pol ? (r[u] < 0) : (r[u] >= 0);
-            rv = pol ? ~r[u] : r[u];
-        } else {
-            rdy = r[u] >= 0;
-            rv = r[u];
-        }
+        const int rv = kPolarity ? (r[u] ^ pm) : r[u];
+        const bool rdy = rv >= 0;
         const bool ok = go && (u < n_left) && (!isP || rdy);
         const int tn = isP ? (arr > rv ? arr : rv) : arr;
         // A drop publishes its ready time.  Every other case writes to the
         // unused slot ready[0] instead of branching around the store.
         const bool pub = ok && !isP;
-        int val;
-        if constexpr (kPolarity) {
-            const int x = arr + pblk[pub ? c : 0];
-            val = pol ? ~x : x;
-        } else {
-            val = arr + ~r[u];
-        }
+        const int val = kPolarity ? ((arr + pv[u]) ^ pm) : arr + ~r[u];
         lds_store(&ready[pub ? c : 0], val);
         o.t = ok ? tn : o.t;
         o.w += ok ? (isP ? -1 : 1) : 0;
@@ -180,31 +168,33 @@ __device__ __forceinline__ SweepOut sweep_route(const Route& R, int* ready, cons
     SweepOut o{0, 0, 0, 0, false};
     int ptr = 0;
     const int e = R.vlen;
+    const int pm = -pol;   // stored entries are XOR pm: 0 or all ones
     for (;;) {
         int took = 0;
         if (ptr < e) {
             uint32_t cd[K];
-            int leg[K], r[K];
+            int leg[K], r[K], pv[K];
 #pragma unroll
             for (int u = 0; u < K; ++u) R.fetch(ptr + u, cd[u], leg[u]);
 #pragma unroll
-            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);
-            const int t_before = o.t;
-            (void)t_before;
+            for (int u = 0; u < K; ++u) {
+                r[u] = lds_load(&ready[cd[u] >> 1]);
+                pv[u] = lds_load(&pblk[cd[u] >> 1]);
+            }
             if constexpr (Route::kRecords) {
                 // record needs each op's own time: take the ops one by one
                 SweepOut o2 = o;
-                took = sweep_step<K, true>(o2, cd, leg, r, e - ptr, ready, pblk, pol);
+                took = sweep_step<K, true>(o2, cd, leg, r, e - ptr, ready, pv, pm);
                 int t = o.t;
                 for (int u = 0; u < took; ++u) {
                     const int arr = t + leg[u];
-                    const int rv = pol ? ~r[u] : r[u];
+                    const int rv = r[u] ^ pm;
                     t = (cd[u] & 1u) ? (arr > rv ? arr : rv) : arr;
                     R.record(ptr + u, t);
                 }
                 o = o2;
             } else {
-                took = sweep_step<K, true>(o, cd, leg, r, e - ptr, ready, pblk, pol);
+                took = sweep_step<K, true>(o, cd, leg, r, e - ptr, ready, pv, pm);
             }
             ptr += took;
         }
