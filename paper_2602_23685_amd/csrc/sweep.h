@@ -174,8 +174,16 @@ __device__ __forceinline__ SweepOut sweep_route(const Route& R, int* ready, cons
         if (ptr < e) {
             uint32_t cd[K];
             int leg[K], r[K], pv[K];
+            // Most steps of the wave touch no splice point: their ops are a
+            // contiguous slice of the base, read without the selects.
+            if (__builtin_amdgcn_ballot_w64(!R.plain(ptr, K)) == 0) {
+                const int j0 = R.plain_base(ptr);
 #pragma unroll
-            for (int u = 0; u < K; ++u) R.fetch(ptr + u, cd[u], leg[u]);
+                for (int u = 0; u < K; ++u) R.S->load(j0 + u, cd[u], leg[u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < K; ++u) R.fetch(ptr + u, cd[u], leg[u]);
+            }
 #pragma unroll
             for (int u = 0; u < K; ++u) {
                 r[u] = lds_load(&ready[cd[u] >> 1]);
@@ -239,6 +247,13 @@ struct InsRoute {
         cd = i == x1 ? k1 : (i == x2 ? k2 : c0);
         leg = i == x1 ? lg1 : (i == x2 ? lg2 : (i == x1 + 1 ? la1 : (i == x2 + 1 ? la2 : l0)));
     }
+    // Ops ptr .. ptr + K - 1 are base ops plain_base(ptr) + u with their own
+    // legs when the window holds neither spliced op nor the op after one.
+    __device__ __forceinline__ bool plain(int ptr, int K) const
+    {
+        return (ptr > x1 + 1 || ptr + K <= x1) && (ptr > x2 + 1 || ptr + K <= x2);
+    }
+    __device__ __forceinline__ int plain_base(int ptr) const { return bs + ptr - (ptr > x1) - (ptr > x2); }
     __device__ __forceinline__ void record(int, int) const {}
 };
 
@@ -261,6 +276,12 @@ struct DelRouteT {
         S->load(base_index(i), cd, l0);
         leg = i == y2 ? lb2 : (i == y1 ? lb1 : l0);
     }
+    // As for InsRoute: the window holds no op whose leg was replaced.
+    __device__ __forceinline__ bool plain(int ptr, int K) const
+    {
+        return (ptr > y1 || ptr + K <= y1) && (ptr > y2 || ptr + K <= y2);
+    }
+    __device__ __forceinline__ int plain_base(int ptr) const { return base_index(ptr); }
     __device__ __forceinline__ void record(int i, int t) const
     {
         if (times) times[base_index(i)] = t;
