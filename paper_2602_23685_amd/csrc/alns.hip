@@ -397,41 +397,59 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a)
             key[x] = x < n ? (((unsigned long long)((1LL << 34) - gain[x + 1]) << 16) | (unsigned)(x + 1)) : ~0ull;
         __syncthreads();
         block_sort_u64(key, npow);
-        // total rank weight sum_{r <= min(n, 1024)} floor(2^60 / r^6): integer
+        // rank weights floor(2^60 / r^6) for ranks r <= min(n, 1024) (the
+        // times[] space is free for this operator) and their total: integer
         // sums, so summing in parallel gives the same value
+        const int nw = n < 1024 ? n : 1024;
+        unsigned long long* wt = reinterpret_cast<unsigned long long*>(times);
         __shared__ unsigned long long wtot;
         if (threadIdx.x == 0) wtot = 0;
         __syncthreads();
         {
             unsigned long long part = 0;
-            for (int i = threadIdx.x; i < n && i < 1024; i += blockDim.x) {
+            for (int i = threadIdx.x; i < nw; i += blockDim.x) {
                 const unsigned long long r = (unsigned long long)(i + 1);
-                part += (1ULL << 60) / (r * r * r * r * r * r);
+                wt[i] = (1ULL << 60) / (r * r * r * r * r * r);
+                part += wt[i];
             }
             atomicAdd(&wtot, part);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            // Roulette over the unflagged ranks, one wave: the first rank
+            // whose running weight sum exceeds the draw, found 64 ranks at a
+            // time by a wave prefix sum.
+            const int lane = threadIdx.x;
             unsigned long long tot = wtot;
             int cnt = 0;
             for (int s2 = 0; s2 < q; ++s2) {
                 if (tot == 0) break;
                 const unsigned long long w32 = adraw(a.seed, db + s2, it, uc);
                 const unsigned long long hi = (w32 * (tot >> 32)) + ((w32 * (tot & 0xFFFFFFFFull)) >> 32);
-                unsigned long long acc = 0;
+                unsigned long long base = 0;
                 int pick = -1;
-                for (int i = 0; i < n; ++i) {
-                    const unsigned long long r = (unsigned long long)(i + 1);
-                    const unsigned long long w = (i < 1024 && !flag[i]) ? (1ULL << 60) / (r * r * r * r * r * r) : 0ULL;
-                    acc += w;
-                    if (w && hi < acc) { pick = i; break; }
+                for (int i0 = 0; i0 < nw && pick < 0; i0 += 64) {
+                    const int i = i0 + lane;
+                    const unsigned long long w = (i < nw && !flag[i]) ? wt[i] : 0ULL;
+                    unsigned long long x = w;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const unsigned long long y = __shfl_up(x, o, 64);
+                        if (lane >= o) x += y;
+                    }
+                    const unsigned long long hit = __ballot(w != 0ULL && hi < base + x);
+                    if (hit) pick = i0 + __ffsll((long long)hit) - 1;
+                    base += __shfl(x, 63, 64);
                 }
-                const unsigned long long r = (unsigned long long)(pick + 1);
-                tot -= (1ULL << 60) / (r * r * r * r * r * r);
-                flag[pick] = 1;
-                rem[cnt++] = (int)(key[pick] & 0xFFFFu);
+                tot -= wt[pick];
+                if (lane == 0) {
+                    flag[pick] = 1;
+                    rem[cnt] = (int)(key[pick] & 0xFFFFu);
+                }
+                ++cnt;
+                wave_lds_fence();
             }
-            sh_cnt = cnt;
+            if (lane == 0) sh_cnt = cnt;
         }
     } else if (di == 2 || di == 3) {                 // Shaw, cluster
         const int cen = 1 + uint_below(adraw(a.seed, db, it, uc), n);
@@ -2019,7 +2037,7 @@ template <typename DT, int GL>
 static int launch_gains(alns_state* s, hipStream_t st)
 {
     constexpr int WPB = kGainWaves;
-    constexpr int per_block = 64;
+    constexpr int per_block = 2 * kGainGroups;   // two sweeps per group
     const AlnsDev& d = s->d;
     hipLaunchKernelGGL((k_gains<DT, GL, WPB>), dim3(d.C, (d.N + per_block - 1) / per_block), dim3(64 * WPB),
                        s->lds_gain, st, d, per_block);
