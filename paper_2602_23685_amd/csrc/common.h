@@ -174,10 +174,48 @@ __device__ __forceinline__ void sort8_stage(unsigned long long (&r)[8], int base
     }
 }
 
-// The same sort with the stages of partner distance below 8 done in
-// registers: a thread loads 8 consecutive keys, runs those stages and stores
-// them back, so they need a third of the memory traffic and one barrier
-// instead of three.  n >= 16; smaller n uses the memory-only network.
+// Compare-exchange toward ascending order when up, descending otherwise.
+__device__ __forceinline__ void cx_u64(unsigned long long& a, unsigned long long& b, bool up)
+{
+    const bool sw = (a > b) == up;
+    const unsigned long long x = a;
+    a = sw ? b : a;
+    b = sw ? x : b;
+}
+
+// S consecutive stages of the bitonic merge of size k, partner distances
+// j, j/2, ..., q = j / 2^(S-1) (q >= 8), in one pass over memory: each
+// thread loads the 2^S keys i0 + e q (i0 with the S distance bits clear, all
+// in one run of 2j <= k keys, so one direction), runs the S stages in
+// registers and stores them back.
+template <int S>
+__device__ __forceinline__ void bitonic_group(unsigned long long* key, int n, int k, int j)
+{
+    constexpr int E = 1 << S;
+    const int q = j >> (S - 1);
+    const int lq = __ffs(q) - 1;
+    for (int g = threadIdx.x; g < n / E; g += blockDim.x) {
+        const int i0 = (g & (q - 1)) | ((g >> lq) << (lq + S));
+        const bool up = (i0 & k) == 0;
+        unsigned long long r[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) r[e] = key[i0 + e * q];
+#pragma unroll
+        for (int d = E / 2; d >= 1; d >>= 1)
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (!(e & d)) cx_u64(r[e], r[e | d], up);
+#pragma unroll
+        for (int e = 0; e < E; ++e) key[i0 + e * q] = r[e];
+    }
+    __syncthreads();
+}
+
+// The same sort with few passes over memory: the stages of partner distance
+// below 8 run in registers on 8 consecutive keys per thread, the others in
+// groups of up to three stages per pass (bitonic_group), so a merge of size
+// k = 2048 takes three passes and a register pass instead of eight stages.
+// n >= 16 (a power of two); smaller n uses the memory-only network.
 __device__ inline void block_sort_u64(unsigned long long* key, int n)
 {
     if (n < 16) {
@@ -200,18 +238,18 @@ __device__ inline void block_sort_u64(unsigned long long* key, int n)
     }
     __syncthreads();
     for (int k = 16; k <= n; k <<= 1) {
-        for (int j = k >> 1; j >= 8; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += T) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const unsigned long long a = key[i], b = key[l];
-                    if ((a > b) == ((i & k) == 0)) {
-                        key[i] = b;
-                        key[l] = a;
-                    }
-                }
+        int j = k >> 1;
+        while (j >= 8) {
+            if (j >= 32) {
+                bitonic_group<3>(key, n, k, j);
+                j >>= 3;
+            } else if (j >= 16) {
+                bitonic_group<2>(key, n, k, j);
+                j >>= 2;
+            } else {
+                bitonic_group<1>(key, n, k, j);
+                j >>= 1;
             }
-            __syncthreads();
         }
         for (int base = 8 * threadIdx.x; base < n; base += 8 * T) {
             unsigned long long r[8];
