@@ -1,15 +1,15 @@
 // brkga_decode_eval: the multi-pass decoder of Section 4.4.2 (Algorithm 2)
 // and the makespan / penalised fitness of the schedule it builds.
 //
-// Mapping: one wavefront per chromosome, in two launches.
-//  decode_sort_kernel: loads and checks the 2n priority keys (and hints) and
-//     sorts (key, op index) pairs with a bitonic network in LDS; the op order
-//     goes to a workspace in global memory.
-//  decode_kernel: runs the passes: the ops in priority order are read in
-//     chunks of 64 lanes (the next chunk's load in flight); a ballot finds the
-//     next unscheduled op that is feasible at its turn, lanes v < m price it
-//     on vehicle v (completion time, hint-rotated tie index) and the least
-//     key picks the vehicle; then optionally scatters the schedule into
+// Mapping: one block per chromosome in each of two launches.
+//  decode_sort_kernel (four waves): loads and checks the 2n priority keys (and
+//     hints) and sorts (key, op index) pairs with a bitonic network in LDS;
+//     the op order goes to a workspace in global memory.
+//  decode_kernel (one wave): runs the passes: the ops in priority order are
+//     read in chunks of 64 lanes (the next chunk's load in flight); lane masks
+//     give the next unscheduled op that is feasible at its turn, lanes v < m
+//     price it on vehicle v (completion time, hint-rotated tie index) and the
+//     least key picks the vehicle; then optionally scatters the schedule into
 //     per-vehicle sequences.
 // The passes, a long chain of dependent wave-wide decisions, keep only
 // ready[] and the scheduled-op bits in LDS (about 4n bytes), so many more
@@ -95,10 +95,12 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
     return x;
 }
 
-__global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
+constexpr int kSortThreads = 256;   // threads per chromosome in the key sort
+
+__global__ __launch_bounds__(kSortThreads) void decode_sort_kernel(DecodeArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
     if (b >= a.B) return;
     unsigned long long* kx = reinterpret_cast<unsigned long long*>(smem);
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
     bool bad = bad_inst;
     // A valid key is a non-negative float, so its bits order like the value;
     // the op index in the low 16 bits breaks ties (padding sorts last).
-    for (int o = lane; o < cap; o += 64) {
+    for (int o = tid; o < cap; o += kSortThreads) {
         uint32_t kb = 0xFFFFFFFFu;
         if (o < O) {
             if (!key_ok(pr[o], kb)) bad = true;
@@ -125,8 +127,8 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
         }
         kx[o] = ((unsigned long long)kb << 16) | (unsigned)(o < O ? o : 0xFFFF);
     }
-    if (__ballot(bad)) {
-        if (lane == 0) {
+    if (__syncthreads_or(bad)) {
+        if (tid == 0) {
             a.badkey[b] = 1;
             a.fitness[b] = INT64_MAX;
             a.makespan[b] = INT32_MAX;
@@ -134,16 +136,15 @@ __global__ __launch_bounds__(64) void decode_sort_kernel(DecodeArgs a)
             a.status[b] = VRPRPD_ST_BAD_KEY;
         }
         if (a.rt_out)
-            for (int v = lane; v < m; v += 64) a.rt_out[b * a.rt_stride + v] = 0;
+            for (int v = tid; v < m; v += kSortThreads) a.rt_out[b * a.rt_stride + v] = 0;
         return;
     }
-    wave_lds_fence();
 
     // ---- 2. bitonic sort of (key, op) pairs ----------------------------------
     block_sort_u64(kx, cap);
     uint16_t* ord = a.order + b * a.cap;
-    for (int j = lane; j < O; j += 64) ord[j] = (uint16_t)(kx[j] & 0xFFFFu);
-    if (lane == 0) a.badkey[b] = 0;
+    for (int j = tid; j < O; j += kSortThreads) ord[j] = (uint16_t)(kx[j] & 0xFFFFu);
+    if (tid == 0) a.badkey[b] = 0;
 }
 
 // Minima by DPP row shifts (VALU only, no LDS crossbar, no scalar chain):
@@ -398,7 +399,7 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     };
     int rc = launch(reinterpret_cast<const void*>(decode_sort_kernel), sort_lds);
     if (rc) return rc;
-    hipLaunchKernelGGL(decode_sort_kernel, dim3((unsigned)B), dim3(64), sort_lds, st, a);
+    hipLaunchKernelGGL(decode_sort_kernel, dim3((unsigned)B), dim3(kSortThreads), sort_lds, st, a);
     VRP_HIP(hipGetLastError());
     const bool small_m = (inst ? set->m_max : set->host[0].m) <= 16;
     const void* kern = set->dist16 ? decode_kernel_for<uint16_t>(small_m, log != nullptr)
