@@ -61,6 +61,44 @@ def test_decode_parity(orc, P, case):
                 assert np.array_equal(ops[b][:L], r["ops"]), b
 
 
+@pytest.mark.parametrize("case", [(1000, 10, 10, 100, "1R20d10", 64), (20, 40, 1, 10, "1R10", 64)],
+                         ids=lambda c: f"n{c[0]}m{c[1]}")
+def test_decode_parity_without_sequences(orc, P, case):
+    """The launch without op sequences (no schedule log) prices the same."""
+    n, m, k, R, rule, B = case
+    inst = synth.make_instance(n, m, k, R, rule, seed=7100 + n)
+    prio, hint = synth.random_keys(B, n, seed=n + 3, special=True)
+    S = P.InstanceSet([inst])
+    out = P.brkga_decode_eval(S, dev(prio), dev(hint))
+    torch.cuda.synchronize()
+    got = np.stack([out["fitness"].cpu().numpy(), out["makespan"].cpu().numpy(),
+                    out["unscheduled"].cpu().numpy(), out["status"].cpu().numpy().view(np.uint32)], axis=1)
+    for b in range(B):
+        r = orc.decode(inst, prio[b], hint[b])
+        assert tuple(got[b]) == (r["fitness"], r["makespan"], r["unscheduled"], r["status"]), b
+
+
+def test_decode_parity_wide_distances(orc, P):
+    """Travel times above 65535 keep the int32 distance layout in the decoder."""
+    inst = synth.make_instance(80, 5, 4, 20, "2x", seed=7201)
+    inst.d = (inst.d.astype(np.int64) * 500).astype(np.int32)
+    inst.p = (inst.p.astype(np.int64) * 500).astype(np.int32)
+    S = P.InstanceSet([inst])
+    assert S.dist16 == 0
+    B = 64
+    prio, hint = synth.random_keys(B, 80, seed=7202, special=True)
+    for want_ops in (False, True):
+        out = P.brkga_decode_eval(S, dev(prio), dev(hint), want_ops=want_ops)
+        torch.cuda.synchronize()
+        f = out["fitness"].cpu().numpy()
+        for b in range(B):
+            r = orc.decode(inst, prio[b], hint[b], want_ops=want_ops)
+            assert f[b] == r["fitness"], (b, want_ops)
+            if want_ops and not r["status"] & 16:
+                L = int(r["rt_end"][-1])
+                assert np.array_equal(out["ops"][b].cpu().numpy()[:L], r["ops"]), b
+
+
 @pytest.mark.parametrize("Np", [1024, 4096, 5000], ids=lambda x: f"Np{x}")
 def test_evolve_parity(orc, P, Np):
     """Ranking by the block-wide sort (Np <= 4096) and by counting (larger)."""

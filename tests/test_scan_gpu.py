@@ -67,6 +67,25 @@ def test_scan_parity(orc, P, case):
         assert (ost == 0).any()
 
 
+def test_scan_parity_wide_distances(orc, P):
+    """Travel times above 65535: the int32 op store (separate code and leg
+    arrays, its own padding) in the scan."""
+    inst = synth.make_instance(70, 4, 5, 20, "2x", seed=5301)
+    inst.d = (inst.d.astype(np.int64) * 500).astype(np.int32)
+    inst.p = (inst.p.astype(np.int64) * 500).astype(np.int32)
+    S = P.InstanceSet([inst])
+    assert S.dist16 == 0
+    bops, brt = make_base(inst, 7, 6)
+    T = 2000
+    tuples = synth.random_tuples(bops, brt, 70, 4, T, seed=8, invalid_frac=0.05)
+    seg_off = np.array([0, 700, 1300, T], np.int64)
+    mk, st, top = run_scan(P, S, bops, brt, tuples, seg_off)
+    omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg_off)
+    assert np.array_equal(mk, omk) and np.array_equal(st, ost)
+    assert np.array_equal(top, otop)
+    assert (omk < 2**31 - 1).sum() > T // 2       # most tuples were swept to a makespan
+
+
 def test_scan_deadlock_tuples_and_reuse(orc, P):
     """Pickups placed before their own drop on another vehicle deadlock; the
     group must reset its state and evaluate the following tuples exactly."""
