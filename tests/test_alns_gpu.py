@@ -63,6 +63,29 @@ def test_alns_trajectory_parity(orc, P, case):
         assert orc.eval_one(inst, bops.cpu().numpy()[:2 * n], b_rt) == (mk, 0)
 
 
+def test_alns_trajectory_parity_wide_distances(orc, P):
+    """Travel times above 65535: the int32 op store in every ALNS kernel."""
+    inst = synth.make_instance(30, 3, 3, 9, "2x", seed=9301)
+    inst.d = (inst.d.astype(np.int64) * 500).astype(np.int32)
+    inst.p = (inst.p.astype(np.int64) * 500).astype(np.int32)
+    S = P.InstanceSet([inst])
+    assert S.dist16 == 0
+    ops, rt = synth.round_robin_solution(inst, vehicles=3)
+    chains, iters, seed = 2, 20, 9302
+    prm = dict(tuple_budget=300, import_interval=0)
+    ref = orc.alns_run(inst, orc.alns_params(**prm), chains, iters, seed, ops, rt, trace=True)
+    st = P.AlnsState(S, [0], chains, P.alns_params(**prm), seed, torch.from_numpy(ops).cuda(),
+                     torch.from_numpy(rt).cuda())
+    tr = st.set_trace(iters)
+    st.step(iters)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    for ch in range(chains):
+        for it in range(iters):
+            assert np.array_equal(got[ch, it], ref["trace"][ch, it]), (ch, it)
+    assert np.array_equal(st.state()["zb"], ref["best_mk"])
+
+
 def test_alns_continues_across_calls(orc, P):
     """Two calls of alns_step(k) equal one call of alns_step(2k)."""
     inst = synth.make_instance(16, 2, 2, 4, "2x", seed=77)
