@@ -975,37 +975,33 @@ __global__ __launch_bounds__(256) void k_enum(AlnsDev a)
 __device__ void splice_tuple(const uint16_t* src, const uint16_t* srt, int m, const vrprpd_tuple tp, uint16_t* dst,
                              uint16_t* drt)
 {
-    __shared__ int nstart[kMaxM + 1];
+    __shared__ int nstart[kMaxM + 1], sstart[kMaxM];
     __syncthreads();
     if (threadIdx.x == 0) {
         int w = 0;
         for (int v = 0; v < m; ++v) {
             nstart[v] = w;
-            const int len = srt[v] - (v ? srt[v - 1] : 0);
+            sstart[v] = v ? srt[v - 1] : 0;
+            const int len = srt[v] - sstart[v];
             w += len + (v == tp.vD) + (v == tp.vP);
             drt[v] = (uint16_t)w;
         }
         nstart[m] = w;
     }
     __syncthreads();
-    if (threadIdx.x < m) {
-        const int v = threadIdx.x;
-        const int s = v ? srt[v - 1] : 0, len = srt[v] - s;
-        const int w = nstart[v];
-        // virtual positions of the inserted ops on this route
+    // every output position at once: its route v, the virtual index i on it,
+    // and the inserted ops at virtual positions x1 < x2 of that route
+    const int total = nstart[m];
+    for (int p = threadIdx.x; p < total; p += blockDim.x) {
+        int v = 0;
+        while (nstart[v + 1] <= p) ++v;
+        const int i = p - nstart[v];
         int x1 = kNoPos, x2 = kNoPos;
         uint16_t k1 = 0, k2 = 0;
         if (v == tp.vD && v == tp.vP) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); x2 = tp.pP; k2 = (uint16_t)((tp.c << 1) | 1); }
         else if (v == tp.vD) { x1 = tp.pD; k1 = (uint16_t)(tp.c << 1); }
         else if (v == tp.vP) { x1 = tp.pP; k1 = (uint16_t)((tp.c << 1) | 1); }
-        const int vlen = len + (x1 != kNoPos) + (x2 != kNoPos);
-        for (int i = 0; i < vlen; ++i) {
-            uint16_t code;
-            if (i == x1) code = k1;
-            else if (i == x2) code = k2;
-            else code = src[s + i - (i > x1) - (i > x2)];
-            dst[w + i] = code;
-        }
+        dst[p] = i == x1 ? k1 : (i == x2 ? k2 : src[sstart[v] + i - (i > x1) - (i > x2)]);
     }
 }
 
@@ -1060,17 +1056,27 @@ __global__ __launch_bounds__(256) void k_select(AlnsDev a)
             atomicMin((unsigned long long*)&o[a.tuples[t0 + k].vD], (unsigned long long)a.tmk[t0 + k]);
         }
         wave_lds_fence();
-        if (lane == 0) {
-            for (int x = 1; x < m; ++x)   // ascending, in place
-                for (int y = x; y > 0 && o[y] < o[y - 1]; --y) {
-                    const long long t = o[y];
-                    o[y] = o[y - 1];
-                    o[y - 1] = t;
+        // regret = sum over the kreg best vehicles (kBigC past m) of their
+        // best minus the overall best: the kk = min(kreg, m) smallest of
+        // o[0..m) by rank, summed across the wave
+        {
+            const long long ov = lane < m ? o[lane] : 0;
+            int rank = 0;
+            if (lane < m)
+                for (int u = 0; u < m; ++u) {
+                    const long long x = o[u];
+                    rank += (x < ov || (x == ov && u < lane)) ? 1 : 0;
                 }
-            long long reg = 0;
-            for (int h = 1; h < kreg && h < m; ++h) reg += o[h] - o[0];
-            for (int h = m; h < kreg; ++h) reg += kBigC - o[0];
-            regs[i] = reg;
+            const int kk = kreg < m ? kreg : m;
+            long long sum = (lane < m && rank < kk) ? ov : 0;
+            long long mn = lane < m ? ov : LLONG_MAX;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                sum += __shfl_xor(sum, off, 64);
+                const long long y = __shfl_xor(mn, off, 64);
+                mn = y < mn ? y : mn;
+            }
+            if (lane == 0) regs[i] = sum - (long long)kk * mn + (long long)(kreg > m ? kreg - m : 0) * (kBigC - mn);
         }
         wave_lds_fence();
     }
