@@ -114,11 +114,20 @@ def paper_start_oracle(oracle, inst, ls_budget=16384):
 
 
 def paper_start_gpu(P, S, chains, prm, seed):
-    """The same on the GPU: vrprpd_construct, an ALNS state from it and
-    alns_refine; returns the state and the refinement rounds."""
+    """The same on the GPU: vrprpd_construct, then alns_refine on a one-chain
+    state per instance (construction and refinement are deterministic, so
+    every chain would refine the same solution), then the ALNS state of all
+    chains from the refined solutions; returns it and the refinement rounds."""
+    import torch
     ops, rt = P.vrprpd_construct(S, P.CONS_SWEEP)
-    st = P.AlnsState(S, list(range(S.num_inst)), chains, prm, seed, ops, rt)
-    return st, st.refine()
+    ids = list(range(S.num_inst))
+    one = P.AlnsState(S, ids, 1, prm, seed, ops, rt)
+    rounds = one.refine()
+    best = [one.best(i) for i in ids]
+    one.close()
+    r_ops = torch.stack([b[1] for b in best])
+    r_rt = torch.stack([b[2] for b in best])
+    return P.AlnsState(S, ids, chains, prm, seed, r_ops, r_rt), rounds
 
 
 def time_to_oracle_best(P, torch, iters_oracle=2000, chains=32, budget_iters=4000):
