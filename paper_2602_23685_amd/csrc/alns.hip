@@ -2119,9 +2119,16 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
                 d.C * d.Q, std::max(1, (d.TPC + kScanTuplesPerBlock - 1) / kScanTuplesPerBlock), 1};
     for (int r = 0; r < d.Q; ++r) {
-        hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, d.Q), dim3(256), s->lds_enum, st, d);
+        // round r: at most Q - r customers still wait in any chain, so only
+        // those slots get blocks
+        const int active = d.Q - r;
+        hipLaunchKernelGGL(k_enum<DT>, dim3(d.C, active), dim3(256), s->lds_enum, st, d);
         VRP_HIP(hipGetLastError());
-        if ((rc = insert_scan_launch(sa, d.M, s->dist16, st))) return rc;
+        ScanArgs sr = sa;
+        sr.num_seg = d.C * active;
+        sr.seg_active = active;
+        sr.seg_stride = d.Q;
+        if ((rc = insert_scan_launch(sr, d.M, s->dist16, st))) return rc;
         hipLaunchKernelGGL(k_select, dim3(d.C), dim3(256), (size_t)16 * d.Q, st, d);
         VRP_HIP(hipGetLastError());
     }

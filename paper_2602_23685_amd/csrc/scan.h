@@ -24,6 +24,10 @@ struct ScanArgs {
     int32_t num_bases, num_inst, n_max, num_seg;
     int32_t blocks_per_seg;   // blocks sharing one segment's tuples (>= 1)
     int32_t top3_ready = 0;   // internal: seg_top3 already holds INT64_MAX (no fill launch)
+    // internal: with seg_active > 0 the launch covers only the first
+    // seg_active segments of each group of seg_stride (num_seg = groups *
+    // seg_active): block x scans segment (x / seg_active) * seg_stride + x % seg_active
+    int32_t seg_active = 0, seg_stride = 0;
 };
 
 // Launches the insertion-scan kernel for the arguments above.

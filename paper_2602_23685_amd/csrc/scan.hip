@@ -61,7 +61,8 @@ __global__ __launch_bounds__(64 * WPB) void scan_kernel(ScanArgs a)
     constexpr int NT = 64 * WPB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = lane / GL, li = lane % GL, gidx = wave * G + grp;
-    const int seg = blockIdx.x;
+    const int seg = a.seg_active > 0 ? (int)(blockIdx.x / a.seg_active) * a.seg_stride + (int)(blockIdx.x % a.seg_active)
+                                     : (int)blockIdx.x;
     const int ychunk = blockIdx.y, ny = gridDim.y;   // blocks sharing the segment
     const ScanLayout L = scan_layout<WPB, GL>(a.n_max, OpStore<DT>::kBytesPerOp);
     int* pblk = reinterpret_cast<int*>(smem + L.p_off);
