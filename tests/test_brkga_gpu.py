@@ -31,6 +31,7 @@ DECODE_CASES = [
     (30, 3, 2, 2, "5x", 0, 256),           # scarce resources: many passes, unscheduled ops
     (1, 1, 1, 1, "base", 0, 16),
     (20, 40, 1, 10, "1R10", 0, 64),        # more vehicles than customers
+    (70, 64, 2, 100, "2x", 1, 48),         # every lane a vehicle (all-ones vehicle mask)
 ]
 
 
