@@ -277,6 +277,7 @@ struct vrprpd_set {
     int device = 0;
     int32_t num_inst = 0, n_max = 0, m_max = 0, dist16 = 1;
     bool uniform_nm = true;
+    int64_t time_bound = 0;            // max over instances of (2n+1) * max d + sum p (bounds every time)
     std::vector<vrprpd::InstDev> host;  // same table as d_inst, on the host
     vrprpd::InstDev* d_inst = nullptr;
     void* d_dist = nullptr;            // uint16_t or int32_t, per dist16

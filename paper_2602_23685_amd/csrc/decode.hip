@@ -178,9 +178,13 @@ __device__ __forceinline__ int wave_min_dpp(int x)   // minimum over all 64 lane
 
 // kSmallM: every instance has m <= 16 (vehicle minimum within one DPP row).
 // kLog: the schedule is logged for the op sequences (ops_out).
-template <typename DT, bool kSmallM, bool kLog>
+// kPacked (with kSmallM): every time is below 2^27, so a vehicle's key
+// (completion time << 4 | its rank in the hint-rotated order) fits 31 bits
+// and one minimum gives both the time and the vehicle.
+template <typename DT, bool kSmallM, bool kLog, bool kPacked>
 __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 {
+    static_assert(!kPacked || kSmallM, "packed keys need m <= 16");
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
@@ -263,10 +267,20 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 const int r = lds_load(&ready[ci]);
                 const int key = isPi ? (arr > r ? arr : r) : arr;
                 const int kv = (isPi ? pok : dok) ? key : INT_MAX;
-                const int ks = kSmallM ? row0_min(kv) : wave_min_dpp(kv);
-                const unsigned long long tie = __builtin_amdgcn_ballot_w64(kv == ks) & VEH;
-                const unsigned long long upper = tie & (~0ull << hi);
-                const int vs = __ffsll((long long)(upper ? upper : tie)) - 1;
+                int ks, vs;
+                if constexpr (kPacked) {
+                    // rank (v - hint) mod 16: the hint vehicle first, then
+                    // the following ones cyclically (lanes >= m hold INT_MAX)
+                    const int kp = kv == INT_MAX ? INT_MAX : (kv << 4) | ((lane - hi) & 15);
+                    const int kq = row0_min(kp);
+                    ks = kq >> 4;
+                    vs = ((kq & 15) + hi) & 15;
+                } else {
+                    ks = kSmallM ? row0_min(kv) : wave_min_dpp(kv);
+                    const unsigned long long tie = __builtin_amdgcn_ballot_w64(kv == ks) & VEH;
+                    const unsigned long long upper = tie & (~0ull << hi);
+                    vs = __ffsll((long long)(upper ? upper : tie)) - 1;
+                }
                 const bool me = lane == vs;
                 // a drop on an empty vehicle preloads one resource
                 const int pre = (!isPi && __builtin_amdgcn_readlane(q, vs) == 0) ? 1 : 0;
@@ -346,11 +360,14 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 // Workspace of one launch over B chromosomes: op orders, key flags and, when
 // the sequences are wanted, the schedule logs.
 template <typename DT>
-static const void* decode_kernel_for(bool small_m, bool log)
+static const void* decode_kernel_for(bool small_m, bool packed, bool log)
 {
+    if (small_m && packed)
+        return log ? (const void*)decode_kernel<DT, true, true, true> : (const void*)decode_kernel<DT, true, false, true>;
     if (small_m)
-        return log ? (const void*)decode_kernel<DT, true, true> : (const void*)decode_kernel<DT, true, false>;
-    return log ? (const void*)decode_kernel<DT, false, true> : (const void*)decode_kernel<DT, false, false>;
+        return log ? (const void*)decode_kernel<DT, true, true, false>
+                   : (const void*)decode_kernel<DT, true, false, false>;
+    return log ? (const void*)decode_kernel<DT, false, true, false> : (const void*)decode_kernel<DT, false, false, false>;
 }
 
 int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool want_ops)
@@ -402,8 +419,9 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     hipLaunchKernelGGL(decode_sort_kernel, dim3((unsigned)B), dim3(kSortThreads), sort_lds, st, a);
     VRP_HIP(hipGetLastError());
     const bool small_m = (inst ? set->m_max : set->host[0].m) <= 16;
-    const void* kern = set->dist16 ? decode_kernel_for<uint16_t>(small_m, log != nullptr)
-                                   : decode_kernel_for<int32_t>(small_m, log != nullptr);
+    const bool packed = set->time_bound < (int64_t(1) << 27);   // (time << 4) | 15 stays below 2^31
+    const void* kern = set->dist16 ? decode_kernel_for<uint16_t>(small_m, packed, log != nullptr)
+                                   : decode_kernel_for<int32_t>(small_m, packed, log != nullptr);
     if ((rc = launch(kern, L.bytes))) return rc;
     void* kargs[] = {&a};
     VRP_HIP(hipLaunchKernel(kern, dim3((unsigned)B), dim3(64), kargs, (size_t)L.bytes, st));

@@ -82,6 +82,8 @@ extern "C" int vrprpd_set_create(vrprpd_set** out, int32_t num_inst, const vrprp
             return set_error(VRPRPD_ERANGE, "instance %d: (2n+1)*max d + sum p = %lld overflows int32 times", i,
                              (long long)((2 * (int64_t)D.n + 1) * dmax + psum));
         }
+        const int64_t tb = (2 * (int64_t)D.n + 1) * dmax + psum;
+        if (tb > s->time_bound) s->time_bound = tb;
         if (dmax > 65535) s->dist16 = 0;
         int ashift = 0;
         while ((dmax >> ashift) >= (1 << 14)) ++ashift;
