@@ -132,6 +132,75 @@ def _declare_alns(L):
     L.orc_alns_destroy.restype = C.c_int32
     L.orc_alns_destroy.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                    C.c_int32, P]
+    L.orc_alns_update.restype = C.c_int32
+    L.orc_alns_update.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int64]
+    L.orc_alns_enumerate.restype = C.c_int32
+    L.orc_alns_enumerate.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P]
+    L.orc_alns_repair.restype = C.c_int32
+    L.orc_alns_repair.argtypes = [P, C.c_int32, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P]
+    L.orc_alns_budget_split.restype = None
+    L.orc_alns_budget_split.argtypes = [C.c_int32, C.c_int32, P, P]
+
+
+class AlnsChain(C.Structure):
+    """The scalars Algorithm 1 keeps per chain (current and best makespan,
+    temperature, weights, scores, attempts, stagnation)."""
+    _fields_ = [("z", C.c_int32), ("zb", C.c_int32), ("T", C.c_double), ("T_init", C.c_double),
+                ("wD", C.c_double * 6), ("wR", C.c_double * 4), ("sD", C.c_int64 * 6), ("sR", C.c_int64 * 4),
+                ("aD", C.c_int32 * 6), ("aR", C.c_int32 * 4), ("stag", C.c_int32)]
+
+
+def alns_chain(z, zb=None, T=None, T0=0.30):
+    """A chain as Algorithm 1 initialises it from a solution of makespan z."""
+    c = AlnsChain()
+    c.z = z
+    c.zb = z if zb is None else zb
+    c.T = T0 * c.zb if T is None else T
+    c.T_init = c.T
+    for i in range(6):
+        c.wD[i] = 1.0
+    for i in range(4):
+        c.wR[i] = 1.0
+    return c
+
+
+def alns_update(params, chain, di, ri, repaired, zn, u, it):
+    """Algorithm 1 after one repair on `chain` (updated in place); returns 0
+    rejected, 1 improving, 2 new best, 3 accepted by annealing."""
+    return int(lib().orc_alns_update(C.byref(params), C.byref(chain), di, ri, int(repaired), zn, float(u), it))
+
+
+def alns_enumerate(inst, ops, rt_end, c, KD=0, KP=0):
+    """Ranked insertion tuples of customer c against a partial solution."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    cap = (2 * oi.n + oi.m + 2) ** 2
+    out = np.zeros(cap, dtype=TUPLE_DTYPE)
+    T = lib().orc_alns_enumerate(oi.ref, _ptr(ops), _ptr(rt), c, KD, KP, _ptr(out))
+    return out[:T]
+
+
+def alns_repair(inst, op, ops, rt_end, removed, KD=0, KP=0):
+    """One repair (0 greedy, 1 regret-2, 2 regret-3, 3 regret-m) of a partial
+    solution; returns (ok, makespan, ops, rt_end, insertion order)."""
+    oi = _oinst(inst)
+    ops = np.ascontiguousarray(ops, dtype=np.uint16)
+    rt = np.ascontiguousarray(rt_end, dtype=np.uint16)
+    rem = np.ascontiguousarray(removed, dtype=np.int32)
+    oo = np.zeros(2 * oi.n + 2, np.uint16)
+    orr = np.zeros(oi.m, np.uint16)
+    z = np.zeros(1, np.int32)
+    order = np.zeros(max(len(rem), 1), np.int32)
+    ok = lib().orc_alns_repair(oi.ref, op, _ptr(ops), _ptr(rt), _ptr(rem), len(rem), KD, KP, _ptr(oo), _ptr(orr),
+                               _ptr(z), _ptr(order))
+    return bool(ok), int(z[0]), oo[:int(orr[-1])], orr, [int(x) for x in order[:len(rem)]]
+
+
+def alns_budget_split(budget, nrem):
+    a, b = C.c_int32(), C.c_int32()
+    lib().orc_alns_budget_split(budget, nrem, C.byref(a), C.byref(b))
+    return a.value, b.value
 
 
 def det_exp(x):

@@ -572,8 +572,8 @@ static int local_search(const orc_inst* I, int kind, int budget, sol_t* S, int32
 
 /* ------------------------------------------------------------------ repair */
 /* Returns 1 on success (S complete), 0 if some customer had no feasible tuple. */
-static int repair(const orc_inst* I, int op, sol_t* S, int* rem, int nrem, int KD, int KP,
-                  orc_tuple* tbuf, slot_t* dbuf, slot_t* pbuf, sol_t* tmp, int32_t* zout)
+static int repair(const orc_inst* I, int op, sol_t* S, const int* rem, int nrem, int KD, int KP,
+                  orc_tuple* tbuf, slot_t* dbuf, slot_t* pbuf, sol_t* tmp, int32_t* zout, int* order)
 {
     const int m = I->m;
     int kreg = op == 1 ? 2 : op == 2 ? 3 : m;
@@ -622,6 +622,7 @@ static int repair(const orc_inst* I, int op, sol_t* S, int* rem, int nrem, int K
         sol_insert(S, &best_t, m, tmp);
         sol_copy(S, tmp, m);
         *zout = (int32_t)best_c1;
+        if (order) order[nrem - nleft] = left[best_i];
         /* keep the removal-list order of the customers still waiting */
         memmove(left + best_i, left + best_i + 1, (size_t)(nleft - best_i - 1) * sizeof(int));
         --nleft;
@@ -649,6 +650,23 @@ static int roulette(const double* w, int nops, uint32_t mask, double u)
     return last;
 }
 
+/* Slots per removed customer under a budget of tuples per iteration:
+ * T_c = max(1, B / (q(q+1)/2)) tuples for each of the q(q+1)/2 customer
+ * evaluations of a repair, K_D = max(1, floor(sqrt(T_c))) drop slots and
+ * K_P = max(1, T_c / K_D) pickup slots per drop; B = 0 means every slot. */
+static void budget_split(int budget, int nrem, int* KD, int* KP)
+{
+    *KD = 0;
+    *KP = 0;
+    if (budget <= 0) return;
+    long long tc = (long long)budget / ((long long)nrem * (nrem + 1) / 2);
+    if (tc < 1) tc = 1;
+    *KD = (int)floor(sqrt((double)tc));
+    if (*KD < 1) *KD = 1;
+    *KP = (int)(tc / *KD);
+    if (*KP < 1) *KP = 1;
+}
+
 void orc_alns_qrange(int n, int* q_min, int* q_max)
 {
     int qmax = n / 20;              /* floor(0.05 n) */
@@ -661,13 +679,73 @@ void orc_alns_qrange(int n, int* q_min, int* q_max)
 
 typedef struct {
     sol_t S, B;
-    int32_t z, zb;
-    double T, T_init;
-    double wD[ND], wR[NR];
-    long long sD[ND], sR[NR];
-    int aD[ND], aR[NR];
-    int stag;
+    orc_alns_chain k;   /* the scalars Algorithm 1 keeps per chain */
 } chain_t;
+
+/* Algorithm 1 after the repair of iteration it (0-based) of one chain:
+ * attempts of the two chosen operators, the acceptance test (an improving
+ * candidate always, a new best with the extra sigma1 - sigma2, otherwise
+ * annealing with probability exp(-(z' - z) / T) against the uniform u in
+ * [0, 1)), cooling, the stagnation counter and the gated reheat
+ * (Section 4.2.4), and the weight update every tau iterations (Section 4.2.1,
+ * adaptive scoring): w = max(w_min, (1 - r) w + r s / a), unchanged when an
+ * operator had no attempt.  A failed repair (repaired = 0) is not accepted.
+ * Returns 0 rejected, 1 improving, 2 new best, 3 accepted by annealing. */
+int32_t orc_alns_update(const orc_alns_params* P, orc_alns_chain* c, int32_t di, int32_t ri, int32_t repaired,
+                        int32_t zn, double u, int64_t it)
+{
+    int accepted = 0;
+    c->aD[di]++;
+    c->aR[ri]++;
+    if (repaired) {
+        if (zn < c->z) {
+            c->z = zn;
+            c->sD[di] += P->sigma2;
+            c->sR[ri] += P->sigma2;
+            accepted = 1;
+            if (zn < c->zb) {
+                c->zb = zn;
+                c->sD[di] += P->sigma1 - P->sigma2;
+                c->sR[ri] += P->sigma1 - P->sigma2;
+                c->stag = 0;
+                accepted = 2;
+            }
+        } else {
+            const double pacc = orc_det_exp(-((double)zn - (double)c->z) / c->T);
+            if (u < pacc) {
+                c->z = zn;
+                c->sD[di] += P->sigma3;
+                c->sR[ri] += P->sigma3;
+                accepted = 3;
+            }
+        }
+    }
+    c->T = P->alpha * c->T;
+    c->stag += 1;
+    if (c->stag >= P->stag_limit && c->T < P->gate * c->T_init) {
+        c->T = P->reheat * P->T0 * (double)c->zb;
+        c->stag = 0;
+    }
+    if ((it + 1) % P->tau == 0) {
+        for (int i = 0; i < ND; ++i) {
+            if (c->aD[i] > 0) {
+                double w = (1.0 - P->r) * c->wD[i] + P->r * ((double)c->sD[i] / (double)c->aD[i]);
+                c->wD[i] = w > P->w_min ? w : P->w_min;
+            }
+            c->sD[i] = 0;
+            c->aD[i] = 0;
+        }
+        for (int i = 0; i < NR; ++i) {
+            if (c->aR[i] > 0) {
+                double w = (1.0 - P->r) * c->wR[i] + P->r * ((double)c->sR[i] / (double)c->aR[i]);
+                c->wR[i] = w > P->w_min ? w : P->w_min;
+            }
+            c->sR[i] = 0;
+            c->aR[i] = 0;
+        }
+    }
+    return accepted;
+}
 
 /* chain0: the first chain's index in the random-draw counters (chains of
  * one instance in a state that holds several instances are numbered on from
@@ -703,121 +781,64 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
         memcpy(c->S.ops, init_ops, (size_t)c->S.L * sizeof(uint16_t));
         memcpy(c->S.rt, init_rt, (size_t)m * sizeof(uint16_t));
         sol_copy(&c->B, &c->S, m);
-        sol_eval(I, &c->S, &c->z, NULL);
-        c->zb = c->z;
-        c->T = P->T0 * (double)c->zb;
-        c->T_init = c->T;
-        for (int i = 0; i < ND; ++i) c->wD[i] = 1.0;
-        for (int i = 0; i < NR; ++i) c->wR[i] = 1.0;
+        sol_eval(I, &c->S, &c->k.z, NULL);
+        c->k.zb = c->k.z;
+        c->k.T = P->T0 * (double)c->k.zb;
+        c->k.T_init = c->k.T;
+        for (int i = 0; i < ND; ++i) c->k.wD[i] = 1.0;
+        for (int i = 0; i < NR; ++i) c->k.wR[i] = 1.0;
     }
     for (int64_t it = 0; it < iterations; ++it) {
         for (int ch = 0; ch < chains; ++ch) {
             chain_t* c = &C[ch];
             const uint32_t u_it = (uint32_t)it, u_ch = chain0 + (uint32_t)ch;
-            const int di = roulette(c->wD, ND, dmask, unit_d(adraw(seed, 0, u_it, u_ch)));
-            const int ri = roulette(c->wR, NR, rmask, unit_d(adraw(seed, 1, u_it, u_ch)));
+            const int di = roulette(c->k.wD, ND, dmask, unit_d(adraw(seed, 0, u_it, u_ch)));
+            const int ri = roulette(c->k.wR, NR, rmask, unit_d(adraw(seed, 1, u_it, u_ch)));
             const int q = q_min + uint_below(adraw(seed, 2, u_it, u_ch), q_max - q_min + 1);
-            c->aD[di]++;
-            c->aR[ri]++;
-            int nrem = destroy(I, di, &c->S, c->z, q, q_min, seed, u_it, u_ch, 0, rem, &tmp, gone);
+            int nrem = destroy(I, di, &c->S, c->k.z, q, q_min, seed, u_it, u_ch, 0, rem, &tmp, gone);
             memset(gone, 0, (size_t)n + 1);
             for (int i = 0; i < nrem; ++i) gone[rem[i]] = 1;
             sol_remove(&c->S, gone, m, &work);
             memset(gone, 0, (size_t)n + 1);
-            int KD = 0, KP = 0;
-            if (P->tuple_budget > 0) {
-                long long tc = (long long)P->tuple_budget / ((long long)nrem * (nrem + 1) / 2);
-                if (tc < 1) tc = 1;
-                KD = (int)floor(sqrt((double)tc));
-                if (KD < 1) KD = 1;
-                KP = (int)(tc / KD);
-                if (KP < 1) KP = 1;
-            }
+            int KD, KP;
+            budget_split(P->tuple_budget, nrem, &KD, &KP);
             int32_t zn = INT32_MAX;
-            int okr = repair(I, ri, &work, rem, nrem, KD, KP, tbuf, dbuf, pbuf, &tmp2, &zn);
-            int accepted = 0;
-            if (okr) {
-                if (zn < c->z) {
-                    sol_copy(&c->S, &work, m);
-                    c->z = zn;
-                    c->sD[di] += P->sigma2;
-                    c->sR[ri] += P->sigma2;
-                    accepted = 1;
-                    if (zn < c->zb) {
-                        sol_copy(&c->B, &work, m);
-                        c->zb = zn;
-                        c->sD[di] += P->sigma1 - P->sigma2;
-                        c->sR[ri] += P->sigma1 - P->sigma2;
-                        c->stag = 0;
-                        accepted = 2;
-                    }
-                } else {
-                    const double u = unit_d(adraw(seed, 8, u_it, u_ch));
-                    const double pacc = orc_det_exp(-((double)zn - (double)c->z) / c->T);
-                    if (u < pacc) {
-                        sol_copy(&c->S, &work, m);
-                        c->z = zn;
-                        c->sD[di] += P->sigma3;
-                        c->sR[ri] += P->sigma3;
-                        accepted = 3;
-                    }
-                }
-            }
-            c->T = P->alpha * c->T;
-            c->stag += 1;
-            if (c->stag >= P->stag_limit && c->T < P->gate * c->T_init) {
-                c->T = P->reheat * P->T0 * (double)c->zb;
-                c->stag = 0;
-            }
-            if ((it + 1) % P->tau == 0) {
-                for (int i = 0; i < ND; ++i) {
-                    if (c->aD[i] > 0) {
-                        double w = (1.0 - P->r) * c->wD[i] + P->r * ((double)c->sD[i] / (double)c->aD[i]);
-                        c->wD[i] = w > P->w_min ? w : P->w_min;
-                    }
-                    c->sD[i] = 0;
-                    c->aD[i] = 0;
-                }
-                for (int i = 0; i < NR; ++i) {
-                    if (c->aR[i] > 0) {
-                        double w = (1.0 - P->r) * c->wR[i] + P->r * ((double)c->sR[i] / (double)c->aR[i]);
-                        c->wR[i] = w > P->w_min ? w : P->w_min;
-                    }
-                    c->sR[i] = 0;
-                    c->aR[i] = 0;
-                }
-            }
+            int okr = repair(I, ri, &work, rem, nrem, KD, KP, tbuf, dbuf, pbuf, &tmp2, &zn, NULL);
+            const double u = unit_d(adraw(seed, 8, u_it, u_ch));
+            const int accepted = orc_alns_update(P, &c->k, di, ri, okr, zn, u, it);
+            if (accepted) sol_copy(&c->S, &work, m);
+            if (accepted == 2) sol_copy(&c->B, &work, m);
             if (trace) {
                 int64_t* tr = trace + ((size_t)ch * (size_t)iterations + (size_t)it) * 4;
                 tr[0] = okr ? zn : INT32_MAX;
-                tr[1] = c->z;
-                tr[2] = c->zb;
+                tr[1] = c->k.z;
+                tr[2] = c->k.zb;
                 tr[3] = di | (ri << 8) | (accepted << 16) | ((int64_t)nrem << 24);
             }
             /* periodic local search on the current solution (Section 4.2.6):
              * repositioning before relocation when both fall due */
             int ls_any = 0;
             if (P->ls_repos_interval > 0 && (it + 1) % P->ls_repos_interval == 0)
-                ls_any |= local_search(I, 0, P->ls_budget, &c->S, &c->z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
+                ls_any |= local_search(I, 0, P->ls_budget, &c->S, &c->k.z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
             if (P->ls_reloc_interval > 0 && (it + 1) % P->ls_reloc_interval == 0)
-                ls_any |= local_search(I, 1, P->ls_budget, &c->S, &c->z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
-            if (ls_any && c->z < c->zb) {
+                ls_any |= local_search(I, 1, P->ls_budget, &c->S, &c->k.z, &tmp, &tmp2, dbuf, pbuf, rem, gone);
+            if (ls_any && c->k.z < c->k.zb) {
                 sol_copy(&c->B, &c->S, m);
-                c->zb = c->z;
-                c->stag = 0;
+                c->k.zb = c->k.z;
+                c->k.stag = 0;
             }
             memset(gone, 0, (size_t)n + 1);
         }
         if (P->import_interval > 0 && (it + 1) % P->import_interval == 0) {
             int bc = 0;
             for (int ch = 1; ch < chains; ++ch)
-                if (C[ch].zb < C[bc].zb) bc = ch;
+                if (C[ch].k.zb < C[bc].k.zb) bc = ch;
             for (int ch = 0; ch < chains; ++ch) {
-                if (C[ch].zb > C[bc].zb) {
+                if (C[ch].k.zb > C[bc].k.zb) {
                     sol_copy(&C[ch].B, &C[bc].B, m);
-                    C[ch].zb = C[bc].zb;
+                    C[ch].k.zb = C[bc].k.zb;
                     sol_copy(&C[ch].S, &C[bc].B, m);
-                    C[ch].z = C[bc].zb;
+                    C[ch].k.z = C[bc].k.zb;
                 }
             }
         }
@@ -826,8 +847,8 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
     for (int ch = 0; ch < chains; ++ch) {
         if (best_ops) memcpy(best_ops + (size_t)ch * 2 * n, C[ch].B.ops, (size_t)C[ch].B.L * sizeof(uint16_t));
         if (best_rt) memcpy(best_rt + (size_t)ch * m, C[ch].B.rt, (size_t)m * sizeof(uint16_t));
-        if (best_mk) best_mk[ch] = C[ch].zb;
-        if (C[ch].zb < best) best = C[ch].zb;
+        if (best_mk) best_mk[ch] = C[ch].k.zb;
+        if (C[ch].k.zb < best) best = C[ch].k.zb;
         sol_free(&C[ch].S);
         sol_free(&C[ch].B);
     }
@@ -907,4 +928,76 @@ int32_t orc_alns_local_search(const orc_inst* I, int32_t kind, int32_t budget, i
     memcpy(out_rt, S.rt, (size_t)m * sizeof(uint16_t));
     sol_free(&S); sol_free(&base); sol_free(&cand);
     return rc;
+}
+
+
+static void sol_load(sol_t* S, const uint16_t* ops, const uint16_t* rt_end, int m)
+{
+    S->L = m > 0 ? rt_end[m - 1] : 0;
+    memcpy(S->ops, ops, (size_t)S->L * sizeof(uint16_t));
+    memcpy(S->rt, rt_end, (size_t)m * sizeof(uint16_t));
+}
+
+/* Insertion candidates of customer c against a partial solution, in ranked
+ * order (drop slots by detour, then for each the pickup slots by detour on
+ * the route after the drop went in); K_D = K_P = 0 lists every slot pair.
+ * Writes the tuples to out (capacity (2n+m+2)^2 when unbounded) and returns
+ * their number. */
+int32_t orc_alns_enumerate(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end, int32_t c, int32_t KD,
+                           int32_t KP, orc_tuple* out)
+{
+    const int n = I->n, m = I->m;
+    sol_t S;
+    sol_alloc(&S, n, m);
+    sol_load(&S, ops, rt_end, m);
+    const int maxslots = 2 * n + m + 2;
+    slot_t* dbuf = malloc((size_t)maxslots * sizeof(slot_t));
+    slot_t* pbuf = malloc((size_t)maxslots * sizeof(slot_t));
+    const int T = enumerate_tuples(I, &S, c, KD, KP, out, dbuf, pbuf);
+    free(dbuf);
+    free(pbuf);
+    sol_free(&S);
+    return T;
+}
+
+/* One repair (op 0 greedy, 1 regret-2, 2 regret-3, 3 regret-m) of a partial
+ * solution missing the nrem customers of rem (in removal order), with K_D /
+ * K_P slots per customer (0: all).  Writes the completed solution, its
+ * makespan and the customers in the order they were inserted (nullable).
+ * Returns 1, or 0 when some customer had no feasible insertion. */
+int32_t orc_alns_repair(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, const int32_t* rem,
+                        int32_t nrem, int32_t KD, int32_t KP, uint16_t* out_ops, uint16_t* out_rt, int32_t* z,
+                        int32_t* order)
+{
+    const int n = I->n, m = I->m;
+    sol_t S, tmp;
+    sol_alloc(&S, n, m);
+    sol_alloc(&tmp, n, m);
+    sol_load(&S, ops, rt_end, m);
+    const int maxslots = 2 * n + m + 2;
+    slot_t* dbuf = malloc((size_t)maxslots * sizeof(slot_t));
+    slot_t* pbuf = malloc((size_t)maxslots * sizeof(slot_t));
+    orc_tuple* tbuf = malloc((size_t)maxslots * (size_t)maxslots * sizeof(orc_tuple));
+    int* rr = malloc((size_t)(nrem + 1) * sizeof(int));
+    int* oo = malloc((size_t)(nrem + 1) * sizeof(int));
+    for (int i = 0; i < nrem; ++i) rr[i] = rem[i];
+    *z = INT32_MAX;
+    const int ok = repair(I, op, &S, rr, nrem, KD, KP, tbuf, dbuf, pbuf, &tmp, z, oo);
+    if (order)
+        for (int i = 0; i < nrem; ++i) order[i] = ok ? oo[i] : 0;
+    memcpy(out_ops, S.ops, (size_t)S.L * sizeof(uint16_t));
+    memcpy(out_rt, S.rt, (size_t)m * sizeof(uint16_t));
+    free(dbuf); free(pbuf); free(tbuf); free(rr); free(oo);
+    sol_free(&S);
+    sol_free(&tmp);
+    return ok;
+}
+
+/* Slot counts of the budget split (see budget_split). */
+void orc_alns_budget_split(int32_t budget, int32_t nrem, int32_t* KD, int32_t* KP)
+{
+    int a, b;
+    budget_split(budget, nrem, &a, &b);
+    *KD = a;
+    *KP = b;
 }

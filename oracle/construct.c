@@ -34,8 +34,8 @@
  *    (10 (W_max - W_min) >= W_max), move from v_max to v_min the customer
  *    with 0 < w_c < W_max - W_min closest to half the gap (least
  *    |W_max - W_min - 2 w_c|, lowest index on ties); stop when no customer
- *    qualifies.  Every move lowers sum W_v^2, so the loop ends; it is also
- *    cut at n m' moves;
+ *    qualifies.  Every move lowers sum W_v^2, so the loop ends (no move
+ *    limit: the passage gives only the 10% stopping rule);
  *  - per-vehicle nearest neighbour: vehicle v serves its sector alone,
  *    starting at the depot at time 0 with at most cap_v resources out at a
  *    time (cap_v = k under FULL_START; under MIN_PRELOAD R is split as
@@ -162,8 +162,11 @@ int32_t orc_cons_sectors(const orc_inst* I, int32_t* sector0, int32_t* sector)
     int64_t W[64];
     for (int v = 0; v < mv; ++v) W[v] = 0;
     for (int c = 1; c <= n; ++c) W[sector[c]] += 2 * dd(I, 0, c) + I->p[c];
+    /* Each move takes w with 0 < w < gap from the heaviest to the lightest
+     * sector, so the sum of squared workloads falls by 2 w (gap - w) > 0: an
+     * integer that falls at every move, hence the loop ends by itself. */
     int moves = 0;
-    while (moves < n * mv) {
+    for (;;) {
         int hi = 0, lo = 0;
         for (int v = 1; v < mv; ++v) {
             if (W[v] > W[hi]) hi = v;

@@ -89,6 +89,33 @@ typedef struct {
     int32_t ls_budget;         /* tuples per local-search pass (> 0) */
 } orc_alns_params;
 
+/* The scalars Algorithm 1 keeps per chain: current and best makespan,
+ * temperature and its initial value, operator weights (6 destroy, 4 repair),
+ * scores and attempts of the current period, and the stagnation counter. */
+typedef struct {
+    int32_t z, zb;
+    double T, T_init;
+    double wD[6], wR[4];
+    int64_t sD[6], sR[4];
+    int32_t aD[6], aR[4];
+    int32_t stag;
+} orc_alns_chain;
+
+/* Algorithm 1 after the repair of iteration it (0-based): attempts,
+ * acceptance with the uniform u for the annealing test, scores, cooling,
+ * stagnation and reheat, weights every tau iterations.  Returns 0 rejected,
+ * 1 improving, 2 new best, 3 accepted by annealing. */
+int32_t orc_alns_update(const orc_alns_params* P, orc_alns_chain* c, int32_t di, int32_t ri, int32_t repaired,
+                        int32_t zn, double u, int64_t it);
+/* Insertion candidates of customer c against a partial solution (ranked). */
+int32_t orc_alns_enumerate(const orc_inst* I, const uint16_t* ops, const uint16_t* rt_end, int32_t c, int32_t KD,
+                           int32_t KP, orc_tuple* out);
+/* One repair of a partial solution; returns 1, or 0 if a customer could not
+ * be inserted. */
+int32_t orc_alns_repair(const orc_inst* I, int32_t op, const uint16_t* ops, const uint16_t* rt_end, const int32_t* rem,
+                        int32_t nrem, int32_t KD, int32_t KP, uint16_t* out_ops, uint16_t* out_rt, int32_t* z,
+                        int32_t* order);
+void orc_alns_budget_split(int32_t budget, int32_t nrem, int32_t* KD, int32_t* KP);
 double orc_det_exp(double x);
 void orc_alns_qrange(int n, int* q_min, int* q_max);
 int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,

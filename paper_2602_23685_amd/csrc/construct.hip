@@ -214,7 +214,9 @@ __device__ void balance(const InstDev& I, const Dist<DT>& d, const int32_t* P, c
     for (int c = threadIdx.x + 1; c <= n; c += kCT)
         atomicAdd(reinterpret_cast<unsigned long long*>(&W[ws.aux[c]]), (unsigned long long)(2ll * d(0, c) + P[c]));
     __syncthreads();
-    for (int moves = 0; moves < n * mv; ++moves) {
+    // Every move lowers the sum of squared workloads by 2 w (gap - w) > 0
+    // (0 < w < gap), so the loop ends without a move limit.
+    for (;;) {
         if (threadIdx.x == 0) {
             int hi = 0, lo = 0;
             for (int v = 1; v < mv; ++v) {

@@ -31,6 +31,31 @@ def test_h4_hint_tie_break(orc):
     assert list(r["rt_end"]) == [1, 2] and list(r["ops"]) == [3, 2]
 
 
+def test_hint_rotation_three_vehicles(orc):
+    """Ties go to the first vehicle counting upward (cyclically) from the
+    hint vehicle.  Line: depot 0, c1 at -4, c2 at 6 (d01 = 4, d02 = 6,
+    d12 = 10), p = (3, 5), m = 3, k = 1, R = 3, MIN_PRELOAD.  Priorities put
+    the ops in the order D1, D2, P1, P2; hints floor(3 alpha) = 0, 1, 0, 0 for
+    D1, P1, D2, P2.
+      D1: all three vehicles tie at 4, hint 0 -> v0 (drop at 4, ready 7);
+      D2: v0 holds its one resource and may not load another; v1 and v2 tie
+          at 6, hint 0 -> v1 (the next after v0; counting down would give v2);
+          ready 11;
+      P1: v0 max(4, 7) = 7, v1 max(16, 7) = 16, v2 max(4, 7) = 7; hint 1,
+          tie v0 / v2 -> v2 (after v1 comes v2, then v0);
+      P2: v2 is full; v0 max(14, 11) = 14, v1 max(6, 11) = 11 -> v1.
+    Returns: v0 4 + 4 = 8, v1 11 + 6 = 17, v2 7 + 4 = 11; z = 17."""
+    x = np.array([0, -4, 6])
+    d = np.abs(x[:, None] - x[None, :]).astype(np.int32)
+    inst = synth.instance_from_matrix(d, np.array([0, 3, 5], np.int32), m=3, k=1, R=3)
+    prio = np.array([0.1, 0.8, 0.2, 0.9], np.float32)
+    hint = np.array([0.1, 0.5, 0.1, 0.1], np.float32)
+    r = orc.decode(inst, prio, hint, want_ops=True)
+    assert (r["fitness"], r["makespan"], r["unscheduled"]) == (17, 17, 0)
+    assert list(r["rt_end"]) == [1, 3, 4]
+    assert list(r["ops"]) == [2, 4, 5, 3]
+
+
 def test_single_vehicle_closed_form(orc):
     """m = 1 with room for everything: pass 1 takes ops in priority order,
     skipping pickups whose drop comes later; pass 2 takes those pickups in
