@@ -389,6 +389,17 @@ int brkga_state_step(brkga_state* st, int32_t generations, int32_t use_graph, vo
 int brkga_state_get(const brkga_state* st, int64_t* generations, int64_t* best_fitness, float* best_prio,
                     float* best_hint, float* prio, float* hint, void* stream);
 int brkga_state_destroy(brkga_state* st);
+/* Checkpoint of a BRKGA state: the populations to be decoded next, every
+ * population's best chromosome and fitness so far and the generation counter.
+ * buf (host, caller-owned) receives it; with buf = NULL only *bytes (host) is
+ * set to the size it needs.  Waits for the stream, then copies (synchronous).
+ * EINVAL if capacity is below that size. */
+int brkga_state_save(const brkga_state* st, void* buf, int64_t capacity, int64_t* bytes, void* stream);
+/* Restores a checkpoint into a state created on the same set and instances
+ * with the same Np, elite and mutant counts, rho_e and seed (EINVAL
+ * otherwise, or when bytes is not the checkpoint's size): generations run
+ * after the load equal those the saved state would have run.  Synchronous. */
+int brkga_state_load(brkga_state* st, const void* buf, int64_t bytes, void* stream);
 
 /* ---- ALNS (Section 4.2) ----------------------------------------------------
  * alns_params: the hyper-parameters of Table 2 (Section 4.2.7) plus this
@@ -483,6 +494,23 @@ int alns_get_best(const alns_state* st, int32_t chain, int32_t* mk, uint16_t* op
 int alns_get_state(const alns_state* st, int64_t* iterations, int64_t* evals, int32_t* z, int32_t* zb, double* T,
                    double* wD, double* wR);
 int alns_state_destroy(alns_state* st);
+/* Checkpoint of every chain's state in Algorithm 1 (Section 4.2): current
+ * and best solutions and makespans, temperature and its initial value,
+ * operator weights, the scores and attempts of the running weight period,
+ * the stagnation counter, plus the evaluation count and the iteration
+ * counter (the random draws are keyed by the iteration, so nothing else is
+ * needed to continue).  buf (host, caller-owned) receives it; with buf = NULL
+ * only *bytes (host) is set to the size it needs.  Waits for the stream, then
+ * copies (synchronous).  Not included: the learned proposal's settings,
+ * traces and records, which stay as the loading state has them.  EINVAL if
+ * capacity is below that size. */
+int alns_state_save(const alns_state* st, void* buf, int64_t capacity, int64_t* bytes, void* stream);
+/* Restores a checkpoint into a state created on the same set with the same
+ * instances, chains per instance, parameters and seed (EINVAL otherwise, or
+ * when bytes is not the checkpoint's size).  k iterations, a save, a load
+ * into a fresh state and k' more iterations give the same chains, bit for
+ * bit, as k + k' iterations without the checkpoint.  Synchronous. */
+int alns_state_load(alns_state* st, const void* buf, int64_t bytes, void* stream);
 /* The last phase of the initial construction (Section 4.2, "Initial Solution
  * Construction": relocation and pickup reassignment until nothing improves),
  * before the first iteration: rounds of the periodic local searches

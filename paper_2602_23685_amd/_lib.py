@@ -56,6 +56,10 @@ SIGNATURES = {
     "alns_get_best": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
     "alns_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "alns_state_destroy": (C.c_int, [_P]),
+    "alns_state_save": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "alns_state_load": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "brkga_state_save": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "brkga_state_load": (C.c_int, [_P, _P, C.c_int64, _P]),
     "brkga_state_create": (C.c_int, [C.POINTER(C.c_void_p), _P, _I32, _P, _I32, _I32, _I32, C.c_double, _U64,
                                      _P, _P, _P]),
     "brkga_state_step": (C.c_int, [_P, _I32, _I32, _P]),
@@ -335,6 +339,19 @@ def vrprpd_construct(S: InstanceSet, heuristic, inst=None, stream=None):
     return ops, rt
 
 
+def _save(fn, handle, stream):
+    n = C.c_int64()
+    _check(fn(handle, None, 0, C.byref(n), _stream(stream)))
+    buf = C.create_string_buffer(n.value)
+    _check(fn(handle, buf, n.value, C.byref(n), _stream(stream)))
+    return buf.raw[:n.value]
+
+
+def _load(fn, handle, blob, stream):
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _check(fn(handle, buf, len(blob), _stream(stream)))
+
+
 class BrkgaState:
     """Batched BRKGA over several instances (brkga_state_*)."""
 
@@ -359,6 +376,14 @@ class BrkgaState:
         _check(load().brkga_state_get(self.handle, None, f.ctypes.data, _dptr(bp), _dptr(bh), None, None,
                                       _stream(stream)))
         return f, bp, bh
+
+    def save(self, stream=None):
+        """Checkpoint (bytes) of the populations, bests and generation count."""
+        return _save(load().brkga_state_save, self.handle, stream)
+
+    def load(self, blob, stream=None):
+        """Continue from a checkpoint of a state with the same configuration."""
+        _load(load().brkga_state_load, self.handle, blob, stream)
 
     def population(self, stream=None):
         p = torch.empty((self.P * self.Np, self.stride), dtype=torch.float32, device="cuda")
@@ -448,6 +473,15 @@ class AlnsState:
         _check(load().alns_get_state(self.handle, C.byref(it), C.byref(ev), z.ctypes.data, zb.ctypes.data,
                                      T.ctypes.data, wD.ctypes.data, wR.ctypes.data))
         return dict(iterations=it.value, evals=ev.value, z=z, zb=zb, T=T, wD=wD, wR=wR)
+
+    def save(self, stream=None):
+        """Checkpoint (bytes) of every chain's search state and the
+        iteration counter."""
+        return _save(load().alns_state_save, self.handle, stream)
+
+    def load(self, blob, stream=None):
+        """Continue from a checkpoint of a state with the same configuration."""
+        _load(load().alns_state_load, self.handle, blob, stream)
 
     def set_graph(self, enable):
         """Replay one captured iteration (True, the default) or launch every

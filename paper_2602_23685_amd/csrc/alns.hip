@@ -23,6 +23,7 @@
 #include "philox.h"
 #include "scan.h"
 #include "sweep.h"
+#include "ckpt.h"
 
 namespace vrprpd {
 
@@ -1702,6 +1703,7 @@ struct alns_state {
     hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};        // per local-search mask
     hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};    // rebuilt after any change of the launch arguments
     int lds_ls = 0;
+    std::vector<int32_t> inst_ids;     // host copy of the instances (checkpoint check)
 };
 
 namespace vrprpd {
@@ -1766,6 +1768,9 @@ static void qrange(const alns_params& P, int n, int* qmin, int* qmax)
 extern "C" int alns_state_destroy(alns_state* s)
 {
     if (!s) return VRPRPD_OK;
+    // graphs of this state may still be replaying on the caller's streams:
+    // let the device finish before their executables and buffers go
+    (void)hipDeviceSynchronize();
     for (int i = 0; i < 4; ++i) {
         if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
         if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
@@ -1812,6 +1817,7 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
     auto* s = new alns_state();
     s->set = set;
     s->n_inst = n_inst;
+    s->inst_ids.assign(inst_ids, inst_ids + n_inst);
     s->cpi = chains_per_inst;
     s->dist16 = set->dist16;
     AlnsDev& d = s->d;
@@ -2439,5 +2445,99 @@ extern "C" int alns_get_learned(const alns_state* s, uint16_t* feat, int32_t* ca
         VRP_HIP(hipMemcpyAsync(cand_rem, d.cand_rem, (size_t)d.C * d.K * d.Q * 4, hipMemcpyDeviceToDevice, st));
     if (cand_cnt) VRP_HIP(hipMemcpyAsync(cand_cnt, d.cand_cnt, (size_t)d.C * d.K * 4, hipMemcpyDeviceToDevice, st));
     if (chosen) VRP_HIP(hipMemcpyAsync(chosen, d.chosen, (size_t)d.C * 4, hipMemcpyDeviceToDevice, st));
+    return VRPRPD_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+namespace vrprpd {
+
+struct AlnsCkptHead {
+    char magic[8];           // "VRPALNS1"
+    int32_t C, N, M, Q, TPC, n_inst, cpi, dist16;
+    uint64_t seed;
+    int64_t it;
+    alns_params prm;
+};
+
+static bool same_params(const alns_params& a, const alns_params& b)
+{
+    return a.T0 == b.T0 && a.alpha == b.alpha && a.reheat == b.reheat && a.gate == b.gate &&
+           a.stag_limit == b.stag_limit && a.tau == b.tau && a.r == b.r && a.sigma1 == b.sigma1 &&
+           a.sigma2 == b.sigma2 && a.sigma3 == b.sigma3 && a.w_min == b.w_min && a.q_min == b.q_min &&
+           a.q_max == b.q_max && a.tuple_budget == b.tuple_budget && a.import_interval == b.import_interval &&
+           a.op_mask == b.op_mask && a.ls_repos_interval == b.ls_repos_interval &&
+           a.ls_reloc_interval == b.ls_reloc_interval && a.ls_budget == b.ls_budget;
+}
+
+// Everything an iteration reads from the previous one: both solutions of
+// every chain, makespans, temperatures, operator weights, the scores and
+// attempts of the running period, stagnation, the evaluation count and the
+// device iteration counter; then the chains' instance ids.
+static std::vector<DevField> alns_fields(const alns_state* s)
+{
+    const AlnsDev& d = s->d;
+    const size_t C = (size_t)d.C;
+    return {{d.S_ops, C * 2 * d.N * 2}, {d.S_rt, C * d.M * 2}, {d.B_ops, C * 2 * d.N * 2}, {d.B_rt, C * d.M * 2},
+            {d.z, C * 4}, {d.zb, C * 4}, {d.T, C * 8}, {d.T_init, C * 8}, {d.wD, kND * C * 8},
+            {d.wR, kNR * C * 8}, {d.sD, kND * C * 8}, {d.sR, kNR * C * 8}, {d.aD, kND * C * 4},
+            {d.aR, kNR * C * 4}, {d.stag, C * 4}, {d.evals, 8}, {d.it_dev, 4}};
+}
+
+static AlnsCkptHead alns_head(const alns_state* s)
+{
+    AlnsCkptHead h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "VRPALNS1", 8);
+    h.C = s->d.C;
+    h.N = s->d.N;
+    h.M = s->d.M;
+    h.Q = s->d.Q;
+    h.TPC = s->d.TPC;
+    h.n_inst = s->n_inst;
+    h.cpi = s->cpi;
+    h.dist16 = s->dist16;
+    h.seed = s->d.seed;
+    h.it = s->it;
+    h.prm = s->d.prm;
+    return h;
+}
+
+}  // namespace vrprpd
+
+extern "C" int alns_state_save(const alns_state* s, void* buf, int64_t capacity, int64_t* bytes, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || (!buf && !bytes)) return set_error(VRPRPD_EINVAL, "alns_state_save: bad arguments");
+    std::vector<unsigned char> head(sizeof(AlnsCkptHead) + s->inst_ids.size() * sizeof(int32_t));
+    const AlnsCkptHead h = alns_head(s);
+    std::memcpy(head.data(), &h, sizeof h);
+    std::memcpy(head.data() + sizeof h, s->inst_ids.data(), s->inst_ids.size() * sizeof(int32_t));
+    return ckpt_save(head.data(), head.size(), alns_fields(s), buf, capacity, bytes,
+                     reinterpret_cast<hipStream_t>(stream), "alns_state_save");
+}
+
+extern "C" int alns_state_load(alns_state* s, const void* buf, int64_t bytes, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || !buf || bytes < (int64_t)sizeof(AlnsCkptHead))
+        return set_error(VRPRPD_EINVAL, "alns_state_load: bad arguments");
+    AlnsCkptHead h;
+    std::memcpy(&h, buf, sizeof h);
+    const AlnsCkptHead mine = alns_head(s);
+    if (std::memcmp(h.magic, "VRPALNS1", 8) != 0)
+        return set_error(VRPRPD_EINVAL, "alns_state_load: not an ALNS checkpoint");
+    if (h.C != mine.C || h.N != mine.N || h.M != mine.M || h.Q != mine.Q || h.TPC != mine.TPC ||
+        h.n_inst != mine.n_inst || h.cpi != mine.cpi || h.dist16 != mine.dist16 || h.seed != mine.seed ||
+        !same_params(h.prm, mine.prm))
+        return set_error(VRPRPD_EINVAL, "alns_state_load: the checkpoint was taken from a state with other "
+                                        "instances, chains, seed or parameters");
+    const size_t ids_bytes = s->inst_ids.size() * sizeof(int32_t);
+    if (bytes < (int64_t)(sizeof h + ids_bytes) ||
+        std::memcmp(static_cast<const unsigned char*>(buf) + sizeof h, s->inst_ids.data(), ids_bytes) != 0)
+        return set_error(VRPRPD_EINVAL, "alns_state_load: the checkpoint's chains belong to other instances");
+    const int rc = ckpt_load(buf, bytes, sizeof h + ids_bytes, alns_fields(s), reinterpret_cast<hipStream_t>(stream),
+                             "alns_state_load");
+    if (rc) return rc;
+    s->it = h.it;
     return VRPRPD_OK;
 }

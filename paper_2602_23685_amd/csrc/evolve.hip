@@ -17,6 +17,7 @@
 // fresh U(0,1) individuals.
 #include "common.h"
 #include "philox.h"
+#include "ckpt.h"
 
 namespace vrprpd {
 
@@ -462,6 +463,7 @@ struct brkga_state {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::vector<void*> allocs;
+    std::vector<int32_t> inst_ids;   // host copy (checkpoint check)
 };
 
 namespace vrprpd {
@@ -490,6 +492,8 @@ static int brkga_generation(brkga_state* s, int from, hipStream_t st)
 extern "C" int brkga_state_destroy(brkga_state* s)
 {
     if (!s) return VRPRPD_OK;
+    // graphs of this state may still be replaying on the caller's streams
+    (void)hipDeviceSynchronize();
     for (int i = 0; i < 2; ++i) {
         if (s->gexec[i]) (void)hipGraphExecDestroy(s->gexec[i]);
         if (s->graph[i]) (void)hipGraphDestroy(s->graph[i]);
@@ -527,6 +531,7 @@ extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int3
     s->nm = n_mutant;
     s->thr = (uint32_t)std::floor(rho_e * 16777216.0);
     s->seed = seed;
+    s->inst_ids.assign(inst_ids, inst_ids + n_inst);
     s->stride = 2 * (int64_t)set->n_max;
     const int64_t B = (int64_t)n_inst * Np;
     hipError_t e = hipSuccess;
@@ -636,5 +641,80 @@ extern "C" int brkga_state_get(const brkga_state* s, int64_t* generations, int64
         VRP_HIP(hipStreamSynchronize(st));
         VRP_HIP(hipMemcpy(best_fitness, s->best_fit, s->P * 8, hipMemcpyDeviceToHost));
     }
+    return VRPRPD_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+namespace vrprpd {
+
+struct BrkgaCkptHead {
+    char magic[8];           // "VRPBRKG1"
+    int32_t P, Np, ne, nm;
+    uint32_t thr, pad;
+    uint64_t seed;
+    int64_t stride, generations;
+};
+
+// The population to decode next, the best chromosome and fitness of every
+// population so far, and the device generation counter.
+static std::vector<DevField> brkga_fields(const brkga_state* s)
+{
+    const size_t B = (size_t)s->P * s->Np, S = (size_t)s->stride;
+    return {{s->prio[s->cur], B * S * 4}, {s->hint[s->cur], B * S * 4}, {s->best_fit, (size_t)s->P * 8},
+            {s->best_prio, (size_t)s->P * S * 4}, {s->best_hint, (size_t)s->P * S * 4}, {s->gen_dev, 4}};
+}
+
+static BrkgaCkptHead brkga_head(const brkga_state* s)
+{
+    BrkgaCkptHead h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "VRPBRKG1", 8);
+    h.P = s->P;
+    h.Np = s->Np;
+    h.ne = s->ne;
+    h.nm = s->nm;
+    h.thr = s->thr;
+    h.seed = s->seed;
+    h.stride = s->stride;
+    h.generations = s->generations;
+    return h;
+}
+
+}  // namespace vrprpd
+
+extern "C" int brkga_state_save(const brkga_state* s, void* buf, int64_t capacity, int64_t* bytes, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || (!buf && !bytes)) return set_error(VRPRPD_EINVAL, "brkga_state_save: bad arguments");
+    std::vector<unsigned char> head(sizeof(BrkgaCkptHead) + s->inst_ids.size() * sizeof(int32_t));
+    const BrkgaCkptHead h = brkga_head(s);
+    std::memcpy(head.data(), &h, sizeof h);
+    std::memcpy(head.data() + sizeof h, s->inst_ids.data(), s->inst_ids.size() * sizeof(int32_t));
+    return ckpt_save(head.data(), head.size(), brkga_fields(s), buf, capacity, bytes,
+                     reinterpret_cast<hipStream_t>(stream), "brkga_state_save");
+}
+
+extern "C" int brkga_state_load(brkga_state* s, const void* buf, int64_t bytes, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || !buf || bytes < (int64_t)sizeof(BrkgaCkptHead))
+        return set_error(VRPRPD_EINVAL, "brkga_state_load: bad arguments");
+    BrkgaCkptHead h;
+    std::memcpy(&h, buf, sizeof h);
+    const BrkgaCkptHead mine = brkga_head(s);
+    if (std::memcmp(h.magic, "VRPBRKG1", 8) != 0)
+        return set_error(VRPRPD_EINVAL, "brkga_state_load: not a BRKGA checkpoint");
+    if (h.P != mine.P || h.Np != mine.Np || h.ne != mine.ne || h.nm != mine.nm || h.thr != mine.thr ||
+        h.seed != mine.seed || h.stride != mine.stride)
+        return set_error(VRPRPD_EINVAL, "brkga_state_load: the checkpoint was taken from a state with other "
+                                        "populations, sizes, rho_e or seed");
+    const size_t ids_bytes = s->inst_ids.size() * sizeof(int32_t);
+    if (bytes < (int64_t)(sizeof h + ids_bytes) ||
+        std::memcmp(static_cast<const unsigned char*>(buf) + sizeof h, s->inst_ids.data(), ids_bytes) != 0)
+        return set_error(VRPRPD_EINVAL, "brkga_state_load: the checkpoint's populations belong to other instances");
+    const int rc = ckpt_load(buf, bytes, sizeof h + ids_bytes, brkga_fields(s), reinterpret_cast<hipStream_t>(stream),
+                             "brkga_state_load");
+    if (rc) return rc;
+    s->generations = h.generations;
     return VRPRPD_OK;
 }

@@ -102,3 +102,15 @@ def test_host_argument_checks_of_the_newer_entry_points(lib):
     assert lib.brkga_warm_start_multi(None, 0, 1, None, 2, None, 1, nv, 8, 1, 0, 2, None, None, None) == E
     assert lib.alns_refine(None, 5, None, None) == E
     assert lib.vrprpd_solution_stats(None, 1, None, None, None, None, None, None, None, None) == E
+
+
+def test_checkpoint_argument_checks(lib):
+    """Checkpoints of missing states, and loads of foreign buffers, are
+    refused before any device work."""
+    import paper_2602_23685_amd as P
+    E = P._lib.EINVAL
+    n = C.c_int64()
+    assert lib.alns_state_save(None, None, 0, C.byref(n), None) == E
+    assert lib.alns_state_load(None, None, 0, None) == E
+    assert lib.brkga_state_save(None, None, 0, C.byref(n), None) == E
+    assert lib.brkga_state_load(None, None, 0, None) == E
