@@ -240,6 +240,31 @@ int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, con
                       void* stream);
 
 /*
+ * brkga_decode_eval_noalloc — brkga_decode_eval for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * brkga_decode_eval, bit for bit; it calls no hipMalloc / hipMallocAsync /
+ * hipFree.  Its workspace (op orders, key flags and, with ops_out, schedule
+ * logs) is a fixed device array inside the library of
+ * brkga_decode_noalloc_max_bytes() = 32 MiB, one per GPU, held from the
+ * library's load until the process ends; its address is looked up on the
+ * first call on each device.  A batch whose workspace would exceed it is
+ * rejected with EINVAL (message in vrprpd_last_error()); the workspace of B
+ * chromosomes is about 2 * 2^ceil(log2(2n)) * B bytes, three times that with
+ * ops_out (at n = 1000: up to 8,190 chromosomes, 2,730 with ops_out).
+ * Every call on one GPU uses the same array and leaves its contents behind
+ * (each call writes what it reads before reading it): calls that overlap on
+ * one GPU (two streams, two host threads) race and must be serialised by the
+ * caller.
+ */
+int brkga_decode_eval_noalloc(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
+                              const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
+                              int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
+                              void* stream);
+/* Size in bytes of brkga_decode_eval_noalloc's fixed workspace. */
+int64_t brkga_decode_noalloc_max_bytes(void);
+
+/*
  * brkga_evolve — one BRKGA generation (Section 4.4.3): rank by (fitness,
  * index); children [0, n_elite) copy the ranked elites; [n_elite,
  * n_elite + n_mutant) get fresh U(0,1) genes; the rest take each gene from a

@@ -47,6 +47,8 @@ SIGNATURES = {
     "vrprpd_autotune_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P, _P, _P]),
     "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_decode_eval_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_decode_noalloc_max_bytes": (C.c_int64, []),
     "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
                                _P, _P, _P, _P]),
     "brkga_warm_start": (C.c_int, [_P, _I32, _P, _P, _I32, _I32, _I32, _U64, _I64, _P, _P, _P]),
@@ -236,28 +238,51 @@ def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_b
     return mk, st, top
 
 
-def brkga_decode_eval(S: InstanceSet, prio, hint=None, inst=None, want_ops=False, out=None, stream=None):
-    """Decode B chromosomes (see brkga_decode_eval in vrprpd.h).  prio/hint:
-    [B, stride] float32 device tensors.  Returns dict of device tensors."""
+def _decode_out(S: InstanceSet, B, dev, inst, want_ops):
+    out = dict(fitness=torch.empty(B, dtype=torch.int64, device=dev),
+               makespan=torch.empty(B, dtype=torch.int32, device=dev),
+               unscheduled=torch.empty(B, dtype=torch.int32, device=dev),
+               status=torch.empty(B, dtype=torch.int32, device=dev))
+    if want_ops:
+        n_max = S.n_max if inst is not None else S.instances[0].n
+        m_max = S.m_max if inst is not None else S.instances[0].m
+        out["ops"] = torch.zeros((B, 2 * n_max), dtype=torch.uint16, device=dev)
+        out["rt_end"] = torch.zeros((B, m_max), dtype=torch.uint16, device=dev)
+    return out
+
+
+def _decode_call(fn, S, prio, hint, inst, out, stream):
     B, stride = prio.shape
-    dev = prio.device
-    if out is None:
-        out = dict(fitness=torch.empty(B, dtype=torch.int64, device=dev),
-                   makespan=torch.empty(B, dtype=torch.int32, device=dev),
-                   unscheduled=torch.empty(B, dtype=torch.int32, device=dev),
-                   status=torch.empty(B, dtype=torch.int32, device=dev))
-        if want_ops:
-            n_max = S.n_max if inst is not None else S.instances[0].n
-            m_max = S.m_max if inst is not None else S.instances[0].m
-            out["ops"] = torch.zeros((B, 2 * n_max), dtype=torch.uint16, device=dev)
-            out["rt_end"] = torch.zeros((B, m_max), dtype=torch.uint16, device=dev)
-    _check(load().brkga_decode_eval(
+    _check(fn(
         S.handle, B, _dptr(inst, torch.int32, "inst"), _dptr(prio, torch.float32, "prio"),
         _dptr(hint, torch.float32, "hint"), stride, _dptr(out["fitness"], torch.int64, "fitness"),
         _dptr(out["makespan"], torch.int32, "makespan"), _dptr(out["unscheduled"], torch.int32, "unscheduled"),
         _dptr(out["status"], None, "status"), _dptr(out.get("ops"), torch.uint16, "ops_out"),
         _dptr(out.get("rt_end"), torch.uint16, "rt_end_out"), _stream(stream)))
     return out
+
+
+def brkga_decode_eval(S: InstanceSet, prio, hint=None, inst=None, want_ops=False, out=None, stream=None):
+    """Decode B chromosomes (see brkga_decode_eval in vrprpd.h).  prio/hint:
+    [B, stride] float32 device tensors.  Returns dict of device tensors."""
+    if out is None:
+        out = _decode_out(S, prio.shape[0], prio.device, inst, want_ops)
+    return _decode_call(load().brkga_decode_eval, S, prio, hint, inst, out, stream)
+
+
+def brkga_decode_eval_noalloc(S: InstanceSet, prio, hint=None, inst=None, out=None, want_ops=False, stream=None):
+    """brkga_decode_eval with the library's fixed workspace (see
+    brkga_decode_eval_noalloc in vrprpd.h): the library allocates no device
+    memory.  Pass `out` (the dict brkga_decode_eval returns) to allocate
+    nothing here either."""
+    if out is None:
+        out = _decode_out(S, prio.shape[0], prio.device, inst, want_ops)
+    return _decode_call(load().brkga_decode_eval_noalloc, S, prio, hint, inst, out, stream)
+
+
+def brkga_decode_noalloc_max_bytes():
+    """Size in bytes of brkga_decode_eval_noalloc's fixed workspace."""
+    return int(load().brkga_decode_noalloc_max_bytes())
 
 
 def brkga_evolve(prio, hint, fitness, n_elite, n_mutant, rho_e, seed, generation, genes=None,

@@ -16,6 +16,7 @@
 // chromosomes are in flight per CU than if the sort's 6 bytes per op stayed
 // allocated through them.
 #include <climits>
+#include <mutex>
 
 #include "common.h"
 
@@ -448,4 +449,71 @@ extern "C" int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t
                                  ops_out, rt_end_out, ws, st);
     (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+// The workspace of brkga_decode_eval_noalloc: one file-scope device array.
+// Each GPU the library runs on holds its own copy (at its own address) from
+// the module's load to the end of the process.  In host code the name stands
+// for a host-side shadow, never for device memory: kernels get the address
+// hipGetSymbolAddress returns for the current device.
+static constexpr int64_t kDecodeScratchBytes = int64_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kDecodeScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};   // device ordinal -> address of that device's scratch
+}  // namespace
+
+// Address of the current device's scratch array, looked up once per device.
+static int scratch_for_current_device(void** out)
+{
+    int dev = -1;
+    VRP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices)
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval_noalloc: device %d (at most %d devices)", dev,
+                         kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                             "brkga_decode_eval_noalloc: hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VRPRPD_OK;
+}
+
+extern "C" int64_t brkga_decode_noalloc_max_bytes(void) { return kDecodeScratchBytes; }
+
+extern "C" int brkga_decode_eval_noalloc(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
+                                         const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
+                                         int32_t* unscheduled, uint32_t* status, uint16_t* ops_out,
+                                         uint16_t* rt_end_out, void* stream)
+{
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!set || B <= 0)   // argument errors and the empty batch: no workspace touched
+        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+                             rt_end_out, nullptr, st);
+    const int n_lds = inst ? set->n_max : set->host[0].n;
+    if (2 * n_lds > 8192)   // decode_launch reports it; keep the size arithmetic below in range
+        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+                             rt_end_out, nullptr, st);
+    if (B > (int64_t(1) << 40))
+        return set_error(VRPRPD_EINVAL, "brkga_decode_eval_noalloc: B = %lld is beyond the %lld-byte workspace",
+                         (long long)B, (long long)kDecodeScratchBytes);
+    const int64_t need = decode_ws_bytes(set, B, inst != nullptr, ops_out != nullptr);
+    if (need > kDecodeScratchBytes)
+        return set_error(VRPRPD_EINVAL,
+                         "brkga_decode_eval_noalloc: %lld chromosomes of 2n = %d ops need a %lld-byte workspace; "
+                         "the fixed one holds %lld bytes (use brkga_decode_eval or a smaller batch)",
+                         (long long)B, 2 * n_lds, (long long)need, (long long)kDecodeScratchBytes);
+    void* ws = nullptr;
+    const int rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+                         rt_end_out, ws, st);
 }
