@@ -123,6 +123,8 @@ def _declare_alns(L):
     L.orc_alns_run.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P]
     L.orc_alns_run_from.restype = C.c_int32
     L.orc_alns_run_from.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P, C.c_uint32]
+    L.orc_alns_run_ex.restype = C.c_int32
+    L.orc_alns_run_ex.argtypes = [P, P, C.c_int32, C.c_int64, C.c_uint64, P, P, P, P, P, P, C.c_uint32, P, P]
     L.orc_det_exp.restype = C.c_double
     L.orc_det_exp.argtypes = [C.c_double]
     L.orc_alns_qrange.restype = None
@@ -244,7 +246,9 @@ def alns_local_search(inst, kind, ops, rt_end, budget=16384, passes=3):
 
 def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=False, chain0=0):
     """Run ALNS chains from one initial solution.  Returns dict(best_mk [chains],
-    best_ops [chains, 2n], best_rt [chains, m], trace [chains, iters, 4]).
+    best_ops [chains, 2n], best_rt [chains, m], z [chains] (final current
+    makespans), T [chains], wD [chains, 6], wR [chains, 4] (final temperatures
+    and operator weights), trace [chains, iters, 4]).
     chain0: index of the first chain in the random-draw counters."""
     oi = _oinst(inst)
     init_ops = np.ascontiguousarray(init_ops, dtype=np.uint16)
@@ -252,10 +256,13 @@ def alns_run(inst, params, chains, iterations, seed, init_ops, init_rt, trace=Fa
     bo = np.zeros((chains, 2 * oi.n), dtype=np.uint16)
     br = np.zeros((chains, oi.m), dtype=np.uint16)
     bm = np.zeros(chains, dtype=np.int32)
+    z = np.zeros(chains, dtype=np.int32)
+    fs = np.zeros((chains, 11), dtype=np.float64)
     tr = np.zeros((chains, iterations, 4), dtype=np.int64) if trace else None
-    lib().orc_alns_run_from(oi.ref, C.byref(params), chains, iterations, seed & (2**64 - 1), _ptr(init_ops),
-                            _ptr(init_rt), _ptr(bo), _ptr(br), _ptr(bm), _ptr(tr), chain0)
-    out = dict(best_mk=bm, best_ops=bo, best_rt=br)
+    lib().orc_alns_run_ex(oi.ref, C.byref(params), chains, iterations, seed & (2**64 - 1), _ptr(init_ops),
+                          _ptr(init_rt), _ptr(bo), _ptr(br), _ptr(bm), _ptr(tr), chain0, _ptr(z), _ptr(fs))
+    out = dict(best_mk=bm, best_ops=bo, best_rt=br, z=z, T=fs[:, 0].copy(), wD=fs[:, 1:7].copy(),
+               wR=fs[:, 7:11].copy())
     if trace:
         out["trace"] = tr
     return out

@@ -750,9 +750,10 @@ int32_t orc_alns_update(const orc_alns_params* P, orc_alns_chain* c, int32_t di,
 /* chain0: the first chain's index in the random-draw counters (chains of
  * one instance in a state that holds several instances are numbered on from
  * the earlier instances' chains). */
-int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
-                          uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
-                          uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0)
+int32_t orc_alns_run_ex(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                        uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                        uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0, int32_t* cur_mk,
+                        double* fstate)
 {
     const int n = I->n, m = I->m;
     int q_min = P->q_min, q_max = P->q_max;
@@ -848,6 +849,13 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
         if (best_ops) memcpy(best_ops + (size_t)ch * 2 * n, C[ch].B.ops, (size_t)C[ch].B.L * sizeof(uint16_t));
         if (best_rt) memcpy(best_rt + (size_t)ch * m, C[ch].B.rt, (size_t)m * sizeof(uint16_t));
         if (best_mk) best_mk[ch] = C[ch].k.zb;
+        if (cur_mk) cur_mk[ch] = C[ch].k.z;
+        if (fstate) {   /* final temperature and operator weights */
+            double* f = fstate + (size_t)ch * (1 + ND + NR);
+            f[0] = C[ch].k.T;
+            for (int i = 0; i < ND; ++i) f[1 + i] = C[ch].k.wD[i];
+            for (int i = 0; i < NR; ++i) f[1 + ND + i] = C[ch].k.wR[i];
+        }
         if (C[ch].k.zb < best) best = C[ch].k.zb;
         sol_free(&C[ch].S);
         sol_free(&C[ch].B);
@@ -857,6 +865,14 @@ int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t c
     return best;
 }
 
+
+int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                          uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                          uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0)
+{
+    return orc_alns_run_ex(I, P, chains, iterations, seed, init_ops, init_rt, best_ops, best_rt, best_mk, trace,
+                           chain0, NULL, NULL);
+}
 
 int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
                      uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,

@@ -125,6 +125,13 @@ int32_t orc_alns_run(const orc_inst* I, const orc_alns_params* P, int32_t chains
 int32_t orc_alns_run_from(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
                           uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
                           uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0);
+/* The same, also writing each chain's final current makespan (cur_mk
+ * [chains], nullable) and its final temperature and operator weights (fstate
+ * [chains][1 + 6 + 4] = T, w_D, w_R; nullable). */
+int32_t orc_alns_run_ex(const orc_inst* I, const orc_alns_params* P, int32_t chains, int64_t iterations,
+                        uint64_t seed, const uint16_t* init_ops, const uint16_t* init_rt, uint16_t* best_ops,
+                        uint16_t* best_rt, int32_t* best_mk, int64_t* trace, uint32_t chain0, int32_t* cur_mk,
+                        double* fstate);
 /* One destroy operator on a complete feasible solution, as iteration `it` of
  * chain `chain` applies it, candidate `cand` of a learned proposal (draw
  * counters 16 + 4096 cand + i).  Returns the number of removed customers

@@ -31,6 +31,14 @@ ALNS_CASES = [
 ]
 
 
+def _same_state(info, ref):
+    """Final current makespans, fp64 temperatures and operator weights, bit
+    for bit."""
+    assert np.array_equal(info["z"], ref["z"])
+    for key in ("T", "wD", "wR"):
+        assert np.array_equal(info[key].view(np.uint64), ref[key].view(np.uint64)), key
+
+
 @pytest.mark.parametrize("case", ALNS_CASES, ids=lambda c: f"n{c[0]}m{c[1]}b{c[8]}")
 def test_alns_trajectory_parity(orc, P, case):
     n, m, k, R, rule, lm, chains, iters, budget, imp = case
@@ -54,6 +62,7 @@ def test_alns_trajectory_parity(orc, P, case):
     info = st.state()
     assert info["iterations"] == iters
     assert np.array_equal(info["zb"], ref["best_mk"])
+    _same_state(info, ref)
     for ch in range(chains):
         mk, bops, brt = st.best(ch)
         assert mk == ref["best_mk"][ch]
@@ -167,8 +176,50 @@ def test_alns_local_search_parity(orc, P, case):
                                                                            ref["trace"][ch, it])
         info = st.state()
         assert np.array_equal(info["zb"], ref["best_mk"])
+        _same_state(info, ref)
         for ch in range(chains):
             mk, bops, brt = st.best(ch)
             assert np.array_equal(bops.cpu().numpy()[:2 * n], ref["best_ops"][ch])
             assert orc.eval_one(inst, bops.cpu().numpy()[:2 * n], brt.cpu().numpy()[:m]) == (mk, 0)
         st.close()
+
+
+FULL_SCALE = [
+    # 1000 customers, 10 vehicles, k = 10, R = 100, p = U_int[1,20] floor(dbar/10), 16,384 tuples per
+    # iteration: q in [25, 50], enumeration sorts of ~2,000 slot keys, gains over n customers
+    ("alns", dict(tuple_budget=16384, import_interval=2)),
+    # the same with both local searches due in the first iterations (16,384-tuple passes)
+    ("ls", dict(tuple_budget=16384, import_interval=0, ls_repos_interval=2, ls_reloc_interval=3,
+                ls_budget=16384)),
+]
+
+
+@pytest.mark.parametrize("name,kw", FULL_SCALE, ids=[c[0] for c in FULL_SCALE])
+def test_alns_full_scale_parity(orc, P, name, kw):
+    """alns_step at the full-scale configuration (the one the benchmark
+    times): four chains x three iterations cover all six destroy operators;
+    traces, final makespans, fp64 temperatures and weights and the best
+    solutions equal the oracle's."""
+    inst = synth.make_instance(1000, 10, 10, 100, "1R20d10", seed=10000)
+    ops, rt = synth.round_robin_solution(inst, vehicles=10)
+    chains, iters, seed = 4, 3, 77
+    ref = orc.alns_run(inst, orc.alns_params(**kw), chains, iters, seed, ops, rt, trace=True)
+    assert set((ref["trace"][:, :, 3] & 0xFF).ravel()) == set(range(6))
+    S = P.InstanceSet([inst])
+    st = P.AlnsState(S, [0], chains, P.alns_params(**kw), seed, torch.from_numpy(ops).cuda(),
+                     torch.from_numpy(rt).cuda())
+    tr = st.set_trace(iters)
+    st.step(iters)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    for ch in range(chains):
+        for it in range(iters):
+            assert np.array_equal(got[ch, it], ref["trace"][ch, it]), (ch, it, got[ch, it], ref["trace"][ch, it])
+    info = st.state()
+    assert np.array_equal(info["zb"], ref["best_mk"])
+    _same_state(info, ref)
+    for ch in range(chains):
+        mk, bops, brt = st.best(ch)
+        assert np.array_equal(brt.cpu().numpy()[:10], ref["best_rt"][ch])
+        assert np.array_equal(bops.cpu().numpy()[:2000], ref["best_ops"][ch])
+    st.close()

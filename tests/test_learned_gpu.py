@@ -45,6 +45,7 @@ CASES = [
     (30, 3, 3, 9, "base", 4, 4),
     (100, 4, 5, 20, "2x", 3, 6),
     (60, 17, 3, 60, "1R10", 2, 3),    # 32-lane groups
+    (500, 10, 8, 50, "base", 2, 8),   # the learned-proposal configuration (500 customers, K = 8)
 ]
 
 
@@ -57,7 +58,7 @@ def test_one_learned_iteration_matches_oracle(orc, P, case):
     assert st0 == 0
     seed = 4242 + n
     S = P.InstanceSet([inst])
-    prm = P.alns_params(tuple_budget=300)
+    prm = P.alns_params(tuple_budget=16384 if n >= 500 else 300)
     st = P.AlnsState(S, [0], chains, prm, seed, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
     net = om.MLP.init(seed=n)
     g = np.random.Generator(np.random.Philox(key=n))
