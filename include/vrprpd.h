@@ -217,8 +217,13 @@ int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, const int32_t* 
  * SelectVehicle picks the feasible vehicle with the earliest completion time
  * of the op (arrival for a drop, max(arrival, ready) for a pickup); ties go to
  * the first vehicle counting cyclically from floor(m * alpha_o) (fp32
- * product), or from vehicle 0 without hints.  Passes repeat until every op is
- * scheduled or a pass schedules nothing (at most 2n passes).
+ * product), or from vehicle 0 without hints.  With flags =
+ * VRPRPD_DECODE_HINT_FIRST the hint vehicle floor(m * alpha_o) takes the op
+ * whenever it can (Section 4.4.1: the hint is the vehicle, overridden only to
+ * keep the schedule feasible; Section 4.4.4: the encoded ALNS solution then
+ * decodes close to itself), and SelectVehicle decides only when it cannot.
+ * Passes repeat until every op is scheduled or a pass schedules nothing (at
+ * most 2n passes).
  * makespan = latest return of a used vehicle; unscheduled = 2n - #scheduled;
  * fitness = makespan + 10^6 * unscheduled (lambda of the paper).
  * Keys must lie in [0, 1) (-0.0 counts as 0.0): otherwise status BAD_KEY,
@@ -228,14 +233,16 @@ int vrprpd_insert_scan(const vrprpd_set* set, int32_t num_bases, const int32_t* 
  * Arguments (device pointers):
  *   B            chromosomes; inst [B] instance index or NULL (all instance 0)
  *   prio, hint   [B][key_stride] fp32 keys (hint may be NULL); key_stride >= 2n
+ *   flags        (host) 0, or VRPRPD_DECODE_HINT_FIRST
  *   fitness      [B] int64 out; makespan, unscheduled [B] int32 out; status [B] out
  *   ops_out      [B][2 n_max] uint16 out, the decoded sequences route after
  *                route (only the first rt_end_out[m-1] entries are written), or NULL
  *   rt_end_out   [B][m_max] uint16 out, cumulative route ends, or NULL
  * Limits: 2n <= 8192.  Errors: EINVAL, EHIP.
  */
+#define VRPRPD_DECODE_HINT_FIRST 1
 int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
-                      const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
+                      const float* hint, int64_t key_stride, int32_t flags, int64_t* fitness, int32_t* makespan,
                       int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
                       void* stream);
 
@@ -258,9 +265,9 @@ int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, con
  * caller.
  */
 int brkga_decode_eval_noalloc(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
-                              const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
-                              int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
-                              void* stream);
+                              const float* hint, int64_t key_stride, int32_t flags, int64_t* fitness,
+                              int32_t* makespan, int32_t* unscheduled, uint32_t* status, uint16_t* ops_out,
+                              uint16_t* rt_end_out, void* stream);
 /* Size in bytes of brkga_decode_eval_noalloc's fixed workspace. */
 int64_t brkga_decode_noalloc_max_bytes(void);
 
@@ -401,12 +408,13 @@ int vrprpd_construct(const vrprpd_set* set, int32_t B, const int32_t* inst, int3
  * seed and generation g.  The set's largest instance must be among
  * inst_ids.  prio0 / hint0 (device [n_inst * Np][2 n_max]) give the initial
  * populations, or NULL for U(0,1) genes (Philox, counter (gene / 4,
- * individual, 0, 'RAND'), key pop_seed).
+ * individual, 0, 'RAND'), key pop_seed).  decode_flags: the decoder's flags
+ * (0 or VRPRPD_DECODE_HINT_FIRST, see brkga_decode_eval).
  */
 typedef struct brkga_state brkga_state;
 int brkga_state_create(brkga_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
                        int32_t Np, int32_t n_elite, int32_t n_mutant, double rho_e, uint64_t seed,
-                       const float* prio0, const float* hint0, void* stream);
+                       int32_t decode_flags, const float* prio0, const float* hint0, void* stream);
 int brkga_state_step(brkga_state* st, int32_t generations, int32_t use_graph, void* stream);
 /* Generations done (host), best fitness per population so far (host
  * [n_inst], synchronises), the best chromosomes (device [n_inst][2 n_max])

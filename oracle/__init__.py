@@ -71,6 +71,8 @@ def _declare(L):
     L.orc_insert_scan.argtypes = [P, P, P, C.c_int64, P, C.c_int32, P, P, P, P]
     L.orc_decode.restype = C.c_uint32
     L.orc_decode.argtypes = [P, P, P, P, P, P, P, P]
+    L.orc_decode_ex.restype = C.c_uint32
+    L.orc_decode_ex.argtypes = [P, P, P, P, P, P, P, P, C.c_int32]
     L.orc_philox.restype = None
     L.orc_philox.argtypes = [P, P, P]
     L.orc_brkga_evolve.restype = None
@@ -345,9 +347,13 @@ def insert_scan(inst, base_ops, base_rt, tuples, seg_off):
     return mk[:T], st[:T], top[:S]
 
 
-def decode(inst, prio, hint=None, want_ops=False):
+DECODE_HINT_FIRST = 1
+
+
+def decode(inst, prio, hint=None, want_ops=False, flags=0):
     """Decode one chromosome.  Returns dict(fitness, makespan, unscheduled,
-    status[, ops, rt_end])."""
+    status[, ops, rt_end]).  flags: DECODE_HINT_FIRST (the hint vehicle takes
+    an op whenever it can)."""
     oi = _oinst(inst)
     prio = np.ascontiguousarray(prio, dtype=np.float32)
     hint = None if hint is None else np.ascontiguousarray(hint, dtype=np.float32)
@@ -356,8 +362,8 @@ def decode(inst, prio, hint=None, want_ops=False):
     un = np.zeros(1, dtype=np.int32)
     ops = np.zeros(2 * oi.n, dtype=np.uint16) if want_ops else None
     rt = np.zeros(oi.m, dtype=np.uint16) if want_ops else None
-    st = lib().orc_decode(oi.ref, _ptr(prio), _ptr(hint), _ptr(f), _ptr(mk), _ptr(un),
-                          _ptr(ops), _ptr(rt))
+    st = lib().orc_decode_ex(oi.ref, _ptr(prio), _ptr(hint), _ptr(f), _ptr(mk), _ptr(un),
+                             _ptr(ops), _ptr(rt), int(flags))
     out = dict(fitness=int(f[0]), makespan=int(mk[0]), unscheduled=int(un[0]), status=int(st))
     if want_ops:
         out["ops"] = ops[: int(rt[-1])] if rt[-1] else ops[:0]
@@ -365,7 +371,7 @@ def decode(inst, prio, hint=None, want_ops=False):
     return out
 
 
-def decode_batch(inst, prio, hint=None):
+def decode_batch(inst, prio, hint=None, flags=0):
     oi = _oinst(inst)
     B = prio.shape[0]
     f = np.zeros(B, dtype=np.int64)
@@ -373,7 +379,7 @@ def decode_batch(inst, prio, hint=None):
     un = np.zeros(B, dtype=np.int32)
     st = np.zeros(B, dtype=np.uint32)
     for b in range(B):
-        r = decode(oi, prio[b], None if hint is None else hint[b])
+        r = decode(oi, prio[b], None if hint is None else hint[b], flags=flags)
         f[b], mk[b], un[b], st[b] = r["fitness"], r["makespan"], r["unscheduled"], r["status"]
     return f, mk, un, st
 

@@ -12,6 +12,11 @@
  *  - SelectVehicle minimises the op's completion time (arrival for a drop,
  *    max(arrival, ready) for a pickup); ties go to the vehicle first reached
  *    when counting cyclically from the hint vehicle floor(m * alpha_o);
+ *  - with ORC_DECODE_HINT_FIRST the hint vehicle takes the op whenever it can
+ *    (Section 4.4.1: the hint maps to vehicle floor(m * alpha_o) and is
+ *    overridden only for feasibility; Section 4.4.4: the ALNS encoding then
+ *    decodes to the ALNS solution); SelectVehicle as above chooses only when
+ *    the hint vehicle cannot take it;
  *  - initial loads follow the instance's load model (FULL_START: q = k as in
  *    Algorithm 2; MIN_PRELOAD: a vehicle takes one more resource from the
  *    depot only when a drop needs it, within k and the fleet total R).
@@ -42,10 +47,11 @@ static int canon_key(float x, float* out)
     return 1;
 }
 
-uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
-                    int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
-                    uint16_t* ops_out, uint16_t* rt_end_out)
+uint32_t orc_decode_ex(const orc_inst* I, const float* prio, const float* hint,
+                       int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                       uint16_t* ops_out, uint16_t* rt_end_out, int32_t flags)
 {
+    const int hint_first = (flags & ORC_DECODE_HINT_FIRST) != 0;
     const int n = I->n, m = I->m, k = I->k, N1 = n + 1, O = 2 * n;
     const int minpre = I->load_model != ORC_FULL_START;
     keyed* ord = malloc((size_t)O * sizeof(keyed));
@@ -106,6 +112,10 @@ uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
                     key = arr > ready[c] ? arr : ready[c];
                 }
                 if (!cand) continue;
+                if (hint_first && v == h) {   /* the hint vehicle can take it: it does */
+                    bv = v; bkey = key;
+                    break;
+                }
                 int rot = (v - h + m) % m;
                 if (bv < 0 || key < bkey || (key == bkey && rot < brot)) {
                     bv = v; bkey = key; brot = rot;
@@ -153,4 +163,12 @@ uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
     free(t); free(loc); free(q); free(M); free(len); free(seq); free(sched); free(ready);
     free(ord); free(alpha);
     return st;
+}
+
+
+uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
+                    int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                    uint16_t* ops_out, uint16_t* rt_end_out)
+{
+    return orc_decode_ex(I, prio, hint, fitness, makespan, unscheduled, ops_out, rt_end_out, 0);
 }

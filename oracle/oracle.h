@@ -63,6 +63,12 @@ void orc_insert_scan(const orc_inst* I, const uint16_t* base_ops, const uint16_t
 uint32_t orc_decode(const orc_inst* I, const float* prio, const float* hint,
                     int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
                     uint16_t* ops_out, uint16_t* rt_end_out);
+/* The same with flags: ORC_DECODE_HINT_FIRST gives the op to the hint
+ * vehicle whenever it can take it (SelectVehicle decides otherwise). */
+#define ORC_DECODE_HINT_FIRST 1
+uint32_t orc_decode_ex(const orc_inst* I, const float* prio, const float* hint,
+                       int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                       uint16_t* ops_out, uint16_t* rt_end_out, int32_t flags);
 
 /* Philox4x32-10 (Salmon et al., SC'11). */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -46,8 +46,8 @@ SIGNATURES = {
     "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "vrprpd_autotune_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P, _P, _P]),
     "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
-    "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
-    "brkga_decode_eval_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "brkga_decode_eval_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_decode_noalloc_max_bytes": (C.c_int64, []),
     "brkga_evolve": (C.c_int, [_I32, _I32, _I64, _P, _P, _P, _I32, _I32, C.c_double, _U64, C.c_uint32,
                                _P, _P, _P, _P]),
@@ -63,7 +63,7 @@ SIGNATURES = {
     "brkga_state_save": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "brkga_state_load": (C.c_int, [_P, _P, C.c_int64, _P]),
     "brkga_state_create": (C.c_int, [C.POINTER(C.c_void_p), _P, _I32, _P, _I32, _I32, _I32, C.c_double, _U64,
-                                     _P, _P, _P]),
+                                     _I32, _P, _P, _P]),
     "brkga_state_step": (C.c_int, [_P, _I32, _I32, _P]),
     "brkga_state_get": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_state_destroy": (C.c_int, [_P]),
@@ -91,6 +91,7 @@ SIGNATURES = {
 }
 
 CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT = 0, 1, 2, 3
+DECODE_HINT_FIRST = 1
 
 MLP_IN, MLP_HIDDEN, MLP_NUM_PARAMS = 64, 256, 148481
 
@@ -251,33 +252,35 @@ def _decode_out(S: InstanceSet, B, dev, inst, want_ops):
     return out
 
 
-def _decode_call(fn, S, prio, hint, inst, out, stream):
+def _decode_call(fn, S, prio, hint, inst, out, stream, flags):
     B, stride = prio.shape
     _check(fn(
         S.handle, B, _dptr(inst, torch.int32, "inst"), _dptr(prio, torch.float32, "prio"),
-        _dptr(hint, torch.float32, "hint"), stride, _dptr(out["fitness"], torch.int64, "fitness"),
+        _dptr(hint, torch.float32, "hint"), stride, int(flags), _dptr(out["fitness"], torch.int64, "fitness"),
         _dptr(out["makespan"], torch.int32, "makespan"), _dptr(out["unscheduled"], torch.int32, "unscheduled"),
         _dptr(out["status"], None, "status"), _dptr(out.get("ops"), torch.uint16, "ops_out"),
         _dptr(out.get("rt_end"), torch.uint16, "rt_end_out"), _stream(stream)))
     return out
 
 
-def brkga_decode_eval(S: InstanceSet, prio, hint=None, inst=None, want_ops=False, out=None, stream=None):
+def brkga_decode_eval(S: InstanceSet, prio, hint=None, inst=None, want_ops=False, out=None, stream=None, flags=0):
     """Decode B chromosomes (see brkga_decode_eval in vrprpd.h).  prio/hint:
-    [B, stride] float32 device tensors.  Returns dict of device tensors."""
+    [B, stride] float32 device tensors; flags 0 or DECODE_HINT_FIRST.
+    Returns dict of device tensors."""
     if out is None:
         out = _decode_out(S, prio.shape[0], prio.device, inst, want_ops)
-    return _decode_call(load().brkga_decode_eval, S, prio, hint, inst, out, stream)
+    return _decode_call(load().brkga_decode_eval, S, prio, hint, inst, out, stream, flags)
 
 
-def brkga_decode_eval_noalloc(S: InstanceSet, prio, hint=None, inst=None, out=None, want_ops=False, stream=None):
+def brkga_decode_eval_noalloc(S: InstanceSet, prio, hint=None, inst=None, out=None, want_ops=False, stream=None,
+                              flags=0):
     """brkga_decode_eval with the library's fixed workspace (see
     brkga_decode_eval_noalloc in vrprpd.h): the library allocates no device
     memory.  Pass `out` (the dict brkga_decode_eval returns) to allocate
     nothing here either."""
     if out is None:
         out = _decode_out(S, prio.shape[0], prio.device, inst, want_ops)
-    return _decode_call(load().brkga_decode_eval_noalloc, S, prio, hint, inst, out, stream)
+    return _decode_call(load().brkga_decode_eval_noalloc, S, prio, hint, inst, out, stream, flags)
 
 
 def brkga_decode_noalloc_max_bytes():
@@ -381,12 +384,13 @@ class BrkgaState:
     """Batched BRKGA over several instances (brkga_state_*)."""
 
     def __init__(self, S: InstanceSet, inst_ids, Np, n_elite, n_mutant, rho_e, seed, prio0=None, hint0=None,
-                 stream=None):
+                 stream=None, decode_flags=0):
         ids = (C.c_int32 * len(inst_ids))(*inst_ids)
         h = C.c_void_p()
         _check(load().brkga_state_create(C.byref(h), S.handle, len(inst_ids), ids, Np, n_elite, n_mutant,
-                                         float(rho_e), seed & (2**64 - 1), _dptr(prio0, torch.float32, "prio0"),
-                                         _dptr(hint0, torch.float32, "hint0"), _stream(stream)))
+                                         float(rho_e), seed & (2**64 - 1), int(decode_flags),
+                                         _dptr(prio0, torch.float32, "prio0"), _dptr(hint0, torch.float32, "hint0"),
+                                         _stream(stream)))
         self.handle = h
         self.P, self.Np, self.stride = len(inst_ids), Np, 2 * S.n_max
 

@@ -36,8 +36,8 @@ int64_t mlp_max_rows(const vrprpd_mlp* h);   // rows a network handle can score 
 // (by_inst: an instance array is passed; want_ops: sequences are written).
 int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool want_ops);
 int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio, const float* hint,
-                  int64_t key_stride, int64_t* fitness, int32_t* makespan, int32_t* unscheduled, uint32_t* status,
-                  uint16_t* ops_out, uint16_t* rt_end_out, void* ws, hipStream_t st);
+                  int64_t key_stride, int32_t flags, int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                  uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out, void* ws, hipStream_t st);
 
 #define VRP_HIP(call)                                                      \
     do {                                                                   \

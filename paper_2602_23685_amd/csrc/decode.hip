@@ -42,6 +42,7 @@ struct DecodeArgs {
     uint16_t* order;       // [B][cap] op indices in priority order (workspace)
     uint8_t* badkey;       // [B] 1: the chromosome's keys failed the check (workspace)
     uint32_t* log;         // [B][cap] schedule log, code | vehicle << 16 (workspace, with ops_out)
+    int32_t hint_first;    // 1: the hint vehicle takes an op whenever it can (VRPRPD_DECODE_HINT_FIRST)
 };
 
 __host__ __device__ inline int d16(int x) { return (x + 15) & ~15; }
@@ -269,7 +270,12 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 const int key = isPi ? (arr > r ? arr : r) : arr;
                 const int kv = (isPi ? pok : dok) ? key : INT_MAX;
                 int ks, vs;
-                if constexpr (kPacked) {
+                // hint-first rule: the hint vehicle, if it can take the op
+                const int kh = a.hint_first ? __builtin_amdgcn_readlane(kv, hi) : INT_MAX;
+                if (kh != INT_MAX) {
+                    ks = kh;
+                    vs = hi;
+                } else if constexpr (kPacked) {
                     // rank (v - hint) mod 16: the hint vehicle first, then
                     // the following ones cyclically (lanes >= m hold INT_MAX)
                     const int kp = kv == INT_MAX ? INT_MAX : (kv << 4) | ((lane - hi) & 15);
@@ -380,10 +386,11 @@ int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool wan
 }
 
 int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio, const float* hint,
-                  int64_t key_stride, int64_t* fitness, int32_t* makespan, int32_t* unscheduled, uint32_t* status,
-                  uint16_t* ops_out, uint16_t* rt_end_out, void* ws, hipStream_t st)
+                  int64_t key_stride, int32_t flags, int64_t* fitness, int32_t* makespan, int32_t* unscheduled,
+                  uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out, void* ws, hipStream_t st)
 {
     if (!set) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: set is NULL");
+    if (flags & ~VRPRPD_DECODE_HINT_FIRST) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: unknown flags %d", flags);
     if (B < 0) return set_error(VRPRPD_EINVAL, "brkga_decode_eval: B < 0");
     if (B == 0) return VRPRPD_OK;
     if (!prio || !fitness || !makespan || !unscheduled || !status)
@@ -410,7 +417,8 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     DecodeArgs a{set->d_inst, set->d_dist, set->d_proc, inst, prio, hint, key_stride, fitness, makespan,
                  unscheduled, status, ops_out, rt_end_out, 2 * (int64_t)n_lds, (int64_t)(inst ? set->m_max
                                                                                              : set->host[0].m),
-                 B, set->num_inst, n_lds, cap, (int32_t)B, order, badkey, log};
+                 B, set->num_inst, n_lds, cap, (int32_t)B, order, badkey, log,
+                 (flags & VRPRPD_DECODE_HINT_FIRST) ? 1 : 0};
     auto launch = [&](const void* k, int lds) -> int {
         if (lds > 64 * 1024) VRP_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         return VRPRPD_OK;
@@ -435,17 +443,17 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
 using namespace vrprpd;
 
 extern "C" int brkga_decode_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
-                                 const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
-                                 int32_t* unscheduled, uint32_t* status, uint16_t* ops_out, uint16_t* rt_end_out,
-                                 void* stream)
+                                 const float* hint, int64_t key_stride, int32_t flags, int64_t* fitness,
+                                 int32_t* makespan, int32_t* unscheduled, uint32_t* status, uint16_t* ops_out,
+                                 uint16_t* rt_end_out, void* stream)
 {
     if (!set || B <= 0)   // argument errors and the empty batch: no workspace
-        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+        return decode_launch(set, B, inst, prio, hint, key_stride, flags, fitness, makespan, unscheduled, status, ops_out,
                              rt_end_out, nullptr, reinterpret_cast<hipStream_t>(stream));
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     void* ws = nullptr;
     VRP_HIP(hipMallocAsync(&ws, (size_t)decode_ws_bytes(set, B, inst != nullptr, ops_out != nullptr), st));
-    const int rc = decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status,
+    const int rc = decode_launch(set, B, inst, prio, hint, key_stride, flags, fitness, makespan, unscheduled, status,
                                  ops_out, rt_end_out, ws, st);
     (void)hipFreeAsync(ws, st);
     return rc;
@@ -490,17 +498,17 @@ static int scratch_for_current_device(void** out)
 extern "C" int64_t brkga_decode_noalloc_max_bytes(void) { return kDecodeScratchBytes; }
 
 extern "C" int brkga_decode_eval_noalloc(const vrprpd_set* set, int64_t B, const int32_t* inst, const float* prio,
-                                         const float* hint, int64_t key_stride, int64_t* fitness, int32_t* makespan,
-                                         int32_t* unscheduled, uint32_t* status, uint16_t* ops_out,
-                                         uint16_t* rt_end_out, void* stream)
+                                         const float* hint, int64_t key_stride, int32_t flags, int64_t* fitness,
+                                         int32_t* makespan, int32_t* unscheduled, uint32_t* status,
+                                         uint16_t* ops_out, uint16_t* rt_end_out, void* stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (!set || B <= 0)   // argument errors and the empty batch: no workspace touched
-        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+        return decode_launch(set, B, inst, prio, hint, key_stride, flags, fitness, makespan, unscheduled, status, ops_out,
                              rt_end_out, nullptr, st);
     const int n_lds = inst ? set->n_max : set->host[0].n;
     if (2 * n_lds > 8192)   // decode_launch reports it; keep the size arithmetic below in range
-        return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+        return decode_launch(set, B, inst, prio, hint, key_stride, flags, fitness, makespan, unscheduled, status, ops_out,
                              rt_end_out, nullptr, st);
     if (B > (int64_t(1) << 40))
         return set_error(VRPRPD_EINVAL, "brkga_decode_eval_noalloc: B = %lld is beyond the %lld-byte workspace",
@@ -514,6 +522,6 @@ extern "C" int brkga_decode_eval_noalloc(const vrprpd_set* set, int64_t B, const
     void* ws = nullptr;
     const int rc = scratch_for_current_device(&ws);
     if (rc) return rc;
-    return decode_launch(set, B, inst, prio, hint, key_stride, fitness, makespan, unscheduled, status, ops_out,
+    return decode_launch(set, B, inst, prio, hint, key_stride, flags, fitness, makespan, unscheduled, status, ops_out,
                          rt_end_out, ws, st);
 }

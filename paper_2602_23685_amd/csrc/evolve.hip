@@ -446,6 +446,7 @@ __global__ void gen_tick_kernel(uint32_t* gen)
 struct brkga_state {
     const vrprpd_set* set = nullptr;
     int32_t P = 0, Np = 0, ne = 0, nm = 0;
+    int32_t dflags = 0;   // decoder flags (VRPRPD_DECODE_*)
     uint32_t thr = 0;
     uint64_t seed = 0;
     int64_t stride = 0;
@@ -473,7 +474,7 @@ namespace vrprpd {
 static int brkga_generation(brkga_state* s, int from, hipStream_t st)
 {
     const int64_t B = (int64_t)s->P * s->Np;
-    int rc = decode_launch(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->fit, s->mk,
+    int rc = decode_launch(s->set, B, s->inst_of_row, s->prio[from], s->hint[from], s->stride, s->dflags, s->fit, s->mk,
                            s->unsch, s->status, nullptr, nullptr, s->dec_ws, st);
     if (rc) return rc;
     launch_rank(s->fit, s->Np, s->P, s->order, st);
@@ -506,7 +507,7 @@ extern "C" int brkga_state_destroy(brkga_state* s)
 
 extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int32_t n_inst, const int32_t* inst_ids,
                                   int32_t Np, int32_t n_elite, int32_t n_mutant, double rho_e, uint64_t seed,
-                                  const float* prio0, const float* hint0, void* stream)
+                                  int32_t decode_flags, const float* prio0, const float* hint0, void* stream)
 {
     if (!out) return set_error(VRPRPD_EINVAL, "brkga_state_create: out is NULL");
     *out = nullptr;
@@ -514,6 +515,8 @@ extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int3
         Np - n_elite < 1 || !(rho_e >= 0.0 && rho_e <= 1.0) || ((prio0 == nullptr) != (hint0 == nullptr)))
         return set_error(VRPRPD_EINVAL, "brkga_state_create: bad arguments");
     if ((int64_t)n_inst * Np > INT32_MAX) return set_error(VRPRPD_EINVAL, "brkga_state_create: too many individuals");
+    if (decode_flags & ~VRPRPD_DECODE_HINT_FIRST)
+        return set_error(VRPRPD_EINVAL, "brkga_state_create: unknown decoder flags %d", decode_flags);
     int n_max = 0;
     for (int i = 0; i < n_inst; ++i) {
         if (inst_ids[i] < 0 || inst_ids[i] >= set->num_inst)
@@ -525,6 +528,7 @@ extern "C" int brkga_state_create(brkga_state** out, const vrprpd_set* set, int3
                                         "(the decoder sizes its keys by the set)");
     brkga_state* s = new brkga_state;
     s->set = set;
+    s->dflags = decode_flags;
     s->P = n_inst;
     s->Np = Np;
     s->ne = n_elite;

@@ -90,7 +90,7 @@ def test_host_argument_checks_of_the_newer_entry_points(lib):
     assert lib.alns_record_batch(None, 1, 0, None, None, None, None) == E
     assert lib.alns_set_graph(None, 1) == E
     # batched BRKGA without a set; autotuner without a set
-    assert lib.brkga_state_create(C.byref(h), None, 1, None, 8, 1, 1, C.c_double(0.7), 0, None, None, None) == E
+    assert lib.brkga_state_create(C.byref(h), None, 1, None, 8, 1, 1, C.c_double(0.7), 0, 0, None, None, None) == E
     assert lib.brkga_state_step(None, 1, 1, None) == E
     assert lib.vrprpd_autotune_eval(None, 1, None, None, None, None, None, 0, None, None, 1, None, None, None,
                                     None) == E

@@ -41,8 +41,8 @@ def test_decode_parity(orc, P, case):
     inst = synth.make_instance(n, m, k, R, rule, seed=7000 + n, load_model=lm)
     prio, hint = synth.random_keys(B, n, seed=n + m, special=B >= 8)
     S = P.InstanceSet([inst])
-    for use_hint in (True, False):
-        out = P.brkga_decode_eval(S, dev(prio), dev(hint) if use_hint else None, want_ops=True)
+    for use_hint, flags in ((True, 0), (False, 0), (True, P.DECODE_HINT_FIRST), (False, P.DECODE_HINT_FIRST)):
+        out = P.brkga_decode_eval(S, dev(prio), dev(hint) if use_hint else None, want_ops=True, flags=flags)
         torch.cuda.synchronize()
         f = out["fitness"].cpu().numpy()
         mk = out["makespan"].cpu().numpy()
@@ -51,9 +51,9 @@ def test_decode_parity(orc, P, case):
         ops = out["ops"].cpu().numpy()
         rt = out["rt_end"].cpu().numpy()
         for b in range(B):
-            r = orc.decode(inst, prio[b], hint[b] if use_hint else None, want_ops=True)
+            r = orc.decode(inst, prio[b], hint[b] if use_hint else None, want_ops=True, flags=flags)
             assert (f[b], mk[b], un[b], st[b]) == (r["fitness"], r["makespan"], r["unscheduled"],
-                                                     r["status"]), (b, use_hint)
+                                                     r["status"]), (b, use_hint, flags)
             if r["status"] & 16:
                 assert np.all(rt[b] == 0)
             else:
@@ -154,8 +154,8 @@ def test_generation_loop_matches_oracle(orc, P):
         assert np.array_equal(gp.cpu().numpy().view(np.uint32), op_.view(np.uint32))
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batched_populations_match_oracle(orc, P, graph):
+@pytest.mark.parametrize("graph,flags", [(True, 0), (False, 0), (True, 1)], ids=["graph", "direct", "hintfirst"])
+def test_batched_populations_match_oracle(orc, P, graph, flags):
     """Three instances of different size evolved as one batched state: every
     population equals the oracle's single-population run with its seed, and
     the kept best fitness is the best decoded so far."""
@@ -172,7 +172,7 @@ def test_batched_populations_match_oracle(orc, P, graph):
     for p, inst in enumerate(insts):
         p0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
         h0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
-    st = P.BrkgaState(S, [0, 1, 2], Np, ne, nm, 0.7, seed, dev(p0), dev(h0))
+    st = P.BrkgaState(S, [0, 1, 2], Np, ne, nm, 0.7, seed, dev(p0), dev(h0), decode_flags=flags)
     st.step(2, graph=graph)
     torch.cuda.synchronize()
     st.step(gens - 2, graph=graph)
@@ -185,7 +185,7 @@ def test_batched_populations_match_oracle(orc, P, graph):
         oh_ = h0[p * Np:(p + 1) * Np, :G].copy()
         bf = np.iinfo(np.int64).max
         for gen in range(gens):
-            fit = orc.decode_batch(inst, op_, oh_)[0]
+            fit = orc.decode_batch(inst, op_, oh_, flags=flags)[0]
             bf = min(bf, int(fit.min()))
             op_, oh_, _ = orc.brkga_evolve(op_, oh_, fit, ne, nm, orc.rho_threshold(0.7), P.pop_seed(seed, p), gen)
         assert best[p] == bf, (p, best[p], bf)

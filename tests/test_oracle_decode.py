@@ -56,6 +56,67 @@ def test_hint_rotation_three_vehicles(orc):
     assert list(r["ops"]) == [2, 4, 5, 3]
 
 
+def _line2():
+    """Line: depot 0, c1 at 3, c2 at 10 (d01 = 3, d02 = 10, d12 = 7)."""
+    x = np.array([0, 3, 10])
+    return np.abs(x[:, None] - x[None, :]).astype(np.int32)
+
+
+def test_hint_first_keeps_the_hint_vehicle(orc):
+    """Hint-first rule (Section 4.4.1: the hint is the vehicle unless
+    feasibility overrides it) against SelectVehicle's least completion time
+    (Section 4.4.2).  p = (4, 2), m = 2, k = 2, R = 4, MIN_PRELOAD; order D1,
+    P1, D2, P2; every hint floor(2 * 0.75) = 1.
+    Hint-first: v1 takes all four: D1 at 3 (ready 7), P1 waits to 7, D2 at
+      7 + 7 = 14 (ready 16), P2 waits to 16, return 16 + 10 = 26.
+    Least completion: D1 ties at 3 -> hint v1; P1 ties at 7 -> v1; D2: v0
+      arrives at 10, v1 at 14 -> v0 (ready 12); P2: v0 max(10, 12) = 12, v1
+      max(14, 12) = 14 -> v0; returns v0 12 + 10 = 22, v1 7 + 3 = 10."""
+    inst = synth.instance_from_matrix(_line2(), np.array([0, 4, 2], np.int32), m=2, k=2, R=4)
+    prio = np.array([0.1, 0.2, 0.3, 0.4], np.float32)
+    hint = np.full(4, 0.75, np.float32)
+    r = orc.decode(inst, prio, hint, want_ops=True, flags=orc.DECODE_HINT_FIRST)
+    assert (r["fitness"], r["makespan"], r["unscheduled"], r["status"]) == (26, 26, 0, 0)
+    assert list(r["rt_end"]) == [0, 4] and list(r["ops"]) == [2, 3, 4, 5]
+    r = orc.decode(inst, prio, hint, want_ops=True)
+    assert (r["fitness"], r["makespan"], r["unscheduled"]) == (22, 22, 0)
+    assert list(r["rt_end"]) == [2, 4] and list(r["ops"]) == [4, 5, 2, 3]
+    assert orc.eval_one(inst, np.array([2, 3, 4, 5], np.uint16), np.array([0, 4], np.uint16)) == (26, 0)
+
+
+def test_hint_first_override_and_rotation(orc):
+    """Hint-first when the hint vehicle cannot take the op: SelectVehicle
+    over the others, ties counted cyclically from the hint.  Same line,
+    p = (4, 2), m = 3, k = 1, R = 3, FULL_START (every vehicle leaves with
+    one resource); order D1, D2, P1, P2; hints floor(3 alpha) = 0 (D1), 0
+    (D2), 2 (P1), 1 (P2).
+      D1: v0 can drop -> v0 at 3 (ready 7);
+      D2: v0 is empty; v1 and v2 tie at 10, counting from 0 -> v1 (ready 12);
+      P1: v2 is full; v0 max(3, 7) = 7, v1 max(17, 7) = 17 -> v0;
+      P2: v1 has room -> v1, max(10, 12) = 12.
+    Returns v0 7 + 3 = 10, v1 12 + 10 = 22; v2 unused."""
+    inst = synth.instance_from_matrix(_line2(), np.array([0, 4, 2], np.int32), m=3, k=1, R=3, load_model=1)
+    prio = np.array([0.1, 0.3, 0.2, 0.4], np.float32)
+    hint = np.array([0.1, 0.9, 0.1, 0.5], np.float32)
+    r = orc.decode(inst, prio, hint, want_ops=True, flags=orc.DECODE_HINT_FIRST)
+    assert (r["fitness"], r["makespan"], r["unscheduled"], r["status"]) == (22, 22, 0, 0)
+    assert list(r["rt_end"]) == [2, 4, 4] and list(r["ops"]) == [2, 3, 4, 5]
+
+
+def test_hint_first_reproduces_warm_encoding(orc):
+    """Under hint-first every op of an encoded solution goes to its own
+    vehicle when the encoding's priority order is a time order of the
+    schedule: the one-vehicle-per-route solution of a round-robin start
+    (drop then own pickup, customers in turn) decodes back to itself."""
+    inst = synth.make_instance(30, 3, 3, 9, "base", seed=44)
+    ops, rt = synth.round_robin_solution(inst)
+    po, ho = orc.brkga_warm_start(inst, ops, rt, 1, 1, 1, 5)
+    r = orc.decode(inst, po[0], ho[0], want_ops=True, flags=orc.DECODE_HINT_FIRST)
+    assert r["unscheduled"] == 0
+    assert list(r["rt_end"]) == list(rt) and list(r["ops"]) == list(ops)
+    assert r["makespan"] == orc.eval_one(inst, ops, rt)[0]
+
+
 def test_single_vehicle_closed_form(orc):
     """m = 1 with room for everything: pass 1 takes ops in priority order,
     skipping pickups whose drop comes later; pass 2 takes those pickups in

@@ -49,6 +49,11 @@ def test_noalloc_matches_allocating_decoder_twice(orc, P):
         ref2 = P.brkga_decode_eval(S, p, None)
         torch.cuda.synchronize()
         _same(got2, ref2, KEYS)
+        # the hint-first vehicle rule
+        got3 = P.brkga_decode_eval_noalloc(S, p, h, want_ops=True, flags=P.DECODE_HINT_FIRST)
+        ref3 = P.brkga_decode_eval(S, p, h, want_ops=True, flags=P.DECODE_HINT_FIRST)
+        torch.cuda.synchronize()
+        _same(got3, ref3, KEYS + ("ops", "rt_end"))
         # a few against the oracle as well
         f = got["fitness"].cpu().numpy()
         for b in range(0, B, max(1, B // 6)):
