@@ -278,116 +278,108 @@ def race_to_oracle(P, torch, chains=32, limit_s=60.0, alns_chunk=10, brkga_chunk
     return out
 
 
-def batched_form(P, torch, count=256, cpi=2, iters=10, gens=10, Np=128):
-    """The batched form on instances of uneven size: every instance's
-    construction (one launch per n-bucket), refinement, ALNS chains and BRKGA
-    population advance together, one graph replay per n-bucket per iteration
-    or generation, against the same work done instance by instance with
-    direct launches."""
+def batched_form(P, torch, count=256, cpi=4, iters=40, Np=128, gens=20, chunk=10, gchunk=2, limit_s=60.0):
+    """The batched form on 256 instances of uneven size against the plain
+    two-stage method run instance by instance.
+    Plain: for every instance in turn, the paper's start, `cpi` ALNS chains
+    for `iters` iterations (graph replay) and BRKGA of `Np` x `gens` from
+    the incumbent; its best is that instance's target.
+    Batched: every instance of an n-bucket in one set -- one construction
+    launch, one refinement state, one ALNS state (one captured iteration
+    replayed for all), one BRKGA state -- advanced chunk by chunk until
+    every instance has reached its plain target (or the time limit).
+    Reported: both wall times, the share of instances reaching their target
+    and when."""
     import synth
+    from paper_2602_23685_amd import pipeline
     insts = synth.batched_instances(count)
+    prm = P.alns_params(tuple_budget=2048, import_interval=0)
     edges = [0, 50, 150, 450, 10**9]
     buckets = [[i for i, x in enumerate(insts) if edges[b] <= x.n < edges[b + 1]] for b in range(4)]
     buckets = [b for b in buckets if b]
-    prm = P.alns_params(tuple_budget=4096, import_interval=0)
-    ne, nm = int(0.15 * Np), int(0.15 * Np)
-    # batched
-    log(f"batched form: {count} instances in {len(buckets)} n-buckets")
-    sets = [P.InstanceSet([insts[i] for i in b]) for b in buckets]
+    # instance i is the pos[i]-th of its bucket: its plain run draws as its
+    # chains and population do in the bucket's states, so both forms follow
+    # the same trajectories and reach the same bests
+    pos = {i: k for b in buckets for k, i in enumerate(b)}
+    log(f"batched form: plain two-stage method on {count} instances one by one")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    starts = [P.vrprpd_construct(S, P.CONS_SWEEP) for S in sets]
-    torch.cuda.synchronize()
-    t_cons_b = time.perf_counter() - t0
-    states, pops = [], []
-    for S, b, (o, r) in zip(sets, buckets, starts):
-        states.append(P.AlnsState(S, list(range(len(b))), cpi, prm, 11, o, r))
-        pops.append(P.BrkgaState(S, list(range(len(b))), Np, ne, nm, 0.7, 13))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rounds_b = [st.refine() for st in states]
-    t_ref_b = time.perf_counter() - t0
-    z_ref_b = np.zeros(count, np.int64)
-    for b, st in zip(buckets, states):
-        z_ref_b[b] = st.state()["zb"].reshape(-1, cpi).min(axis=1)
-    for st in states:
-        st.step(1)
-    for pp in pops:
-        pp.step(1)
-    torch.cuda.synchronize()
-    e0 = sum(st.state()["evals"] for st in states)
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        for st in states:
-            st.step(1)
-    torch.cuda.synchronize()
-    t_alns_b = time.perf_counter() - t0
-    e1 = sum(st.state()["evals"] for st in states)
-    t0 = time.perf_counter()
-    for pp in pops:
-        pp.step(gens)
-    torch.cuda.synchronize()
-    t_brkga_b = time.perf_counter() - t0
-    zb_b = np.zeros(count, np.int64)
-    for b, st in zip(buckets, states):
-        zb_b[b] = st.state()["zb"].reshape(-1, cpi).min(axis=1)
-    # instance by instance, direct launches
-    log("batched form: the same work instance by instance")
-    one_sets = [P.InstanceSet([x]) for x in insts]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    one_starts = [P.vrprpd_construct(S, P.CONS_SWEEP) for S in one_sets]
-    torch.cuda.synchronize()
-    t_cons_p = time.perf_counter() - t0
-    plain = []
-    for S, (o, r) in zip(one_sets, one_starts):
-        st = P.AlnsState(S, [0], cpi, prm, 11, o, r)
-        st.set_graph(False)
-        plain.append((S, st))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _, st in plain:
-        st.refine()
-    t_ref_p = time.perf_counter() - t0
-    z_ref_p = np.array([st.state()["zb"].min() for _, st in plain])
-    for _, st in plain:
-        st.step(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        for S, st in plain:
-            st.step(1)
-    torch.cuda.synchronize()
-    t_alns_p = time.perf_counter() - t0
-    # BRKGA per instance: decode + evolve launches per generation
-    keys = []
+    target = np.zeros(count, np.int64)
     for i, x in enumerate(insts):
-        pr, hi = synth.random_keys(Np, x.n, seed=500 + i)
-        keys.append((plain[i][0], torch.from_numpy(pr).cuda(), torch.from_numpy(hi).cuda()))
+        prm_i = P.alns_params(tuple_budget=2048, import_interval=0, chain_base=pos[i] * cpi)
+        r = pipeline.run(P.InstanceSet([x]), 0, prm_i, cpi, iters, 11, Np, gens, P.pop_seed(13, pos[i]))
+        target[i] = r["best"]
+    t_plain = time.perf_counter() - t0
+    # batched
+    log(f"batched form: the same method on {len(buckets)} n-buckets together")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for S, pr, hi in keys:
-        for gen in range(gens):
-            out = P.brkga_decode_eval(S, pr, hi)
-            pr, hi, _ = P.brkga_evolve(pr, hi, out["fitness"], ne, nm, 0.7, 13, gen)
-    torch.cuda.synchronize()
-    t_brkga_p = time.perf_counter() - t0
-    zb_p = np.array([st.state()["zb"].min() for _, st in plain])
-    ns = np.array([x.n for x in insts])
+    now = lambda: time.perf_counter() - t0
+    sets = [P.InstanceSet([insts[i] for i in b]) for b in buckets]
+    best = np.full(count, np.iinfo(np.int64).max)
+    reach_t = np.full(count, np.nan)
+
+    def update(b, z):
+        idx = np.array(buckets[b])
+        better = z < best[idx]
+        best[idx[better]] = z[better]
+        newly = idx[(best[idx] <= target[idx]) & np.isnan(reach_t[idx])]
+        reach_t[newly] = now()
+
+    states = []
+    for b, S in enumerate(sets):
+        ops, rt, _ = pipeline.paper_start(S, prm, 11)
+        st = P.AlnsState(S, list(range(len(buckets[b]))), cpi, prm, 11, ops, rt)
+        update(b, st.state()["zb"].reshape(-1, cpi).min(axis=1))
+        states.append(st)
+    t_start = now()
+    it = 0
+    while np.isnan(reach_t).any() and it < iters:
+        for st in states:
+            st.step(chunk)
+        it += chunk
+        for b, st in enumerate(states):
+            update(b, st.state()["zb"].reshape(-1, cpi).min(axis=1))
+    t_alns = now()
+    pops, g = [], 0
+    if np.isnan(reach_t).any():
+        for b, (S, st) in enumerate(zip(sets, states)):
+            zb = st.state()["zb"].reshape(-1, cpi)
+            P_, H_ = [], []
+            for k in range(len(buckets[b])):
+                _, o, r = st.best(int(k * cpi + zb[k].argmin()))
+                pp, hh = pipeline.warm_population(S, k, o, r, Np, P.pop_seed(13, k))
+                P_.append(pp)
+                H_.append(hh)
+            ne = nm = int(0.15 * Np)
+            pops.append(P.BrkgaState(S, list(range(len(buckets[b]))), Np, ne, nm, 0.7, 13, torch.cat(P_),
+                                     torch.cat(H_), decode_flags=P.DECODE_HINT_FIRST))
+        while np.isnan(reach_t).any() and now() < limit_s:
+            for pp in pops:
+                pp.step(gchunk)
+            g += gchunk
+            for b, pp in enumerate(pops):
+                update(b, pp.best()[0])
+    t_batched = now()
     for st in states:
         st.close()
-    for _, st in plain:
-        st.close()
+    for pp in pops:
+        pp.close()
+    ns = np.array([x.n for x in insts])
+    done = ~np.isnan(reach_t)
     return {"instances": count, "n_range": [int(ns.min()), int(ns.max())], "n_buckets": len(buckets),
-            "chains_per_instance": cpi, "alns_iterations": iters, "brkga_generations": gens, "population": Np,
-            "construct_seconds_batched": t_cons_b, "construct_seconds_one_by_one": t_cons_p,
-            "refine_seconds_batched": t_ref_b, "refine_seconds_one_by_one": t_ref_p,
-            "refine_rounds_batched": rounds_b, "refined_equal_one_by_one": bool(np.array_equal(z_ref_b, z_ref_p)),
-            "alns_seconds_batched": t_alns_b, "alns_seconds_one_by_one": t_alns_p,
-            "alns_speedup": t_alns_p / t_alns_b, "alns_evals_per_s_batched": (e1 - e0) / t_alns_b,
-            "brkga_seconds_batched": t_brkga_b, "brkga_seconds_one_by_one": t_brkga_p,
-            "brkga_speedup": t_brkga_p / t_brkga_b,
-            "mean_best_ratio_batched_vs_one_by_one": float(np.mean(zb_b / zb_p))}
+            "chains_per_instance": cpi, "alns_iterations": iters, "population": Np, "brkga_generations": gens,
+            "tuple_budget": 2048,
+            "plain": "one instance at a time: paper's start, ALNS (graph replay), BRKGA from the incumbent",
+            "plain_seconds": t_plain,
+            "batched_seconds_to_all_targets": t_batched if done.all() else None,
+            "batched_seconds": t_batched, "batched_start_seconds": t_start, "batched_alns_seconds": t_alns - t_start,
+            "batched_alns_iterations": it, "batched_brkga_generations": g,
+            "reached_fraction": float(done.mean()),
+            "reached_seconds_median": float(np.nanmedian(reach_t)) if done.any() else None,
+            "speedup_to_all_targets": (t_plain / t_batched) if done.all() else None,
+            "mean_best_ratio_batched_vs_plain": float(np.mean(best / target)),
+            "same_bests_as_plain": bool(np.array_equal(best, target))}
 
 
 def construction(P, torch, oracle_instances=64):
@@ -424,114 +416,230 @@ TSPLIB_NODES = [17, 21, 24, 29, 48, 51, 52, 100, 101, 202, 431, 666, 783, 1000]
 VARIANTS = ["base", "2x", "5x", "1R10", "1R20"]
 
 
-def hypothesis(P, torch, chains=8, iters=300):
+def signed_rank_p_greater(a, b):
+    """One-sided Wilcoxon signed-rank test of a > b on paired samples: zero
+    differences dropped, tied |differences| given their average rank, and
+    the p-value P(W+ >= observed) from the exact distribution of W+ over
+    all 2^n sign assignments (n <= 20 here)."""
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    d = d[d != 0]
+    nd = len(d)
+    if nd == 0:
+        return 1.0
+    order = np.argsort(np.abs(d), kind="stable")
+    ranks = np.empty(nd)
+    absd = np.abs(d)[order]
+    i = 0
+    while i < nd:
+        j = i
+        while j + 1 < nd and absd[j + 1] == absd[i]:
+            j += 1
+        ranks[order[i:j + 1]] = (i + j + 2) / 2.0
+        i = j + 1
+    w = ranks[d > 0].sum()
+    signs = ((np.arange(2 ** nd)[:, None] >> np.arange(nd)) & 1).astype(np.float64)
+    wplus = signs @ ranks
+    return float(np.mean(wplus >= w - 1e-9))
+
+
+def hypothesis(P, torch, chains=8, iters=300, Np=256, gens=30):
     """The processing-time hypothesis (Section 5.2) re-tested on synthetic
     stand-ins of the 14 benchmark sizes (depot + n customers, fleet m = 3,
     k = 5 below 24 customers, else m = 6, k = 4, R = m k) under the five
-    processing variants: all 70 instances run as one batched GPU pipeline
-    (construction, refinement, ALNS), then the best solution's Cross-Agent
-    and Interleaved shares; paired one-sided Wilcoxon signed-rank tests of
-    each variant against base over the 14 sizes."""
+    processing variants: all 70 instances run the two-stage method as one
+    batched GPU pipeline (construction, refinement, ALNS, BRKGA from each
+    instance's incumbent); the statistics are those of each instance's best
+    schedule (the paper takes them from BRKGA's best); paired one-sided
+    Wilcoxon signed-rank tests of each variant against base over the 14
+    sizes."""
     import synth
-    from scipy.stats import wilcoxon
+    from paper_2602_23685_amd import pipeline
     insts = []
     for v, rule in enumerate(VARIANTS):
-        for s, nodes in enumerate(TSPLIB_NODES):
+        for s_, nodes in enumerate(TSPLIB_NODES):
             n = nodes - 1
             m, k = (3, 5) if n < 24 else (6, 4)
-            insts.append(synth.make_instance(n, m, k, m * k, rule, seed=7000 + 100 * s + v))
+            insts.append(synth.make_instance(n, m, k, m * k, rule, seed=7000 + 100 * s_ + v))
     S = P.InstanceSet(insts)
+    I = len(insts)
+    prm = P.alns_params(tuple_budget=4096)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ops, rt = P.vrprpd_construct(S, P.CONS_SWEEP)
-    st = P.AlnsState(S, list(range(len(insts))), chains, P.alns_params(tuple_budget=4096), 17, ops, rt)
-    st.refine()
+    ops, rt, _ = pipeline.paper_start(S, prm, 17)
+    st = P.AlnsState(S, list(range(I)), chains, prm, 17, ops, rt)
     st.step(iters)
-    zb = st.state()["zb"].reshape(len(insts), chains)
-    best = zb.argmin(axis=1) + np.arange(len(insts)) * chains
-    B_ops = torch.zeros((len(insts), 2 * S.n_max), dtype=torch.uint16, device="cuda")
-    B_rt = torch.zeros((len(insts), S.m_max), dtype=torch.uint16, device="cuda")
-    for i, c in enumerate(best):
-        _, o, r = st.best(int(c))
+    zb = st.state()["zb"].reshape(I, chains)
+    z_alns = zb.min(axis=1)
+    B_ops = torch.zeros((I, 2 * S.n_max), dtype=torch.uint16, device="cuda")
+    B_rt = torch.zeros((I, S.m_max), dtype=torch.uint16, device="cuda")
+    prios, hints = [], []
+    for i in range(I):
+        _, o, r = st.best(int(i * chains + zb[i].argmin()))
         B_ops[i] = o
         B_rt[i] = r
-    off = torch.arange(len(insts), dtype=torch.int64, device="cuda")
-    cross, inter = P.vrprpd_solution_stats(S, B_ops, B_rt, inst=off.to(torch.int32), op_off=off * 2 * S.n_max,
+        pp, hh = pipeline.warm_population(S, i, o, r, Np, P.pop_seed(19, i))
+        prios.append(pp)
+        hints.append(hh)
+    st.close()
+    ne = nm = int(0.15 * Np)
+    pop = P.BrkgaState(S, list(range(I)), Np, ne, nm, 0.7, 19, torch.cat(prios), torch.cat(hints),
+                       decode_flags=P.DECODE_HINT_FIRST)
+    pop.step(gens)
+    bf, bp, bh = pop.best()
+    pop.close()
+    idx = torch.arange(I, dtype=torch.int32, device="cuda")
+    d = P.brkga_decode_eval(S, bp, bh, inst=idx, want_ops=True, flags=P.DECODE_HINT_FIRST)
+    unsch = d["unscheduled"].cpu().numpy()
+    z_brkga = np.where(unsch == 0, d["makespan"].cpu().numpy(), np.iinfo(np.int64).max)
+    for i in np.nonzero(z_brkga < z_alns)[0]:
+        B_ops[i] = d["ops"][i]
+        B_rt[i] = d["rt_end"][i]
+    off = torch.arange(I, dtype=torch.int64, device="cuda")
+    cross, inter = P.vrprpd_solution_stats(S, B_ops, B_rt, inst=idx, op_off=off * 2 * S.n_max,
                                            rt_off=off * S.m_max)
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     ns = np.array([x.n for x in insts], np.float64)
     xa = 100.0 * cross.cpu().numpy() / ns
     il = 100.0 * inter.cpu().numpy() / ns
-    st.close()
     k = len(TSPLIB_NODES)
-    out = {"instances": len(insts), "chains": chains, "alns_iterations": iters, "seconds": seconds,
-           "note": "synthetic stand-ins of the 14 benchmark sizes, one instance per variant; best ALNS solution "
-                   "(the paper extracts the statistics from BRKGA's best)"}
+    out = {"instances": I, "chains": chains, "alns_iterations": iters, "population": Np, "brkga_generations": gens,
+           "seconds": seconds, "brkga_improved": int((z_brkga < z_alns).sum()),
+           "note": "synthetic stand-ins of the 14 benchmark sizes, one instance per variant; statistics of each "
+                   "instance's best schedule of the two-stage method"}
     for v, rule in enumerate(VARIANTS):
         row = {"cross_agent_pct_mean": float(xa[v * k:(v + 1) * k].mean()),
                "interleaved_pct_mean": float(il[v * k:(v + 1) * k].mean())}
         if v:
             for name, arr in (("cross_agent", xa), ("interleaved", il)):
-                a, b = arr[v * k:(v + 1) * k], arr[:k]
-                row[f"{name}_wilcoxon_p_greater_than_base"] = (
-                    float(wilcoxon(a, b, alternative="greater").pvalue) if np.any(a != b) else 1.0)
+                row[f"{name}_wilcoxon_p_greater_than_base"] = signed_rank_p_greater(arr[v * k:(v + 1) * k], arr[:k])
         out[rule] = row
     return out
 
 
-def learned_form(P, torch, n=500, chains=32, rec_iters=200, train_steps=1500, ab_iters=200, K=8, eps=0.1):
-    """The learned form on the cfg5 instance shape: plain ALNS records
-    (removal set, makespan change) pairs, the network trains on them with the
-    library's kernels, then learned and plain ALNS run from the same start;
-    reported: held-out loss, each run's best, and the wall time the learned
-    run needs to reach the plain run's final best."""
+def two_stage_chunked(P, torch, S, ops, rt, prm, chains, iters, seed, Np, gens, bseed, target=None, mlp=None,
+                      K=8, eps=0.1, chunk=10, gchunk=2, limit_s=60.0):
+    """The two-stage method on instance 0 of S from (ops, rt), advanced in
+    chunks of `chunk` ALNS iterations, then `gchunk` BRKGA generations, with
+    the best makespan read after each chunk.  With a target it stops as soon
+    as the best reaches it (BRKGA then runs past `gens` until the time
+    limit); with an ALNS network (mlp) the ALNS stage uses the learned
+    proposal.  Returns the best, the time it was reached (or None) and the
+    (seconds, best) history."""
+    from paper_2602_23685_amd import pipeline
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    st = P.AlnsState(S, [0], chains, prm, seed, ops, rt)
+    if mlp is not None:
+        st.set_learned(mlp, K=K, eps=eps)
+    best = int(st.state()["zb"].min())
+    hist, at = [(now(), best)], None
+    it = 0
+    while it < iters and (target is None or best > target):
+        st.step(chunk)
+        it += chunk
+        best = min(best, int(st.state()["zb"].min()))
+        hist.append((now(), best))
+    if target is not None and best <= target:
+        at = now()
+    g = 0
+    if at is None:
+        _, a_ops, a_rt = st.best(-1)
+        prio, hint = pipeline.warm_population(S, 0, a_ops, a_rt, Np, bseed)
+        ne = nm = int(0.15 * Np)
+        pop = P.BrkgaState(S, [0], Np, ne, nm, 0.7, bseed, prio, hint, decode_flags=P.DECODE_HINT_FIRST)
+        while (g < gens) if target is None else (best > target and now() < limit_s):
+            pop.step(gchunk)
+            g += gchunk
+            best = min(best, int(pop.best()[0][0]))
+            hist.append((now(), best))
+        if target is not None and best <= target:
+            at = now()
+        pop.close()
+    st.close()
+    first = next(t for t, z in hist if z == best)     # when the final best was first held
+    return {"best": best, "reached_at": at, "first_at_best": first, "seconds": now(), "alns_iterations": it,
+            "brkga_generations": g, "history": [(round(t, 4), z) for t, z in hist[-6:]]}
+
+
+def learned_form(P, torch, n=500, train_insts=8, rec_chains=128, rec_iters=1000, rec_budget=1024, epochs=1,
+                 batch_sets=512, lr=1e-3, tests=5, chains=32, iters=200, Np=512, gens=20, K=8, eps=0.1):
+    """The learned form on the 500-customer shape (m = 10, k = 8, R = 50,
+    base rule).  Plain ALNS records (removal set, makespan change) pairs on
+    `train_insts` instances (rec_chains chains x rec_iters iterations each:
+    >= 1M pairs); the network trains on them with the library's kernels for
+    `epochs` passes.  Then on `tests` other instances of the same shape the
+    plain two-stage method (ALNS 32 chains x 200 iterations with 16,384
+    tuples, BRKGA 512 x 20 from its incumbent) sets the target, and the
+    two-stage method with the learned ALNS proposal runs from the same start
+    until it reaches it.  Reported per instance and as medians; the
+    recording and training time is reported apart and amortised over the
+    test instances."""
     import synth
     from paper_2602_23685_amd import learned
-    inst = synth.make_instance(n, 10, 8, 50, "base", seed=5005)
-    ops, rt = synth.round_robin_solution(inst, vehicles=10)
-    S = P.InstanceSet([inst])
-    prm = P.alns_params(tuple_budget=16384, import_interval=100)
-    mk = lambda seed: P.AlnsState(S, [0], chains, prm, seed, torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda())
-    log(f"learned form: recording {rec_iters} x {chains} sets")
-    tr_run, te_run = mk(101), mk(102)
-    t0 = time.perf_counter()
-    sets = learned.record(tr_run, rec_iters)
-    t_rec = time.perf_counter() - t0
-    learned.record(te_run, max(10, rec_iters // 5))
-    _, q = tr_run.record_info()
-    M = P.Mlp(max_rows=max(512 * q, chains * n), seed=7)
-    log(f"learned form: training {train_steps} steps")
+    mk = lambda seed: synth.make_instance(n, 10, 8, 50, "base", seed=seed)
+    train = [mk(5100 + i) for i in range(train_insts)]
+    S_tr = P.InstanceSet(train)
+    starts = [synth.round_robin_solution(x, vehicles=10) for x in train]
+    r_ops = torch.from_numpy(np.stack([o for o, _ in starts])).cuda()
+    r_rt = torch.from_numpy(np.stack([r for _, r in starts])).cuda()
+    rec = P.AlnsState(S_tr, list(range(train_insts)), rec_chains, P.alns_params(tuple_budget=rec_budget), 101,
+                      r_ops, r_rt)
+    log(f"learned form: recording {train_insts} x {rec_chains} chains x {rec_iters} iterations")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    learned.train(M, tr_run, steps=train_steps, batch_sets=512, lr=1e-3, momentum=0.9)
+    sets = learned.record(rec, rec_iters)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    _, q = rec.record_info()
+    M = P.Mlp(max_rows=max(batch_sets * q, chains * n), seed=7)
+    steps = max(1, epochs * sets // batch_sets)
+    log(f"learned form: training {steps} steps on {sets} sets")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    learned.train(M, rec, steps=steps, batch_sets=batch_sets, lr=lr, momentum=0.9)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    loss, base = learned.held_out(M, te_run)
-    log("learned form: A/B")
-    res = {}
-    for name in ("plain", "learned"):
-        st = mk(103)
-        if name == "learned":
-            st.set_learned(M, K=K, eps=eps)
-        st.step(1)
-        torch.cuda.synchronize()
-        hist, t0 = [], time.perf_counter()
-        for it in range(ab_iters // 10):
-            st.step(10)
-            hist.append((time.perf_counter() - t0, int(st.state()["zb"].min())))
-        res[name] = hist
-    target = res["plain"][-1][1]
-    reach = next((t for t, z in res["learned"] if z <= target), None)
-    return {"n": n, "m": 10, "k": 8, "R": 50, "rule": "base", "chains": chains, "recorded_sets": sets,
-            "record_seconds": t_rec, "train_steps": train_steps, "train_batch_sets": 512,
-            "train_seconds": t_train, "heldout_loss": loss, "heldout_mean_predictor_loss": base,
-            "ab_iterations": ab_iters, "K": K, "eps": eps,
-            "plain_best": res["plain"][-1][1], "learned_best": res["learned"][-1][1],
-            "plain_seconds": res["plain"][-1][0], "learned_seconds": res["learned"][-1][0],
-            "learned_seconds_to_plain_best": reach,
-            "note": "training pairs from plain ALNS on this instance; the paper's 1M-pair scale is "
-                    "not run by the benchmark"}
+    rec.close()
+    prm = P.alns_params(tuple_budget=16384, import_interval=100)
+    rows, held = [], []
+    for t in range(tests):
+        x = mk(5200 + t)
+        S = P.InstanceSet([x])
+        o, r = synth.round_robin_solution(x, vehicles=10)
+        d_o, d_r = torch.from_numpy(o).cuda(), torch.from_numpy(r).cuda()
+        if t == 0:   # held-out loss on this instance's plain records
+            te = P.AlnsState(S, [0], 32, P.alns_params(tuple_budget=rec_budget), 102, d_o, d_r)
+            learned.record(te, 20)
+            held = learned.held_out(M, te)
+            te.close()
+        log(f"learned form: test instance {t}")
+        plain = two_stage_chunked(P, torch, S, d_o, d_r, prm, chains, iters, 103 + t, Np, gens, 104 + t)
+        lrn = two_stage_chunked(P, torch, S, d_o, d_r, prm, chains, iters, 103 + t, Np, gens, 104 + t,
+                                target=plain["best"], mlp=M, K=K, eps=eps, limit_s=3 * plain["seconds"] + 5)
+        rows.append({"instance_seed": 5200 + t, "plain_best": plain["best"],
+                     "plain_seconds_to_its_best": plain["first_at_best"], "plain_seconds": plain["seconds"],
+                     "learned_best": lrn["best"], "learned_seconds_to_plain_best": lrn["reached_at"],
+                     "learned_alns_iterations": lrn["alns_iterations"],
+                     "learned_brkga_generations": lrn["brkga_generations"]})
+    M.close()
+    reached = [r for r in rows if r["learned_seconds_to_plain_best"] is not None]
+    ratio = [r["learned_seconds_to_plain_best"] / r["plain_seconds_to_its_best"] for r in reached]
+    return {"n": n, "m": 10, "k": 8, "R": 50, "rule": "base", "train_instances": train_insts,
+            "recorded_sets": sets, "record_chains": train_insts * rec_chains, "record_iterations": rec_iters,
+            "record_tuple_budget": rec_budget, "record_seconds": t_rec, "train_steps": steps,
+            "train_batch_sets": batch_sets, "train_seconds": t_train,
+            "heldout_loss": held[0], "heldout_mean_predictor_loss": held[1],
+            "test_instances": tests, "K": K, "eps": eps, "chains": chains, "alns_iterations": iters,
+            "population": Np, "brkga_generations": gens,
+            "reached": len(reached), "time_ratio_learned_vs_plain": ratio,
+            "time_ratio_median": float(np.median(ratio)) if ratio else None,
+            "time_ratio_range": [float(min(ratio)), float(max(ratio))] if ratio else None,
+            "record_and_train_seconds_per_test_instance": (t_rec + t_train) / tests,
+            "per_instance": rows,
+            "note": "training pairs from plain ALNS on other instances of the same shape; the learned run counts "
+                    "only its own search time, record_and_train_seconds_per_test_instance is the amortised cost"}
 
 
 def main():
@@ -543,6 +651,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-race", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
+    ap.add_argument("--phases", default=None,
+                    help="comma list of the phases after the timed steps to run (race, construction, batched, "
+                         "hypothesis, learned, cpu); default: all not switched off by the --no-* flags")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 256 MiB three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -764,19 +875,32 @@ def main():
              "unit_is": "one chromosome: 2n fp32 priorities + 2n fp32 hints read, 20 B written"},
         ],
     }
-    if not args.no_race:
+    if args.phases is not None:
+        phases = set(x.strip() for x in args.phases.split(",") if x.strip())
+    else:
+        phases = {"race", "construction", "batched", "hypothesis", "learned", "cpu"}
+        if args.no_race:
+            phases.discard("race")
+        if args.no_forms:
+            phases -= {"construction", "batched", "hypothesis", "learned"}
+        if args.no_cpu_baseline:
+            phases.discard("cpu")
+    if "race" in phases:
         log("time to oracle-best (n=16)")
         out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
         log("time to oracle-best (n=100, n=1000)")
         out["time_to_oracle_best_large"] = race_to_oracle(P, torch)
-    if not args.no_forms:
+    if "construction" in phases:
         log("construction heuristics")
         out["construction"] = construction(P, torch)
+    if "batched" in phases:
         out["batched_form"] = batched_form(P, torch)
+    if "hypothesis" in phases:
         log("processing-time hypothesis")
         out["hypothesis"] = hypothesis(P, torch)
+    if "learned" in phases:
         out["learned_form"] = learned_form(P, torch)
-    if not args.no_cpu_baseline:
+    if "cpu" in phases:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -474,8 +474,11 @@ int brkga_state_load(brkga_state* st, const void* buf, int64_t bytes, void* stre
  * notes and followed exactly, so a CPU implementation of the same readings
  * reproduces every chain's trajectory.
  * Random draws: Philox4x32-10 keyed by seed, counter (a / 4, iteration,
- * chain, 'ALNS'): a = 0 destroy roulette, 1 repair roulette, 2 q,
- * 8 annealing, 16.. destroy operator. */
+ * chain_base + chain, 'ALNS'): a = 0 destroy roulette, 1 repair roulette,
+ * 2 q, 8 annealing, 16.. destroy operator.  chain_base (default 0) shifts
+ * the chains' ids in the draws: a state over one instance with chain_base =
+ * k * chains_per_inst follows, chain for chain, the trajectories of the
+ * k-th instance's chains in a state over several instances. */
 typedef struct {
     double T0, alpha, reheat, gate;
     int32_t stag_limit, tau;
@@ -489,6 +492,7 @@ typedef struct {
     int32_t ls_repos_interval;
     int32_t ls_reloc_interval;
     int32_t ls_budget;
+    int32_t chain_base;
 } alns_params;
 
 typedef struct alns_state alns_state;

@@ -444,7 +444,8 @@ class AlnsParams(C.Structure):
                 ("sigma1", C.c_int32), ("sigma2", C.c_int32), ("sigma3", C.c_int32),
                 ("w_min", C.c_double), ("q_min", C.c_int32), ("q_max", C.c_int32),
                 ("tuple_budget", C.c_int32), ("import_interval", C.c_int32), ("op_mask", C.c_uint32),
-                ("ls_repos_interval", C.c_int32), ("ls_reloc_interval", C.c_int32), ("ls_budget", C.c_int32)]
+                ("ls_repos_interval", C.c_int32), ("ls_reloc_interval", C.c_int32), ("ls_budget", C.c_int32),
+                ("chain_base", C.c_int32)]
 
 
 def alns_params(**kw):

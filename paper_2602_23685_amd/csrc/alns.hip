@@ -174,9 +174,9 @@ __global__ void k_begin(AlnsDev a)
     if (qmax > I.n) qmax = I.n;
     if (qmin > qmax) qmin = qmax;
     const uint32_t dmask = a.prm.op_mask & 0x3Fu, rmask = (a.prm.op_mask >> 8) & 0xFu;
-    const int di = roulette(a.wD + kND * c, kND, dmask, unit_d(adraw(a.seed, 0, it, (uint32_t)c)));
-    const int ri = roulette(a.wR + kNR * c, kNR, rmask, unit_d(adraw(a.seed, 1, it, (uint32_t)c)));
-    const int q = qmin + uint_below(adraw(a.seed, 2, it, (uint32_t)c), qmax - qmin + 1);
+    const int di = roulette(a.wD + kND * c, kND, dmask, unit_d(adraw(a.seed, 0, it, (uint32_t)c + (uint32_t)a.prm.chain_base)));
+    const int ri = roulette(a.wR + kNR * c, kNR, rmask, unit_d(adraw(a.seed, 1, it, (uint32_t)c + (uint32_t)a.prm.chain_base)));
+    const int q = qmin + uint_below(adraw(a.seed, 2, it, (uint32_t)c + (uint32_t)a.prm.chain_base), qmax - qmin + 1);
     a.di[c] = di;
     a.ri[c] = ri;
     a.q[c] = q;
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_destroy(AlnsDev a)
     }
     __syncthreads();
     const long long* gain = a.gains + (int64_t)c * (a.N + 1);
-    const uint32_t uc = (uint32_t)c;
+    const uint32_t uc = (uint32_t)c + (uint32_t)a.prm.chain_base;
     if (di == 0) {                                   // random: partial Fisher-Yates
         int* perm = reinterpret_cast<int*>(key);
         for (int x = threadIdx.x; x < n; x += blockDim.x) perm[x] = x + 1;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void k_apply(AlnsDev a, int use_scores)
     unsigned char* flag = smem;
     if (threadIdx.x == 0) {
         int k = 0;
-        if (use_scores && a.K > 1 && !(unit_d(adraw(a.seed, 3, it, (uint32_t)c)) < a.eps)) {
+        if (use_scores && a.K > 1 && !(unit_d(adraw(a.seed, 3, it, (uint32_t)c + (uint32_t)a.prm.chain_base)) < a.eps)) {
             // lowest predicted makespan change; ties to the lower index
             float best = 0.f;
             for (int j = 0; j < a.K; ++j) {
@@ -1505,7 +1505,7 @@ __global__ __launch_bounds__(256) void k_accept(AlnsDev a)
                     copyB = 1;
                 }
             } else {
-                const double u = unit_d(adraw(a.seed, 8, it, (uint32_t)c));
+                const double u = unit_d(adraw(a.seed, 8, it, (uint32_t)c + (uint32_t)a.prm.chain_base));
                 const double pacc = det_exp(-((double)zn - (double)a.z[c]) / *T);
                 if (u < pacc) {
                     a.z[c] = zn;
@@ -2466,7 +2466,7 @@ static bool same_params(const alns_params& a, const alns_params& b)
            a.sigma2 == b.sigma2 && a.sigma3 == b.sigma3 && a.w_min == b.w_min && a.q_min == b.q_min &&
            a.q_max == b.q_max && a.tuple_budget == b.tuple_budget && a.import_interval == b.import_interval &&
            a.op_mask == b.op_mask && a.ls_repos_interval == b.ls_repos_interval &&
-           a.ls_reloc_interval == b.ls_reloc_interval && a.ls_budget == b.ls_budget;
+           a.ls_reloc_interval == b.ls_reloc_interval && a.ls_budget == b.ls_budget && a.chain_base == b.chain_base;
 }
 
 // Everything an iteration reads from the previous one: both solutions of

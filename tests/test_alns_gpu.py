@@ -223,3 +223,38 @@ def test_alns_full_scale_parity(orc, P, name, kw):
         assert np.array_equal(brt.cpu().numpy()[:10], ref["best_rt"][ch])
         assert np.array_equal(bops.cpu().numpy()[:2000], ref["best_ops"][ch])
     st.close()
+
+
+def test_chain_base_matches_the_chains_of_a_batched_state(orc, P):
+    """A one-instance state with chain_base = k * chains draws as the k-th
+    instance's chains of a state over several instances: trajectories and
+    bests equal, and equal to the oracle's run with those chain ids."""
+    insts = [synth.make_instance(n, m, 4, 4 * m, "2x", seed=9500 + n) for n, m in ((30, 3), (45, 4), (25, 3))]
+    S = P.InstanceSet(insts)
+    cpi, iters, seed = 3, 15, 606
+    kw = dict(tuple_budget=300, import_interval=5)
+    starts = [synth.round_robin_solution(x) for x in insts]
+    N, Mx = S.n_max, S.m_max
+    ops = np.zeros((3, 2 * N), np.uint16)
+    rts = np.zeros((3, Mx), np.uint16)
+    for i, (o, r) in enumerate(starts):
+        ops[i, :len(o)] = o
+        rts[i, :len(r)] = r
+    big = P.AlnsState(S, [0, 1, 2], cpi, P.alns_params(**kw), seed, torch.from_numpy(ops).cuda(),
+                      torch.from_numpy(rts).cuda())
+    tb = big.set_trace(iters)
+    big.step(iters)
+    zb_big = big.state()["zb"]
+    tb = tb.cpu().numpy()
+    for k, x in enumerate(insts):
+        one = P.AlnsState(P.InstanceSet([x]), [0], cpi, P.alns_params(chain_base=k * cpi, **kw), seed,
+                          torch.from_numpy(starts[k][0]).cuda(), torch.from_numpy(starts[k][1]).cuda())
+        to = one.set_trace(iters)
+        one.step(iters)
+        assert np.array_equal(to.cpu().numpy(), tb[k * cpi:(k + 1) * cpi]), k
+        assert np.array_equal(one.state()["zb"], zb_big[k * cpi:(k + 1) * cpi]), k
+        ref = orc.alns_run(x, orc.alns_params(**kw), cpi, iters, seed, starts[k][0], starts[k][1], trace=True,
+                           chain0=k * cpi)
+        assert np.array_equal(to.cpu().numpy(), ref["trace"]), k
+        one.close()
+    big.close()
