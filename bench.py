@@ -563,6 +563,51 @@ def two_stage_chunked(P, torch, S, ops, rt, prm, chains, iters, seed, Np, gens, 
             "brkga_generations": g, "history": [(round(t, 4), z) for t, z in hist[-6:]]}
 
 
+MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 matrix peak, flop/s
+
+
+def mlp_roofline(P, torch, row_counts=(16384, 131072), reps=10):
+    """Matrix-core rate of the network's hand-written GEMMs (gemm_kernel,
+    bf16 MFMA with fp32 accumulation): forward, and forward + backward, on
+    `rows` random feature rows, HIP events on the launch stream.  Flops:
+    2 rows (64*256 + 256*256 + 256*256) forward; backward adds the weight
+    gradients of the three layers and the input gradients of the upper two,
+    2 rows (147,456 + 131,072)."""
+    out = []
+    stream = torch.cuda.current_stream()
+    fwd_per_row = 2 * (64 * 256 + 256 * 256 + 256 * 256)
+    bwd_per_row = 2 * (64 * 256 + 256 * 256 + 256 * 256 + 256 * 256 + 256 * 256)
+    for rows in row_counts:
+        M = P.Mlp(max_rows=rows, seed=3)
+        g = torch.Generator(device="cuda").manual_seed(rows)
+        x = (torch.rand((rows, 64), generator=g, device="cuda") * 2 - 1).to(torch.bfloat16)
+        y = torch.empty(rows, dtype=torch.float32, device="cuda")
+        dy = torch.full((rows,), 1e-3, dtype=torch.float32, device="cuda")
+
+        def timed(fn):
+            fn()
+            ev = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                ev.append((a, b))
+            torch.cuda.synchronize()
+            return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+        t_f = timed(lambda: M.forward(x, y))
+        t_fb = timed(lambda: (M.forward(x, y), M.backward(dy)))
+        M.close()
+        f_f, f_fb = fwd_per_row * rows, (fwd_per_row + bwd_per_row) * rows
+        out.append({"rows": rows, "forward_ms": t_f, "forward_tflops": f_f / (t_f * 1e-3) / 1e12,
+                    "forward_backward_ms": t_fb, "forward_backward_tflops": f_fb / (t_fb * 1e-3) / 1e12,
+                    "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK / 1e12,
+                    "frac_forward": f_f / (t_f * 1e-3) / MFMA_BF16_PEAK,
+                    "frac_forward_backward": f_fb / (t_fb * 1e-3) / MFMA_BF16_PEAK})
+    return out
+
+
 def learned_form(P, torch, n=500, train_insts=8, rec_chains=128, rec_iters=1000, rec_budget=1024, epochs=1,
                  batch_sets=512, lr=1e-3, tests=5, chains=32, iters=200, Np=512, gens=20, K=8, eps=0.1):
     """The learned form on the 500-customer shape (m = 10, k = 8, R = 50,
@@ -624,6 +669,7 @@ def learned_form(P, torch, n=500, train_insts=8, rec_chains=128, rec_iters=1000,
                      "learned_alns_iterations": lrn["alns_iterations"],
                      "learned_brkga_generations": lrn["brkga_generations"]})
     M.close()
+    mlp_roof = mlp_roofline(P, torch)
     reached = [r for r in rows if r["learned_seconds_to_plain_best"] is not None]
     ratio = [r["learned_seconds_to_plain_best"] / r["plain_seconds_to_its_best"] for r in reached]
     return {"n": n, "m": 10, "k": 8, "R": 50, "rule": "base", "train_instances": train_insts,
@@ -637,7 +683,7 @@ def learned_form(P, torch, n=500, train_insts=8, rec_chains=128, rec_iters=1000,
             "time_ratio_median": float(np.median(ratio)) if ratio else None,
             "time_ratio_range": [float(min(ratio)), float(max(ratio))] if ratio else None,
             "record_and_train_seconds_per_test_instance": (t_rec + t_train) / tests,
-            "per_instance": rows,
+            "per_instance": rows, "mlp_roofline": mlp_roof,
             "note": "training pairs from plain ALNS on other instances of the same shape; the learned run counts "
                     "only its own search time, record_and_train_seconds_per_test_instance is the amortised cost"}
 
@@ -808,6 +854,11 @@ def main():
     bytes_per_eval = 2 * 2 * inst.n + 2 * inst.m + 4 + 4
     achieved = bytes_per_eval * B / (eval_ms * 1e-3)
     feasible = float((st == 0).float().mean().item())
+    # secondary bound: staging a candidate reads 2n legs, re-reads the m
+    # route starts from the depot and reads the m return legs, at random
+    # entries of the 2 MB travel-time matrix
+    gather_rate, _ = P.vrprpd_gather_rate(S, 0)
+    reads_per_eval = 2 * inst.n + 2 * inst.m
     # insertion scan: LDS bytes of one exact evaluation of base + tuple (per
     # customer: two op codes and two legs read, p and ready[] for the drop,
     # ready[] for the pickup = 20 B)
@@ -861,6 +912,11 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_eval * B,
             "kernel": "eval_kernel", "kernel_ms": eval_ms, "bytes_per_unit": bytes_per_eval,
             "units_per_launch": B,
+            "secondary": {"bound": "l2_gather", "reads_per_unit": reads_per_eval,
+                          "measured_reads_per_s": gather_rate, "ceiling_units_per_s": gather_rate / reads_per_eval,
+                          "frac": value / (gather_rate / reads_per_eval),
+                          "how": "vrprpd_gather_rate: 2^29 random 2-byte reads of the instance's matrix, "
+                                 "8192 x 256 threads, 16 in flight each"},
         },
         "roofline_components": [
             {"kernel": "scan_kernel (vrprpd_insert_scan)", "bound": "lds",

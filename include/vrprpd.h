@@ -145,6 +145,17 @@ int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const 
                          int32_t* makespan, uint32_t* status, int32_t reps, int32_t* ng_out, int32_t* step_out,
                          float* ms_out, void* stream);
 
+/* Rate of random reads of one instance's travel-time matrix (measurement
+ * for vrprpd_eval's secondary bound: staging a candidate of 2n ops makes
+ * 2n + m such reads, one per leg, at entries spread over the whole matrix).
+ * blocks x 256 threads each make per_thread reads (a multiple of 16, 16 in
+ * flight) at hash-chosen entries of instance `inst`; sink [blocks] int32
+ * device out (block sums).  One warm-up launch, then one timed launch
+ * between HIP events on the stream; *ms_out (host) receives its
+ * milliseconds.  Synchronous.  Errors: EINVAL, EHIP. */
+int vrprpd_gather_rate(const vrprpd_set* set, int32_t inst, int32_t blocks, int32_t per_thread, int32_t* sink,
+                       float* ms_out, void* stream);
+
 /* One way to put a removed customer back into a partial solution
  * (Section 4.2.3, repair operators): its drop into route vD before index pD
  * (pD = len(vD) appends), its pickup into route vP before index pP, where pP

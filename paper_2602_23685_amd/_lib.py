@@ -45,6 +45,7 @@ SIGNATURES = {
     "vrprpd_set_info": (C.c_int, [_P, _P, _P, _P, _P]),
     "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "vrprpd_autotune_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P, _P, _P]),
+    "vrprpd_gather_rate": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P]),
     "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_decode_eval_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
@@ -213,6 +214,16 @@ def vrprpd_autotune_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt
                                        ALLOW_PARTIAL if partial else 0, _dptr(mk), _dptr(st), reps, C.byref(w),
                                        C.byref(k), ms.ctypes.data, _stream(stream)))
     return w.value, k.value, ms
+
+
+def vrprpd_gather_rate(S: InstanceSet, inst=0, blocks=8192, per_thread=256, stream=None):
+    """Random reads of instance inst's travel-time matrix per second (see
+    vrprpd_gather_rate in vrprpd.h): (reads per second, milliseconds)."""
+    sink = torch.empty(blocks, dtype=torch.int32, device="cuda")
+    ms = C.c_float()
+    _check(load().vrprpd_gather_rate(S.handle, inst, blocks, per_thread, _dptr(sink), C.byref(ms), _stream(stream)))
+    reads = blocks * 256 * per_thread
+    return reads / (ms.value * 1e-3), ms.value
 
 
 def vrprpd_insert_scan(S: InstanceSet, base_ops, base_rt, seg_off, tuples, num_bases=1,

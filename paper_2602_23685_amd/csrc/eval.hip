@@ -362,6 +362,39 @@ static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, co
     return set->dist16 ? dispatch_gl<uint16_t>(a, sh, st) : dispatch_gl<int32_t>(a, sh, st);
 }
 
+// Random reads of one instance's travel-time matrix: thread t makes `per`
+// reads at uniformly distributed entries (a multiplicative hash of (t, i),
+// scaled into [0, (n+1)^2)), 16 in flight per thread, and adds them up; the
+// block's sum is written so that no read is dropped.
+template <typename DT>
+__global__ __launch_bounds__(256) void gather_rate_kernel(const DT* D, uint32_t entries, int per, int32_t* sink)
+{
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    uint32_t acc = 0;
+    for (int i0 = 0; i0 < per; i0 += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            uint32_t x = t * 0x9E3779B1u + (uint32_t)(i0 + u) * 0x85EBCA77u;
+            x ^= x >> 15;
+            x *= 0x2C1B3C6Du;
+            x ^= x >> 12;
+            const uint32_t idx = (uint32_t)(((uint64_t)x * entries) >> 32);
+            v[u] = (uint32_t)D[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    __shared__ uint32_t red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = (int32_t)red[0];
+}
+
 }  // namespace vrprpd
 
 using namespace vrprpd;
@@ -441,5 +474,41 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     set->eval_tuned[{n_lds, m_max}] = {bw, bs};
     if (ng_out) *ng_out = bw;
     if (step_out) *step_out = bs;
+    return VRPRPD_OK;
+}
+
+extern "C" int vrprpd_gather_rate(const vrprpd_set* set, int32_t inst, int32_t blocks, int32_t per_thread,
+                                  int32_t* sink, float* ms_out, void* stream)
+{
+    if (!set || inst < 0 || inst >= set->num_inst || blocks < 1 || per_thread < 16 || per_thread % 16 || !sink ||
+        !ms_out)
+        return set_error(VRPRPD_EINVAL, "vrprpd_gather_rate: need a set, an instance index, blocks >= 1, "
+                                        "per_thread a positive multiple of 16, sink and ms_out");
+    const InstDev& h = set->host[inst];
+    const uint32_t entries = (uint32_t)((h.n + 1) * (int64_t)(h.n + 1));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    VRP_HIP(hipEventCreate(&e0));
+    VRP_HIP(hipEventCreate(&e1));
+    auto launch = [&]() {
+        if (set->dist16)
+            hipLaunchKernelGGL(gather_rate_kernel<uint16_t>, dim3(blocks), dim3(256), 0, st,
+                               static_cast<const uint16_t*>(set->d_dist) + h.d_off, entries, per_thread, sink);
+        else
+            hipLaunchKernelGGL(gather_rate_kernel<int32_t>, dim3(blocks), dim3(256), 0, st,
+                               static_cast<const int32_t*>(set->d_dist) + h.d_off, entries, per_thread, sink);
+    };
+    launch();   // warm the matrix into the caches
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess) {
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms_out, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_error(e, "vrprpd_gather_rate");
     return VRPRPD_OK;
 }

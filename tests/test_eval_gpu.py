@@ -184,3 +184,19 @@ def test_autotuned_shapes_agree_with_oracle(orc, P, n, m, B):
     pick = synth.rng(n).choice(B, size=min(B, 300), replace=False)
     omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
     assert np.array_equal(mk[pick], omk) and np.array_equal(st[pick], ost)
+
+
+def test_gather_rate_measurement(P):
+    """vrprpd_gather_rate runs (16-bit and 32-bit matrices) and reports a
+    positive rate; bad arguments are refused."""
+    inst = synth.make_instance(200, 4, 5, 20, "base", seed=12)
+    rate, ms = P.vrprpd_gather_rate(P.InstanceSet([inst]), 0, blocks=64, per_thread=32)
+    assert rate > 0 and ms > 0
+    inst.d = (inst.d.astype(np.int64) * 500).astype(np.int32)
+    S = P.InstanceSet([inst])
+    assert S.dist16 == 0
+    assert P.vrprpd_gather_rate(S, 0, blocks=64, per_thread=32)[0] > 0
+    with pytest.raises(P.VrpError):
+        P.vrprpd_gather_rate(S, 1, blocks=64, per_thread=32)
+    with pytest.raises(P.VrpError):
+        P.vrprpd_gather_rate(S, 0, blocks=64, per_thread=20)
