@@ -699,7 +699,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--phases", default=None,
                     help="comma list of the phases after the timed steps to run (race, construction, batched, "
-                         "hypothesis, learned, cpu); default: all not switched off by the --no-* flags")
+                         "hypothesis, learned, mlp, cpu); default: all not switched off by the --no-* flags")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 256 MiB three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -956,6 +956,9 @@ def main():
         out["hypothesis"] = hypothesis(P, torch)
     if "learned" in phases:
         out["learned_form"] = learned_form(P, torch)
+    elif "mlp" in phases:   # the network's GEMM rate alone (the learned form reports it too)
+        log("network GEMM rate")
+        out["mlp_roofline"] = mlp_roofline(P, torch)
     if "cpu" in phases:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds)
