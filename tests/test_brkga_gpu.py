@@ -192,3 +192,43 @@ def test_batched_populations_match_oracle(orc, P, graph, flags):
         assert np.array_equal(pop_p[p * Np:(p + 1) * Np, :G].view(np.uint32), op_.view(np.uint32)), p
         assert np.array_equal(pop_h[p * Np:(p + 1) * Np, :G].view(np.uint32), oh_.view(np.uint32)), p
     st.close()
+
+
+@pytest.mark.parametrize("flags", [0, 1], ids=["selectvehicle", "hintfirst"])
+def test_packed_and_plain_vehicle_minimum_agree_on_ties(orc, P, flags):
+    """The decoder's two vehicle-minimum paths (packed time << 4 | rank keys
+    when every time of the set is below 2^27, a plain minimum and tie ballot
+    otherwise) on the same decoding problems: a 5-vehicle instance on a small
+    integer grid (many equal travel times, so many completion-time ties), decoded
+    alone (packed) and inside a set whose second instance has travel times
+    large enough to switch the whole set to the plain path."""
+    g = np.random.Generator(np.random.Philox(key=4141))
+    n, m = 40, 5
+    pts = g.integers(0, 4, size=(n + 1, 2))
+    d = (np.abs(pts[:, None, :] - pts[None, :, :]).sum(axis=2) * 3).astype(np.int32)   # Manhattan: ties
+    d[d == 0] = 1
+    np.fill_diagonal(d, 0)
+    p = np.concatenate([[0], g.integers(0, 4, size=n)]).astype(np.int32)
+    inst = synth.instance_from_matrix(d, p, m=m, k=3, R=10)
+    big = synth.make_instance(30, 3, 4, 12, "base", seed=4142)
+    big.p = (big.p.astype(np.int64) * (150_000_000 // int(big.p.sum()))).astype(np.int32)   # sum p > 2^27
+    alone, mixed = P.InstanceSet([inst]), P.InstanceSet([inst, big])
+    assert alone.dist16 == 1 and mixed.dist16 == 1         # same 16-bit matrix layout on both paths
+    B = 256
+    prio, hint = synth.random_keys(B, n, seed=4143, special=True)
+    prio[B // 2:] = np.round(prio[B // 2:] * 8) / 8 * 0.99          # coarse keys: tied priorities too
+    hint[B // 2:] = np.round(hint[B // 2:] * 5) / 5 * 0.99
+    inst_idx = torch.zeros(B, dtype=torch.int32, device="cuda")
+    pm = np.zeros((B, 2 * mixed.n_max), np.float32)
+    hm = np.zeros((B, 2 * mixed.n_max), np.float32)
+    pm[:, :2 * n], hm[:, :2 * n] = prio, hint
+    a = P.brkga_decode_eval(alone, dev(prio), dev(hint), want_ops=True, flags=flags)
+    b = P.brkga_decode_eval(mixed, dev(pm), dev(hm), inst=inst_idx, want_ops=True, flags=flags)
+    torch.cuda.synchronize()
+    for key in ("fitness", "makespan", "unscheduled", "status"):
+        assert torch.equal(a[key], b[key]), key
+    assert torch.equal(a["rt_end"], b["rt_end"][:, :m])
+    assert torch.equal(a["ops"], b["ops"][:, :2 * n])
+    f = a["fitness"].cpu().numpy()
+    for i in range(0, B, 16):
+        assert f[i] == orc.decode(inst, prio[i], hint[i], flags=flags)["fitness"], i
