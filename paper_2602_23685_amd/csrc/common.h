@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <string>
 #include <map>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -285,4 +286,7 @@ struct vrprpd_set {
     // launch shapes of vrprpd_eval chosen by vrprpd_autotune_eval, keyed by
     // (n, m) of the launch: (waves per block, ops per lane per sweep step)
     std::map<std::pair<int, int>, std::pair<int, int>> eval_tuned;
+    // tuples per workgroup of the ALNS repair rounds' insertion scans chosen by
+    // alns_autotune, keyed by (n_max, m_max, tuple budget) of the state
+    mutable std::map<std::tuple<int, int, int>, int> alns_scan_tuned;
 };

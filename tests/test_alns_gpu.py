@@ -258,3 +258,38 @@ def test_chain_base_matches_the_chains_of_a_batched_state(orc, P):
         assert np.array_equal(to.cpu().numpy(), ref["trace"]), k
         one.close()
     big.close()
+
+
+def test_autotune_keeps_the_trajectory(orc, P):
+    """alns_autotune tries the repair rounds' scan shapes from a checkpoint and
+    restores it: the run continues exactly as one never tuned (and as the
+    oracle), with the trace it had before the call."""
+    inst = synth.make_instance(100, 4, 5, 20, "2x", seed=9700)
+    ops, rt = synth.round_robin_solution(inst)
+    kw = dict(tuple_budget=2000, import_interval=4)
+    S = P.InstanceSet([inst])
+    mk_state = lambda: P.AlnsState(S, [0], 3, P.alns_params(**kw), 77, torch.from_numpy(ops).cuda(),
+                                   torch.from_numpy(rt).cuda())
+    a, b = mk_state(), mk_state()
+    ta, tb = a.set_trace(20), b.set_trace(20)
+    a.step(5)
+    tpb, ms = a.autotune(2)
+    assert tpb in (8, 16, 32, 64) and all(x > 0 for x in ms)
+    assert a.state()["iterations"] == 5
+    a.step(15)
+    b.step(20)
+    torch.cuda.synchronize()
+    assert np.array_equal(ta.cpu().numpy(), tb.cpu().numpy())
+    sa, sb = a.state(), b.state()
+    for key in ("z", "zb", "T", "wD", "wR"):
+        assert np.array_equal(sa[key], sb[key]), key
+    ref = orc.alns_run(inst, orc.alns_params(**kw), 3, 20, 77, ops, rt, trace=True)
+    assert np.array_equal(ta.cpu().numpy(), ref["trace"])
+    # a later state on the set starts with the tuned shape and still matches
+    c = mk_state()
+    tc = c.set_trace(20)
+    c.step(20)
+    assert np.array_equal(tc.cpu().numpy(), ref["trace"])
+    a.close()
+    b.close()
+    c.close()
