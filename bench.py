@@ -573,6 +573,87 @@ def two_stage_chunked(P, torch, S, ops, rt, prm, chains, iters, seed, Np, gens, 
             "brkga_generations": g, "history": [(round(t, 4), z) for t, z in hist[-6:]]}
 
 
+def small_configs(P, torch, reps=10):
+    """Throughput at the two smaller workloads (HIP events on the launch
+    stream, median of `reps`):
+      depot + 16 customers (m = 2, k = 2, R = 4, base rule): vrprpd_eval on
+        4,096 random feasible solutions;
+      100 customers (m = 4, k = 5, R = 20, 2x rule): 65,536 ALNS neighbours of
+        one solution as insertion tuples (vrprpd_insert_scan against a
+        feasible solution with 5 customers removed), the same number of explicit
+        random candidates (vrprpd_eval), and one BRKGA generation of 1,024
+        chromosomes (brkga_decode_eval + brkga_evolve).
+    With the evaluation's rooflines: HBM bytes 4n + 2m + 8 per candidate and
+    the measured L2 random-read ceiling at 2n + 2m reads per candidate."""
+    import synth
+    stream = torch.cuda.current_stream()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def timed(fn):
+        fn()
+        ev = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    out = {}
+    for name, (n, m, k, R, rule, B) in {"n16": (16, 2, 2, 4, "base", 4096),
+                                        "n100": (100, 4, 5, 20, "2x", 65536)}.items():
+        inst = synth.make_instance(n, m, k, R, rule, seed=1001 if n == 16 else 2002)
+        S = P.InstanceSet([inst])
+        pool_o, pool_r = synth.random_candidates(inst, min(B, 1024), seed=n + 1)
+        if B > len(pool_o):
+            ops, rt = synth.relabel_candidates(pool_o, pool_r, n, B, seed=n + 2)
+        else:
+            ops, rt = pool_o, pool_r
+        d_ops, d_rt = dev(ops), dev(rt)
+        mk_ = torch.empty(B, dtype=torch.int32, device="cuda")
+        st_ = torch.empty(B, dtype=torch.int32, device="cuda")
+        form = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)[2]
+        t = timed(lambda: P.vrprpd_eval(S, d_ops, d_rt, makespan=mk_, status=st_))
+        rate, _ = P.vrprpd_gather_rate(S, 0)
+        row = {"workload": f"{n} customers, m = {m}, k = {k}, R = {R}, {rule} rule", "eval_candidates": B,
+               "eval_form": ("staged", "live legs")[form], "eval_ms": t, "eval_per_s": B / (t * 1e-3),
+               "eval_hbm_frac": (4 * n + 2 * m + 8) * B / (t * 1e-3) / HBM_PEAK,
+               "eval_l2_gather_frac": B / (t * 1e-3) / (rate / (2 * n + 2 * m)),
+               "l2_reads_per_s": rate}
+        if n == 100:
+            g = synth.rng(n + 3)
+            removed = sorted(int(c) for c in g.choice(np.arange(1, n + 1), size=5, replace=False))
+            gone = set(removed)
+            base = [[x for x in r if x[0] not in gone] for r in synth.unpack_candidate(pool_o[0], pool_r[0])]
+            fo, _, frt = synth.pack_candidates([base], m)
+            T = 65536
+            tuples = synth.random_tuples(fo, frt[0], n, m, T, seed=n + 4, absent=removed)
+            tuples = tuples[np.argsort(tuples["c"], kind="stable")]
+            cs = tuples["c"].astype(np.int64)
+            seg_off = np.concatenate([[0], np.nonzero(np.diff(cs))[0] + 1, [T]]).astype(np.int64)
+            d_b, d_br, d_seg, d_t = dev(fo), dev(frt[0]), dev(seg_off), dev(tuples.view(np.uint8))
+            ts = timed(lambda: P.vrprpd_insert_scan(S, d_b, d_br, d_seg, d_t))
+            row.update({"neighbours": T, "scan_ms": ts, "scan_per_s": T / (ts * 1e-3)})
+            Np = 1024
+            prio, hint = synth.random_keys(Np, n, seed=n + 5)
+            d_p, d_h = dev(prio), dev(hint)
+            out_ = P.brkga_decode_eval(S, d_p, d_h)
+            p2, h2 = torch.empty_like(d_p), torch.empty_like(d_h)
+            rk = torch.empty(Np, dtype=torch.int32, device="cuda")
+            ne = nm = int(0.15 * Np)
+
+            def gen():
+                P.brkga_decode_eval(S, d_p, d_h, out=out_)
+                P.brkga_evolve(d_p, d_h, out_["fitness"], ne, nm, 0.7, 5, 0, prio_out=p2, hint_out=h2,
+                               rank_out=rk)
+            tg = timed(gen)
+            row.update({"population": Np, "generation_ms": tg, "chromosomes_per_s": Np / (tg * 1e-3)})
+        out[name] = row
+    return out
+
+
 MFMA_BF16_PEAK = 2.5e15   # MI355X dense bf16 matrix peak, flop/s
 
 
@@ -708,8 +789,9 @@ def main():
     ap.add_argument("--no-race", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--phases", default=None,
-                    help="comma list of the phases after the timed steps to run (race, construction, batched, "
-                         "hypothesis, learned, mlp, cpu); default: all not switched off by the --no-* flags")
+                    help="comma list of the phases after the timed steps to run (small, race, construction, "
+                         "batched, hypothesis, learned, mlp, cpu); default: all not switched off by the --no-* "
+                         "flags")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 256 MiB three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -903,8 +985,10 @@ def main():
             "explicit_candidates": B, "tuples": T, "population": Np, "alns_chains": chains,
             "evals_per_step": evals_per_step, "feasible_fraction": feasible,
         },
-        "eval_launch_shape": {"candidates_per_wave": tuned[0], "ops_per_step": tuned[1],
-                              "candidate_shapes_ms": [round(float(x), 4) for x in tuned[2]]},
+        "eval_launch_shape": {"form": ("staged", "live legs")[tuned[2]], "candidates_per_wave": tuned[0],
+                              "ops_per_step": tuned[1],
+                              "candidate_shapes_ms": {"staged": [round(float(x), 4) for x in tuned[3][:6]],
+                                                      "live legs": [round(float(x), 4) for x in tuned[3][6:]]}},
         "components_ms": comp_ms,
         "component_evals_per_s": {
             "vrprpd_eval": B / (comp_ms["vrprpd_eval"] * 1e-3),
@@ -944,7 +1028,7 @@ def main():
     if args.phases is not None:
         phases = set(x.strip() for x in args.phases.split(",") if x.strip())
     else:
-        phases = {"race", "construction", "batched", "hypothesis", "learned", "cpu"}
+        phases = {"small", "race", "construction", "batched", "hypothesis", "learned", "cpu"}
         if args.no_race:
             phases.discard("race")
         if args.no_forms:
@@ -956,6 +1040,9 @@ def main():
         out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
         log("time to oracle-best (n=100, n=1000)")
         out["time_to_oracle_best_large"] = race_to_oracle(P, torch)
+    if "small" in phases:
+        log("smaller workloads (16 and 100 customers)")
+        out["small_configs"] = small_configs(P, torch)
     if "construction" in phases:
         log("construction heuristics")
         out["construction"] = construction(P, torch)

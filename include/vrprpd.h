@@ -127,23 +127,40 @@ int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int
                 const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
                 int32_t* makespan, uint32_t* status, void* stream);
 
-/* Autotuner of vrprpd_eval's launch shape: candidates per 64-lane wave (one
- * wave per block; with 16-lane groups 2, 3 or 4, with 32-lane groups 1 or 2,
- * with 64 lanes 1 -- fewer candidates per wave leave LDS room for more
- * resident waves) x ops per lane per sweep step (2 or 4).  Runs every shape
- * on the caller's batch `reps` times, checks that each gives the default
- * shape's makespans and statuses bit for bit (EHIP otherwise), and keeps the
- * fastest in the set for later vrprpd_eval launches of the same (n, m) -- n,
- * m of the instance, or n_max, m_max when inst != NULL.  Arguments as
- * vrprpd_eval; outputs the chosen shape and, if ms_out != NULL, the mean
- * milliseconds of six shapes: option i of candidates per wave (i = 0..2, in
- * the order listed) x step (2, 4), -1 where an option does not exist or its
- * LDS does not fit.  Synchronous; not concurrent with other calls on the
- * same set. */
+/* Autotuner of vrprpd_eval's launch shape: form x candidates per 64-lane
+ * wave (one wave per block; with 16-lane groups 2, 3 or 4, with 32-lane
+ * groups 1 or 2, with 64 lanes 1 -- fewer candidates per wave leave LDS room
+ * for more resident waves) x ops per lane per sweep step (2 or 4).  The two
+ * forms compute the same thing: "staged" gathers every travel time of a
+ * candidate into LDS before its timing sweep, "live legs" keeps only the op
+ * codes in LDS (a third less at n = 1000, so more candidates stay resident)
+ * and reads each travel time from the matrix as the sweep takes the op.
+ * Without tuning, vrprpd_eval uses live legs when the staged layout of a
+ * candidate exceeds 8 KB (about n > 650 with 16-bit travel times).  Runs
+ * every shape on the caller's batch `reps` times, checks that each gives the
+ * default shape's makespans and statuses bit for bit (EHIP otherwise), and
+ * keeps the fastest in the set for later vrprpd_eval launches of the same
+ * (n, m) -- n, m of the instance, or n_max, m_max when inst != NULL.
+ * Arguments as vrprpd_eval; outputs the chosen candidates per wave and step
+ * and, if ms_out != NULL, the mean milliseconds of twelve shapes at index
+ * 6 * form (0 staged, 1 live legs) + 2 * i + (step == 4), option i of
+ * candidates per wave in the order listed, -1 where an option does not exist
+ * or its LDS does not fit.  Synchronous; not concurrent with other calls on
+ * the same set. */
 int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                          const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
                          int32_t* makespan, uint32_t* status, int32_t reps, int32_t* ng_out, int32_t* step_out,
                          float* ms_out, void* stream);
+
+/* Pins vrprpd_eval's launch shape for launches of (n, m) -- n, m of the
+ * instance, or n_max, m_max when vrprpd_eval gets an instance array -- as
+ * vrprpd_autotune_eval would keep it: ng candidates per wave (0: the
+ * default for this form; else one of the options listed above), step 2 or 4
+ * ops per lane per sweep step, live 0 (staged) or 1 (live legs).  Lets a
+ * caller reuse a shape tuned in an earlier process or compare the forms.
+ * Not concurrent with other calls on the same set.  Errors: EINVAL (NULL
+ * set, n or m < 1, an option that does not exist or whose LDS does not fit). */
+int vrprpd_eval_set_shape(vrprpd_set* set, int32_t n, int32_t m, int32_t ng, int32_t step, int32_t live);
 
 /* Rate of random reads of one instance's travel-time matrix (measurement
  * for vrprpd_eval's secondary bound: staging a candidate of 2n ops makes

@@ -11,5 +11,5 @@ from ._lib import (  # noqa: F401
     InstanceSet, Mlp, VrpError, BrkgaState, pop_seed, alns_params, brkga_decode_eval, brkga_evolve, brkga_warm_start, load,
     vrprpd_autotune_eval, vrprpd_eval, vrprpd_insert_scan, CONS_SWEEP, CONS_NN, CONS_LB, CONS_SPT, vrprpd_construct,
     brkga_warm_start_multi, vrprpd_solution_stats, brkga_decode_eval_noalloc, brkga_decode_noalloc_max_bytes,
-    DECODE_HINT_FIRST, vrprpd_gather_rate,
+    DECODE_HINT_FIRST, vrprpd_gather_rate, vrprpd_eval_set_shape,
 )

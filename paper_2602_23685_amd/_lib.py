@@ -46,6 +46,7 @@ SIGNATURES = {
     "vrprpd_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "vrprpd_autotune_eval": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P, _P, _P]),
     "vrprpd_gather_rate": (C.c_int, [_P, _I32, _I32, _I32, _P, _P, _P]),
+    "vrprpd_eval_set_shape": (C.c_int, [_P, _I32, _I32, _I32, _I32, _I32]),
     "vrprpd_insert_scan": (C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "brkga_decode_eval": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "brkga_decode_eval_noalloc": (C.c_int, [_P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _P]),
@@ -203,18 +204,27 @@ def vrprpd_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None
 def vrprpd_autotune_eval(S: InstanceSet, ops, rt_end, inst=None, op_off=None, rt_off=None, partial=False,
                          reps=3, stream=None):
     """Tune vrprpd_eval's launch shape on this batch; returns (candidates
-    per wave, ops per step, mean ms of the six shapes)."""
+    per wave, ops per step, live-leg form (0 or 1), mean ms of the twelve
+    shapes indexed 6 * form + 2 * option + (step == 4))."""
     B = rt_end.shape[0]
     mk = torch.empty(B, dtype=torch.int32, device="cuda")
     st = torch.empty(B, dtype=torch.int32, device="cuda")
     w, k = C.c_int32(), C.c_int32()
-    ms = np.zeros(6, np.float32)
+    ms = np.zeros(12, np.float32)
     _check(load().vrprpd_autotune_eval(S.handle, B, _dptr(inst, torch.int32, "inst"),
                                        _dptr(op_off, torch.int64, "op_off"), _dptr(ops, torch.uint16, "ops"),
                                        _dptr(rt_off, torch.int64, "rt_off"), _dptr(rt_end, torch.uint16, "rt_end"),
                                        ALLOW_PARTIAL if partial else 0, _dptr(mk), _dptr(st), reps, C.byref(w),
                                        C.byref(k), ms.ctypes.data, _stream(stream)))
-    return w.value, k.value, ms
+    valid = np.where(ms > 0, ms, np.inf)
+    return w.value, k.value, int(np.argmin(valid)) // 6, ms
+
+
+def vrprpd_eval_set_shape(S: InstanceSet, n, m, ng=0, step=4, live=1):
+    """Pin vrprpd_eval's launch shape for (n, m) (see vrprpd_eval_set_shape
+    in vrprpd.h): ng candidates per wave (0: default), step 2 or 4, live 0
+    (staged travel times) or 1 (live legs)."""
+    _check(load().vrprpd_eval_set_shape(S.handle, n, m, ng, step, live))
 
 
 def vrprpd_gather_rate(S: InstanceSet, inst=0, blocks=8192, per_thread=256, stream=None):

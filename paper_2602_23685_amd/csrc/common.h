@@ -284,8 +284,9 @@ struct vrprpd_set {
     void* d_dist = nullptr;            // uint16_t or int32_t, per dist16
     int32_t* d_proc = nullptr;
     // launch shapes of vrprpd_eval chosen by vrprpd_autotune_eval, keyed by
-    // (n, m) of the launch: (waves per block, ops per lane per sweep step)
-    std::map<std::pair<int, int>, std::pair<int, int>> eval_tuned;
+    // (n, m) of the launch: (candidates per wave, ops per lane per sweep
+    // step, 1 for the live-leg form)
+    std::map<std::pair<int, int>, std::tuple<int, int, int>> eval_tuned;
     // tuples per workgroup of the ALNS repair rounds' insertion scans chosen by
     // alns_autotune, keyed by (n_max, m_max, tuple budget) of the state
     mutable std::map<std::tuple<int, int, int>, int> alns_scan_tuned;

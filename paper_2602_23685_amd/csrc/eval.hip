@@ -4,9 +4,13 @@
 // candidate; up to 64/GL groups share a one-wave block (candidates per wave
 // is a tuned launch parameter).
 // Phase 1 streams the candidate's ops from HBM once (coalesced, route by
-// route), checks cover with an LDS bitmap, and gathers every travel time
-// d[prev][c] in parallel into LDS, so the sweep that follows never waits on
-// the L2.  Phase 2 is the lockstep timing sweep (sweep.h), lane v = vehicle v.
+// route) and checks cover with an LDS bitmap.  Phase 2 is the lockstep
+// timing sweep (sweep.h), lane v = vehicle v.  Two forms, chosen per (n, m)
+// by the autotuner: "staged" (eval_kernel) gathers every travel time
+// d[prev][c] into LDS in phase 1, so the sweep reads only LDS; "live legs"
+// (eval_live_kernel) keeps only the op codes in LDS and reads each travel
+// time from the L2-resident matrix as the sweep takes its op -- a third less
+// LDS per candidate at n = 1000, so more candidates stay resident.
 #include "common.h"
 #include "sweep.h"
 
@@ -250,16 +254,248 @@ __global__ __launch_bounds__(64) void eval_kernel(EvalArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Live-leg form: phase 1 stages only the op codes (2 B per op) and the cover
+// bits; the sweep gathers each op's travel time d[prev][c] from the L2 in the
+// same round trip as its ready[] read.  8.3 KB of LDS per candidate at
+// n = 1000 instead of 12.3 KB, and the gathers spread over the sweep instead
+// of a burst before it.
+
+__host__ __device__ inline GroupLayout live_layout(int n_max)
+{
+    GroupLayout g;
+    g.ready_off = 0;
+    g.bits_off = align16(4 * (n_max + 1));
+    g.ops_off = g.bits_off + align16(4 * ((2 * (n_max + 1) + 31) / 32));
+    // codes start up to 7 entries in, so that the vector stores are aligned
+    g.bytes = g.ops_off + align16(2 * (2 * n_max + kStepOps + 8));
+    return g;
+}
+
+// Cover bit of one code; returns the code, or 0 for a code outside [1, n].
+__device__ __forceinline__ uint32_t cover_code(uint32_t* bits, uint32_t cd, int n, bool live, bool& bad)
+{
+    const int c = (int)(cd >> 1);
+    const bool ok = c >= 1 && c <= n;
+    const int bitpos = ok ? 2 * c + (int)(cd & 1u) : 0;
+    const uint32_t mask = (ok && live) ? 1u << (bitpos & 31) : 0u;
+    const uint32_t old = atomicOr(&bits[bitpos >> 5], mask);
+    bad = bad || (live && (!ok || (old & mask)));
+    return ok ? cd : 0u;
+}
+
+// Travel time at a 32-bit byte offset from the uniform matrix base.
+template <typename DT>
+__device__ __forceinline__ int leg_at(const DT* D, uint32_t entry)
+{
+    return (int)*reinterpret_cast<const DT*>(reinterpret_cast<const unsigned char*>(D) + entry * (uint32_t)sizeof(DT));
+}
+
+// The lockstep sweep of sweep_group with the travel times read from the
+// matrix as the ops are taken: lane v keeps the matrix row of its route's
+// last stop (the depot's at the start) for the next op's leg, so a step
+// reads its K codes from LDS, then their ready[] entries (LDS) and legs (L2)
+// together.  The codes array holds valid codes for K entries past the last
+// route.
+template <int GL, int K, typename DT>
+__device__ __forceinline__ SweepOut sweep_live(const uint16_t* codes, const DT* D, uint32_t N1, int* ready, int s,
+                                               int e)
+{
+    SweepOut o{0, 0, 0, 0, false};
+    int ptr = s;
+    uint32_t prow = 0;
+    for (;;) {
+        int took = 0;
+        if (ptr < e) {
+            uint32_t cd[K], row[K];
+            int leg[K], r[K];
+#pragma unroll
+            for (int u = 0; u < K; ++u) cd[u] = codes[ptr + u];
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                // codes are 16-bit, so customers and n + 1 are below 2^16
+                // and the 24-bit multiply is exact
+                row[u] = __umul24(cd[u] >> 1, N1);
+                leg[u] = leg_at(D, (u == 0 ? prow : row[u > 0 ? u - 1 : 0]) + (cd[u] >> 1));
+            }
+#pragma unroll
+            for (int u = 0; u < K; ++u) r[u] = lds_load(&ready[cd[u] >> 1]);
+            took = sweep_step<K, false>(o, cd, leg, r, e - ptr, ready, nullptr, 0);
+#pragma unroll
+            for (int u = 0; u < K; ++u) prow = took == u + 1 ? row[u] : prow;
+            ptr += took;
+        }
+        const uint64_t left = group_ballot<GL>(ptr < e);
+        if (!left) break;
+        const uint64_t moved = group_ballot<GL>(took > 0);
+        if (!moved) {
+            o.dead = true;
+            break;
+        }
+    }
+    // A deadlock stops the clocks but the load check covers whole routes.
+    for (; ptr < e; ++ptr) {
+        o.w += (codes[ptr] & 1u) ? -1 : 1;
+        o.wmax = o.w > o.wmax ? o.w : o.wmax;
+        o.wmin = o.w < o.wmin ? o.w : o.wmin;
+    }
+    return o;
+}
+
+template <typename DT, int GL, int NG, int K, bool kOneInst>
+__global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
+{
+    static_assert(NG * GL <= 64, "groups per wave");
+    static_assert(K <= kStepOps && K <= GL, "sweep step within the op padding");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / GL, li = lane % GL;
+    if (grp >= NG) return;
+    const int blk = xcd_remap(blockIdx.x, a.nblocks);
+    const int64_t b = (int64_t)blk * NG + grp;
+    const bool live = b < a.B;
+
+    const GroupLayout L = live_layout(a.n_max);
+    unsigned char* gs = smem + (size_t)grp * a.group_bytes;
+    int* ready = reinterpret_cast<int*>(gs + L.ready_off);
+    uint32_t* bits = reinterpret_cast<uint32_t*>(gs + L.bits_off);
+
+    int ii = (!kOneInst && live && a.inst) ? a.inst[b] : 0;
+    const bool bad_inst = ii < 0 || ii >= a.num_inst;
+    if (bad_inst) ii = 0;
+    const InstDev I = a.inst_tab[ii];
+    const int n = I.n, m = I.m, N1 = n + 1;
+    const DT* D = reinterpret_cast<const DT*>(a.dist) + I.d_off;
+    const int32_t* P = a.proc + I.p_off;
+    const int64_t ob = live ? (a.op_off ? a.op_off[b] : b * 2 * (int64_t)n) : 0;
+    const int64_t rb = live ? (a.rt_off ? a.rt_off[b] : b * (int64_t)m) : 0;
+    const uint16_t* ops = a.ops + ob;
+
+    int e = 0;
+    if (live && !bad_inst && li < m) e = a.rt_end[rb + li];
+    int s = __shfl_up(e, 1, GL);
+    if (li == 0) s = 0;
+    const int total = __shfl(e, m - 1, GL);
+    bool bad = bad_inst || (live && li < m && s > e);
+    if (total > 2 * n) bad = true;
+    bool gbad = !live || group_ballot<GL>(bad) != 0;
+
+    // codes[j] = op j, placed so that codes + head is 16-byte aligned
+    int head = (int)((8 - (((uintptr_t)ops >> 1) & 7)) & 7);
+    head = head < total ? head : total;
+    uint16_t* codes = reinterpret_cast<uint16_t*>(gs + L.ops_off) + ((8 - head) & 7);
+
+    // ---- phase 1: ready[], cover bits, op codes --------------------------
+    const int nwords = (2 * N1 + 31) / 32;
+    for (int w = li; w < nwords; w += GL) bits[w] = 0u;
+    wave_lds_fence();
+    bool cbad = false;
+    if (!gbad) {
+        {
+            const int4* P4 = reinterpret_cast<const int4*>(P);
+            int4* R4 = reinterpret_cast<int4*>(ready);
+            const int np4 = (N1 + 3) >> 2;
+            constexpr int VP = 8;
+            for (int q0 = li; q0 < np4; q0 += VP * GL) {
+                int4 x[VP];
+#pragma unroll
+                for (int v = 0; v < VP; ++v) {
+                    const int q = q0 + v * GL;
+                    x[v] = P4[q < np4 ? q : np4 - 1];
+                }
+#pragma unroll
+                for (int v = 0; v < VP; ++v) {
+                    const int q = q0 + v * GL;
+                    if (q < np4) R4[q] = make_int4(~x[v].x, ~x[v].y, ~x[v].z, ~x[v].w);
+                }
+            }
+        }
+        const int nvec = (total - head) >> 3;
+        const int tail0 = head + 8 * nvec;
+        const int nscalar = head + (total - tail0);
+        for (int t = li; t < nscalar; t += GL) {
+            const int j = t < head ? t : tail0 + (t - head);
+            codes[j] = (uint16_t)cover_code(bits, ops[j], n, true, cbad);
+        }
+        const uint4* vec = reinterpret_cast<const uint4*>(ops + head);
+        uint4* cvec = reinterpret_cast<uint4*>(codes + head);
+        constexpr int V = 8;
+        for (int q0 = li; q0 < nvec; q0 += V * GL) {
+            uint4 x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int q = q0 + v * GL;
+                x[v] = vec[q < nvec ? q : nvec - 1];
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int q = q0 + v * GL;
+                const bool in = q < nvec;
+                uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const uint32_t lo = cover_code(bits, w4[h] & 0xFFFFu, n, in, cbad);
+                    const uint32_t hi = cover_code(bits, w4[h] >> 16, n, in, cbad);
+                    w4[h] = lo | (hi << 16);
+                }
+                if (in) cvec[q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+            }
+        }
+    }
+    // padding past the last route: the sweep reads its next K codes without
+    // testing the route's end
+    if (!gbad && li < K) codes[total + li] = 0;
+    wave_lds_fence();
+    if (!gbad) {
+        for (int c = 1 + li; c <= n; c += GL) {
+            const uint32_t two = (bits[(2 * c) >> 5] >> ((2 * c) & 31)) & 3u;
+            if (!(two == 3u || (two == 0u && a.partial))) cbad = true;
+        }
+    }
+    gbad = gbad || group_ballot<GL>(cbad) != 0;
+
+    // ---- phase 2: timing sweep ----------------------------------------------
+    const bool veh = li < m;
+    SweepOut o{0, 0, 0, 0, false};
+    if (!gbad) o = sweep_live<GL, K, DT>(codes, D, (uint32_t)N1, ready, veh ? s : 0, veh ? e : 0);
+
+    uint32_t st = 0;
+    int z = 0;
+    if (!gbad) {
+        st = load_status<GL>(o, veh, m, I.k, I.R, I.load_model);
+        int ret = 0;
+        if (veh && e > s) ret = o.t + (int)D[(int64_t)(codes[e - 1] >> 1) * N1];
+        z = group_max<GL>(ret);
+        if (o.dead) st |= VRPRPD_ST_DEADLOCK;
+    }
+    if (live && li == 0) {
+        if (gbad) {
+            a.makespan[b] = INT32_MAX;
+            a.status[b] = VRPRPD_ST_BAD_COVER;
+        } else {
+            a.makespan[b] = o.dead ? INT32_MAX : z;
+            a.status[b] = st;
+        }
+    }
+}
+
 constexpr int kEvalStep = 4;   // default ops per lane per sweep step
 
 struct LaunchShape {
-    int gl, ng, group_bytes, lds, step;
+    int gl, ng, group_bytes, lds, step, live;
 };
 
-static int group_bytes_of(int n_max, int dist16)
+static int group_bytes_of(int n_max, int dist16, int live)
 {
+    if (live) return live_layout(n_max).bytes;
     return group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
 }
+
+// Default form without tuning: live legs once the staged layout (ops, legs
+// and ready[] of a candidate) outgrows 8 KB of LDS, about n > 650 with
+// 16-bit travel times: below that both forms keep enough waves resident and
+// the staged form's sweep reads only LDS.
+static int default_live(int n_max, int dist16) { return group_bytes_of(n_max, dist16, 0) > 8 * 1024 ? 1 : 0; }
 
 // Candidates per wave tried for a group width: 16 lanes -> 2, 3, 4; 32 -> 1, 2; 64 -> 1.
 static int ng_options(int gl, int* out)
@@ -282,11 +518,12 @@ static int default_ng(int gl, int gb)
     return best;
 }
 
-static LaunchShape eval_shape(int n_max, int m_max, int dist16, int ng, int step)
+static LaunchShape eval_shape(int n_max, int m_max, int dist16, int ng, int step, int live)
 {
     LaunchShape sh;
     sh.gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
-    sh.group_bytes = group_bytes_of(n_max, dist16);
+    sh.live = live >= 0 ? live : default_live(n_max, dist16);
+    sh.group_bytes = group_bytes_of(n_max, dist16, sh.live);
     sh.ng = ng > 0 ? ng : default_ng(sh.gl, sh.group_bytes);
     sh.lds = sh.ng * sh.group_bytes;
     sh.step = step > 0 ? step : kEvalStep;
@@ -294,9 +531,10 @@ static LaunchShape eval_shape(int n_max, int m_max, int dist16, int ng, int step
 }
 
 template <typename DT, int GL, int NG, int K>
-static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
+static int launch_eval(const EvalArgs& a, int lds, int live, hipStream_t stream)
 {
-    auto* k = a.inst ? eval_kernel<DT, GL, NG, K, false> : eval_kernel<DT, GL, NG, K, true>;
+    auto* k = live ? (a.inst ? eval_live_kernel<DT, GL, NG, K, false> : eval_live_kernel<DT, GL, NG, K, true>)
+                   : (a.inst ? eval_kernel<DT, GL, NG, K, false> : eval_kernel<DT, GL, NG, K, true>);
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
@@ -306,9 +544,10 @@ static int launch_eval(const EvalArgs& a, int lds, hipStream_t stream)
 }
 
 template <typename DT, int GL, int NG>
-static int dispatch_step(const EvalArgs& a, int step, int lds, hipStream_t st)
+static int dispatch_step(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
 {
-    return step == 2 ? launch_eval<DT, GL, NG, 2>(a, lds, st) : launch_eval<DT, GL, NG, 4>(a, lds, st);
+    return sh.step == 2 ? launch_eval<DT, GL, NG, 2>(a, sh.lds, sh.live, st)
+                        : launch_eval<DT, GL, NG, 4>(a, sh.lds, sh.live, st);
 }
 
 template <typename DT>
@@ -316,22 +555,22 @@ static int dispatch_gl(const EvalArgs& a, const LaunchShape& sh, hipStream_t st)
 {
     if (sh.gl == 16) {
         switch (sh.ng) {
-        case 2: return dispatch_step<DT, 16, 2>(a, sh.step, sh.lds, st);
-        case 3: return dispatch_step<DT, 16, 3>(a, sh.step, sh.lds, st);
-        default: return dispatch_step<DT, 16, 4>(a, sh.step, sh.lds, st);
+        case 2: return dispatch_step<DT, 16, 2>(a, sh, st);
+        case 3: return dispatch_step<DT, 16, 3>(a, sh, st);
+        default: return dispatch_step<DT, 16, 4>(a, sh, st);
         }
     }
     if (sh.gl == 32) {
-        if (sh.ng == 1) return dispatch_step<DT, 32, 1>(a, sh.step, sh.lds, st);
-        return dispatch_step<DT, 32, 2>(a, sh.step, sh.lds, st);
+        if (sh.ng == 1) return dispatch_step<DT, 32, 1>(a, sh, st);
+        return dispatch_step<DT, 32, 2>(a, sh, st);
     }
-    return dispatch_step<DT, 64, 1>(a, sh.step, sh.lds, st);
+    return dispatch_step<DT, 64, 1>(a, sh, st);
 }
 
 // Validates the arguments and launches one shape (ng, step <= 0: default).
 static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                        const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
-                       int32_t* makespan, uint32_t* status, hipStream_t st, int ng, int step)
+                       int32_t* makespan, uint32_t* status, hipStream_t st, int ng, int step, int live)
 {
     if (!set) return set_error(VRPRPD_EINVAL, "vrprpd_eval: set is NULL");
     if (B < 0) return set_error(VRPRPD_EINVAL, "vrprpd_eval: B < 0");
@@ -343,14 +582,11 @@ static int eval_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, co
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: instances differ in n or m; pass op_off and rt_off");
     const int n_lds = inst ? set->n_max : set->host[0].n;
     const int m_max = inst ? set->m_max : set->host[0].m;
-    if (ng <= 0 && step <= 0) {
+    if (ng <= 0 && step <= 0 && live < 0) {
         const auto it = set->eval_tuned.find({n_lds, m_max});
-        if (it != set->eval_tuned.end()) {
-            ng = it->second.first;
-            step = it->second.second;
-        }
+        if (it != set->eval_tuned.end()) std::tie(ng, step, live) = it->second;
     }
-    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16, ng, step);
+    const LaunchShape sh = eval_shape(n_lds, m_max, set->dist16, ng, step, live);
     if ((size_t)sh.lds > kLdsPerCu)
         return set_error(VRPRPD_EINVAL, "vrprpd_eval: n=%d needs %d B of LDS per candidate", n_lds, sh.lds);
     const int64_t per_block = sh.ng;
@@ -404,7 +640,7 @@ extern "C" int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst
                            int32_t* makespan, uint32_t* status, void* stream)
 {
     return eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status,
-                       reinterpret_cast<hipStream_t>(stream), 0, 0);
+                       reinterpret_cast<hipStream_t>(stream), 0, 0, -1);
 }
 
 extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
@@ -418,9 +654,8 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     const int n_lds = inst ? set->n_max : set->host[0].n;
     const int m_max = inst ? set->m_max : set->host[0].m;
     const int gl = m_max <= 16 ? 16 : (m_max <= 32 ? 32 : 64);
-    const int gb = group_bytes_of(n_lds, set->dist16);
     // reference outputs of the default shape, kept on the host
-    int rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, -1, kEvalStep);
+    int rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, -1, kEvalStep, -1);
     if (rc) return rc;
     std::vector<int32_t> mk0(B), mk1(B);
     std::vector<uint32_t> st0(B), st1(B);
@@ -431,49 +666,78 @@ extern "C" int vrprpd_autotune_eval(vrprpd_set* set, int64_t B, const int32_t* i
     VRP_HIP(hipEventCreate(&e0));
     VRP_HIP(hipEventCreate(&e1));
     float best = 0.f;
-    int bw = default_ng(gl, gb), bs = kEvalStep, v = 0;
+    const int live0 = default_live(n_lds, set->dist16);
+    int bw = default_ng(gl, group_bytes_of(n_lds, set->dist16, live0)), bs = kEvalStep, bl = live0, v = 0;
     int ngs[3];
     const int nng = ng_options(gl, ngs);
     const int steps[2] = {2, 4};
-    for (int wi = 0; wi < 3; ++wi) {
-        for (int si = 0; si < 2; ++si, ++v) {
-            float ms = -1.f;
-            const int w = wi < nng ? ngs[wi] : 0;
-            const int k = steps[si];
-            if (w > 0 && (size_t)w * gb <= kLdsPerCu) {
-                rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, w, k);
-                if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = set_error(VRPRPD_EHIP, "event");
-                for (int r = 0; r < reps && !rc; ++r)
-                    rc = eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st, w, k);
-                if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: timing failed");
-                if (!rc && (hipMemcpy(mk1.data(), makespan, B * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                            hipMemcpy(st1.data(), status, B * 4, hipMemcpyDeviceToHost) != hipSuccess))
-                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: copy failed");
-                if (!rc && (mk1 != mk0 || st1 != st0))
-                    rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: shape (%d candidates per wave, step %d) "
-                                                "disagrees with the default shape", w, k);
-                if (rc) {
-                    (void)hipEventDestroy(e0);
-                    (void)hipEventDestroy(e1);
-                    return rc;
+    for (int lv = 0; lv < 2; ++lv) {
+        const int gb = group_bytes_of(n_lds, set->dist16, lv);
+        for (int wi = 0; wi < 3; ++wi) {
+            for (int si = 0; si < 2; ++si, ++v) {
+                float ms = -1.f;
+                const int w = wi < nng ? ngs[wi] : 0;
+                const int k = steps[si];
+                if (w > 0 && (size_t)w * gb <= kLdsPerCu) {
+                    auto run = [&]() {
+                        return eval_launch(set, B, inst, op_off, ops, rt_off, rt_end, flags, makespan, status, st,
+                                           w, k, lv);
+                    };
+                    rc = run();
+                    if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = set_error(VRPRPD_EHIP, "event");
+                    for (int r = 0; r < reps && !rc; ++r) rc = run();
+                    if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                        rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: timing failed");
+                    if (!rc && (hipMemcpy(mk1.data(), makespan, B * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                                hipMemcpy(st1.data(), status, B * 4, hipMemcpyDeviceToHost) != hipSuccess))
+                        rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: copy failed");
+                    if (!rc && (mk1 != mk0 || st1 != st0))
+                        rc = set_error(VRPRPD_EHIP, "vrprpd_autotune_eval: shape (%s, %d candidates per wave, "
+                                                    "step %d) disagrees with the default shape",
+                                       lv ? "live legs" : "staged legs", w, k);
+                    if (rc) {
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        return rc;
+                    }
+                    ms /= (float)reps;
+                    if (best == 0.f || ms < best) {
+                        best = ms;
+                        bw = w;
+                        bs = k;
+                        bl = lv;
+                    }
                 }
-                ms /= (float)reps;
-                if (best == 0.f || ms < best) {
-                    best = ms;
-                    bw = w;
-                    bs = k;
-                }
+                if (ms_out) ms_out[v] = ms;
             }
-            if (ms_out) ms_out[v] = ms;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set->eval_tuned[{n_lds, m_max}] = {bw, bs};
+    set->eval_tuned[{n_lds, m_max}] = {bw, bs, bl};
     if (ng_out) *ng_out = bw;
     if (step_out) *step_out = bs;
+    return VRPRPD_OK;
+}
+
+extern "C" int vrprpd_eval_set_shape(vrprpd_set* set, int32_t n, int32_t m, int32_t ng, int32_t step, int32_t live)
+{
+    if (!set || n < 1 || m < 1 || (step != 2 && step != 4) || (live != 0 && live != 1) || ng < 0)
+        return set_error(VRPRPD_EINVAL, "vrprpd_eval_set_shape: need a set, n >= 1, m >= 1, step 2 or 4, "
+                                        "live 0 or 1 and ng >= 0");
+    const int gl = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+    int opts[3];
+    const int k = ng_options(gl, opts);
+    const int gb = group_bytes_of(n, set->dist16, live);
+    if (ng == 0) ng = default_ng(gl, gb);
+    bool ok = false;
+    for (int i = 0; i < k; ++i) ok = ok || opts[i] == ng;
+    if (!ok) return set_error(VRPRPD_EINVAL, "vrprpd_eval_set_shape: %d candidates per wave is not an option for m=%d",
+                              ng, m);
+    if ((size_t)ng * gb > kLdsPerCu)
+        return set_error(VRPRPD_EINVAL, "vrprpd_eval_set_shape: %d candidates per wave need %d B of LDS", ng, ng * gb);
+    set->eval_tuned[{n, m}] = {ng, step, live};
     return VRPRPD_OK;
 }
 

@@ -32,19 +32,27 @@ def gpu_eval(P, S, ops, rt, **kw):
     return mk.cpu().numpy(), st.cpu().numpy().view(np.uint32)
 
 
+FORMS = ((0, "staged"), (1, "live legs"))
+
+
 def check(orc, P, inst, ops, rt, label, partial=False, op_off=None):
+    """Both forms of the evaluation kernel against the oracle."""
     S = P.InstanceSet([inst])
     if op_off is None:
-        mk, st = gpu_eval(P, S, ops, rt, partial=partial)
         omk, ost = orc.eval_batch(inst, ops, rt, allow_partial=partial)
     else:
         rt_off = np.arange(len(op_off), dtype=np.int64) * inst.m
-        mk, st = gpu_eval(P, S, ops, rt.reshape(-1), op_off=op_off, rt_off=rt_off, partial=partial)
         omk, ost = orc.eval_batch(inst, ops, rt.reshape(-1), op_off=op_off, rt_off=rt_off,
                                   allow_partial=partial)
-    bad = np.nonzero((mk != omk) | (st != ost))[0]
-    assert bad.size == 0, (f"{label}: {bad.size} mismatches, first b={bad[0]} gpu=({mk[bad[0]]},"
-                           f"{st[bad[0]]}) oracle=({omk[bad[0]]},{ost[bad[0]]})")
+    for form, name in FORMS:
+        P.vrprpd_eval_set_shape(S, inst.n, inst.m, 0, 4, form)
+        if op_off is None:
+            mk, st = gpu_eval(P, S, ops, rt, partial=partial)
+        else:
+            mk, st = gpu_eval(P, S, ops, rt.reshape(-1), op_off=op_off, rt_off=rt_off, partial=partial)
+        bad = np.nonzero((mk != omk) | (st != ost))[0]
+        assert bad.size == 0, (f"{label} ({name}): {bad.size} mismatches, first b={bad[0]} gpu=({mk[bad[0]]},"
+                               f"{st[bad[0]]}) oracle=({omk[bad[0]]},{ost[bad[0]]})")
     return omk, ost
 
 
@@ -128,11 +136,13 @@ def test_eval_parity_mixed_instances(orc, P):
     ops = np.concatenate(ops); rt = np.concatenate(rt)
     op_off = np.array(op_off, np.int64); rt_off = np.array(rt_off, np.int64)
     idx = np.array(idx, np.int32)
-    mk, st = gpu_eval(P, S, ops, rt, inst=idx, op_off=op_off, rt_off=rt_off)
-    for t in range(len(idx)):
-        inst = insts[idx[t]]
-        ref = orc.eval_one(inst, ops[op_off[t]:op_off[t] + 2 * inst.n], rt[rt_off[t]:rt_off[t] + inst.m])
-        assert (mk[t], st[t]) == ref, t
+    refs = [orc.eval_one(insts[idx[t]], ops[op_off[t]:op_off[t] + 2 * insts[idx[t]].n],
+                         rt[rt_off[t]:rt_off[t] + insts[idx[t]].m]) for t in range(len(idx))]
+    for form, name in FORMS:
+        P.vrprpd_eval_set_shape(S, max(x.n for x in insts), max(x.m for x in insts), 0, 4, form)
+        mk, st = gpu_eval(P, S, ops, rt, inst=idx, op_off=op_off, rt_off=rt_off)
+        for t in range(len(idx)):
+            assert (mk[t], st[t]) == refs[t], (name, t)
 
 
 def test_eval_full_scale_sampled(orc, P):
@@ -145,17 +155,28 @@ def test_eval_full_scale_sampled(orc, P):
     ops = np.tile(base_ops, (reps, 1))[perm]
     rt = np.tile(base_rt, (reps, 1))[perm]
     S = P.InstanceSet([inst])
-    mk, st = gpu_eval(P, S, ops, rt)
     pick = synth.rng(6).choice(len(ops), size=200, replace=False)
     omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
-    assert np.array_equal(mk[pick], omk) and np.array_equal(st[pick], ost)
-    # copies of one candidate agree wherever they sit in the batch
     src = perm % 2048
     first = np.full(2048, -1)
     for i, s_ in enumerate(src):
         if first[s_] < 0:
             first[s_] = i
-    assert np.array_equal(mk, mk[first[src]])
+    for form, name in FORMS:
+        P.vrprpd_eval_set_shape(S, 1000, 10, 0, 4, form)
+        mk, st = gpu_eval(P, S, ops, rt)
+        assert np.array_equal(mk[pick], omk) and np.array_equal(st[pick], ost), name
+        # copies of one candidate agree wherever they sit in the batch
+        assert np.array_equal(mk, mk[first[src]]), name
+
+
+def test_eval_set_shape_refuses_bad_options(P):
+    inst = synth.make_instance(30, 3, 4, 12, seed=2)
+    S = P.InstanceSet([inst])
+    for args in [(30, 3, 5, 4, 1), (30, 3, 0, 3, 1), (30, 3, 0, 4, 2), (0, 3, 0, 4, 0), (30, 40, 2, 4, 0)]:
+        with pytest.raises(RuntimeError):
+            P.vrprpd_eval_set_shape(S, *args)
+    P.vrprpd_eval_set_shape(S, 30, 3, 3, 2, 0)
 
 
 def test_eval_empty_batch(P):
@@ -174,12 +195,13 @@ def test_autotuned_shapes_agree_with_oracle(orc, P, n, m, B):
     ops, rt = synth.random_candidates(inst, B, seed=n)
     S = P.InstanceSet([inst])
     d_ops, d_rt = torch.from_numpy(ops).cuda(), torch.from_numpy(rt).cuda()
-    w, k, ms = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)
+    w, k, form, ms = P.vrprpd_autotune_eval(S, d_ops, d_rt, reps=2)
     opts = [2, 3, 4] if m <= 16 else ([1, 2] if m <= 32 else [1])
-    assert w in opts and k in (2, 4)
-    assert ms[2 * opts.index(w) + (0 if k == 2 else 1)] > 0
-    assert ms[0] > 0 and ms[1] > 0    # the smallest option always fits
-    assert np.all(ms[2 * len(opts):] == -1)
+    assert w in opts and k in (2, 4) and form in (0, 1)
+    assert ms[6 * form + 2 * opts.index(w) + (k == 4)] > 0
+    for f in (0, 1):   # both forms; the smallest option always fits
+        assert np.all(ms[6 * f:6 * f + 2] > 0)
+        assert np.all(ms[6 * f + 2 * len(opts):6 * f + 6] == -1)
     mk, st = gpu_eval(P, S, ops, rt)
     pick = synth.rng(n).choice(B, size=min(B, 300), replace=False)
     omk, ost = orc.eval_batch(inst, ops[pick], rt[pick])
