@@ -47,17 +47,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "eval_kernel_n1000_pmc_traffic.md")
+# the evaluation kernel of each form and the rocprofv3 summary of its HBM traffic
+EVAL_KERNELS = ("eval_kernel", "eval_live_kernel")
 EVAL_SOURCES = ["paper_2602_23685_amd/csrc/eval.hip", "paper_2602_23685_amd/csrc/sweep.h",
                 "paper_2602_23685_amd/csrc/common.h"]
 
 
-def measured_traffic():
-    """HBM bytes per eval_kernel launch from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
+def measured_traffic(form):
+    """HBM bytes per launch of the evaluation kernel of `form` (0 staged,
+    1 live legs) from the committed rocprofv3 counter summary, or None when
+    the kernel sources changed since it was taken."""
     import hashlib
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(os.path.join(ROOT, "profiles", f"{EVAL_KERNELS[form]}_n1000_pmc_traffic.md")).read()
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in txt.splitlines() if l.startswith(("traffic_bytes", "kernel_sources")))
@@ -946,11 +948,13 @@ def main():
     bytes_per_eval = 2 * 2 * inst.n + 2 * inst.m + 4 + 4
     achieved = bytes_per_eval * B / (eval_ms * 1e-3)
     feasible = float((st == 0).float().mean().item())
-    # secondary bound: staging a candidate reads 2n legs, re-reads the m
-    # route starts from the depot and reads the m return legs, at random
-    # entries of the 2 MB travel-time matrix
+    # secondary bound: travel times read at random entries of the 2 MB
+    # matrix, one per op and one per return leg (2n + m); the staged form
+    # also reads the m route starts twice (the flat list's leg, then the
+    # depot's)
     gather_rate, _ = P.vrprpd_gather_rate(S, 0)
-    reads_per_eval = 2 * inst.n + 2 * inst.m
+    form = tuned[2]
+    reads_per_eval = 2 * inst.n + (2 if form == 0 else 1) * inst.m
     # insertion scan: LDS bytes of one exact evaluation of base + tuple (per
     # customer: two op codes and two legs read, p and ready[] for the drop,
     # ready[] for the pickup = 20 B)
@@ -1001,10 +1005,10 @@ def main():
                    "scan and BRKGA (joined every step); components_ms from as many sequential steps",
         "roofline": {
             "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
+            "frac": achieved / HBM_PEAK, "traffic": measured_traffic(form),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "algorithmic_bytes_per_launch": bytes_per_eval * B,
-            "kernel": "eval_kernel", "kernel_ms": eval_ms, "bytes_per_unit": bytes_per_eval,
+            "kernel": EVAL_KERNELS[form], "kernel_ms": eval_ms, "bytes_per_unit": bytes_per_eval,
             "units_per_launch": B,
             "secondary": {"bound": "l2_gather", "reads_per_unit": reads_per_eval,
                           "measured_reads_per_s": gather_rate, "ceiling_units_per_s": gather_rate / reads_per_eval,

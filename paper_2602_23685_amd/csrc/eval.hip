@@ -506,15 +506,16 @@ static int ng_options(int gl, int* out)
     return 1;
 }
 
-// Default: the most candidates per wave that still leave room for one wave
-// per SIMD (4 per CU) in LDS, else one wave per CU's worth.
+// Default: the most candidates per wave that still leave LDS room for two
+// waves per SIMD (8 per CU: the sweep is latency-bound and needs a second
+// wave to hide it), else the fewest.
 static int default_ng(int gl, int gb)
 {
     int opts[3];
     const int k = ng_options(gl, opts);
     int best = opts[0];
     for (int i = 0; i < k; ++i)
-        if ((size_t)opts[i] * gb * 4 <= kLdsPerCu) best = opts[i];
+        if ((size_t)opts[i] * gb * 8 <= kLdsPerCu) best = opts[i];
     return best;
 }
 
