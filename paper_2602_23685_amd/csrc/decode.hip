@@ -42,7 +42,6 @@ struct DecodeArgs {
     uint16_t* order;       // [B][cap] op indices in priority order (workspace)
     uint8_t* badkey;       // [B] 1: the chromosome's keys failed the check (workspace)
     uint32_t* log;         // [B][cap] schedule log, code | vehicle << 16 (workspace, with ops_out)
-    int32_t hint_first;    // 1: the hint vehicle takes an op whenever it can (VRPRPD_DECODE_HINT_FIRST)
 };
 
 __host__ __device__ inline int d16(int x) { return (x + 15) & ~15; }
@@ -183,7 +182,8 @@ __device__ __forceinline__ int wave_min_dpp(int x)   // minimum over all 64 lane
 // kPacked (with kSmallM): every time is below 2^27, so a vehicle's key
 // (completion time << 4 | its rank in the hint-rotated order) fits 31 bits
 // and one minimum gives both the time and the vehicle.
-template <typename DT, bool kSmallM, bool kLog, bool kPacked>
+// kHintFirst: the hint-first vehicle rule (VRPRPD_DECODE_HINT_FIRST).
+template <typename DT, bool kSmallM, bool kLog, bool kPacked, bool kHintFirst>
 __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 {
     static_assert(!kPacked || kSmallM, "packed keys need m <= 16");
@@ -211,7 +211,9 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     // ---- 3. passes -------------------------------------------------------------
     const bool veh = lane < m;
     const unsigned long long VEH = m >= 64 ? ~0ull : (1ull << m) - 1ull;   // vehicle lanes
-    int t = 0, loc = 0, q = minpre ? 0 : k, M = 0;
+    // lrow: matrix row offset of the vehicle's location (the depot's, 0, at
+    // the start; lanes past m stay there and read valid entries)
+    int t = 0, lrow = 0, q = minpre ? 0 : k, M = 0;
     int used = 0;
     int Lsum = 0, nsched = 0;
     // dok / pok: this lane's vehicle can take a drop (holds a resource, or
@@ -262,17 +264,18 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 const int ci = (int)((unsigned)oi >> 1) + 1;
                 const bool isPi = oi & 1;
                 // SelectVehicle: least completion time, ties to the first
-                // vehicle at or after the hint vehicle (cyclically).  Lanes
-                // past m keep loc = 0 and read a valid entry; a drop reads
-                // ready[] too and ignores it.
-                const int arr = t + (int)D[loc * N1 + ci];
+                // vehicle at or after the hint vehicle (cyclically).  The
+                // travel time is read at a 32-bit byte offset from the
+                // uniform matrix base; a drop reads ready[] too and ignores it.
+                const uint32_t eoff = (uint32_t)(lrow + ci) * (uint32_t)sizeof(DT);
+                const int arr = t + (int)*reinterpret_cast<const DT*>(reinterpret_cast<const unsigned char*>(D) + eoff);
                 const int r = lds_load(&ready[ci]);
                 const int key = isPi ? (arr > r ? arr : r) : arr;
                 const int kv = (isPi ? pok : dok) ? key : INT_MAX;
                 int ks, vs;
                 // hint-first rule: the hint vehicle, if it can take the op
-                const int kh = a.hint_first ? __builtin_amdgcn_readlane(kv, hi) : INT_MAX;
-                if (kh != INT_MAX) {
+                const int kh = kHintFirst ? __builtin_amdgcn_readlane(kv, hi) : INT_MAX;
+                if (kHintFirst && kh != INT_MAX) {
                     ks = kh;
                     vs = hi;
                 } else if constexpr (kPacked) {
@@ -289,11 +292,17 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                     vs = __ffsll((long long)(upper ? upper : tie)) - 1;
                 }
                 const bool me = lane == vs;
-                // a drop on an empty vehicle preloads one resource
-                const int pre = (!isPi && __builtin_amdgcn_readlane(q, vs) == 0) ? 1 : 0;
+                // a drop on an empty vehicle preloads one resource (the
+                // chosen vehicle's update computed in every lane, then kept
+                // in its lane by selects)
+                const int qv = __builtin_amdgcn_readlane(q, vs);
+                const int pre = (int)(!isPi & (qv == 0));
                 Lsum += pre;
-                q += me ? (isPi ? 1 : pre - 1) : 0;
-                M = me ? (isPi ? (q > M ? q : M) : M + pre) : M;
+                const int qn = q + (isPi ? 1 : pre - 1);
+                const int Mp = qn > M ? qn : M;
+                const int Mn = isPi ? Mp : M + pre;
+                q = me ? qn : q;
+                M = me ? Mn : M;
                 // a drop publishes its ready time; a pickup writes the unused
                 // depot slot (same address and value in every lane)
                 lds_store(&ready[isPi ? 0 : ci], ks + pci);
@@ -301,7 +310,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
                 // match is a drop lane, whose bit is never read)
                 DD |= __builtin_amdgcn_ballot_w64(o == oi + 1);
                 t = me ? ks : t;
-                loc = me ? ci : loc;
+                lrow = me ? ci * N1 : lrow;
                 used |= me ? 1 : 0;
                 if constexpr (kLog) log[nsched] = (uint32_t)((ci << 1) | (int)isPi) | ((uint32_t)vs << 16);
                 ++nsched;
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
     }
 
     // ---- 4. makespan, fitness, optional sequences ---------------------------------
-    int ret = (veh && used) ? t + (int)D[loc * N1] : 0;
+    int ret = (veh && used) ? t + (int)D[lrow] : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ret = max(ret, __shfl_xor(ret, o, 64));
     if (lane == 0) {
@@ -366,15 +375,17 @@ __global__ __launch_bounds__(64) void decode_kernel(DecodeArgs a)
 
 // Workspace of one launch over B chromosomes: op orders, key flags and, when
 // the sequences are wanted, the schedule logs.
-template <typename DT>
+template <typename DT, bool kHintFirst>
 static const void* decode_kernel_for(bool small_m, bool packed, bool log)
 {
     if (small_m && packed)
-        return log ? (const void*)decode_kernel<DT, true, true, true> : (const void*)decode_kernel<DT, true, false, true>;
+        return log ? (const void*)decode_kernel<DT, true, true, true, kHintFirst>
+                   : (const void*)decode_kernel<DT, true, false, true, kHintFirst>;
     if (small_m)
-        return log ? (const void*)decode_kernel<DT, true, true, false>
-                   : (const void*)decode_kernel<DT, true, false, false>;
-    return log ? (const void*)decode_kernel<DT, false, true, false> : (const void*)decode_kernel<DT, false, false, false>;
+        return log ? (const void*)decode_kernel<DT, true, true, false, kHintFirst>
+                   : (const void*)decode_kernel<DT, true, false, false, kHintFirst>;
+    return log ? (const void*)decode_kernel<DT, false, true, false, kHintFirst>
+               : (const void*)decode_kernel<DT, false, false, false, kHintFirst>;
 }
 
 int64_t decode_ws_bytes(const vrprpd_set* set, int64_t B, bool by_inst, bool want_ops)
@@ -417,8 +428,7 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     DecodeArgs a{set->d_inst, set->d_dist, set->d_proc, inst, prio, hint, key_stride, fitness, makespan,
                  unscheduled, status, ops_out, rt_end_out, 2 * (int64_t)n_lds, (int64_t)(inst ? set->m_max
                                                                                              : set->host[0].m),
-                 B, set->num_inst, n_lds, cap, (int32_t)B, order, badkey, log,
-                 (flags & VRPRPD_DECODE_HINT_FIRST) ? 1 : 0};
+                 B, set->num_inst, n_lds, cap, (int32_t)B, order, badkey, log};
     auto launch = [&](const void* k, int lds) -> int {
         if (lds > 64 * 1024) VRP_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         return VRPRPD_OK;
@@ -429,8 +439,11 @@ int decode_launch(const vrprpd_set* set, int64_t B, const int32_t* inst, const f
     VRP_HIP(hipGetLastError());
     const bool small_m = (inst ? set->m_max : set->host[0].m) <= 16;
     const bool packed = set->time_bound < (int64_t(1) << 27);   // (time << 4) | 15 stays below 2^31
-    const void* kern = set->dist16 ? decode_kernel_for<uint16_t>(small_m, packed, log != nullptr)
-                                   : decode_kernel_for<int32_t>(small_m, packed, log != nullptr);
+    const bool hf = (flags & VRPRPD_DECODE_HINT_FIRST) != 0;
+    const void* kern = set->dist16 ? (hf ? decode_kernel_for<uint16_t, true>(small_m, packed, log != nullptr)
+                                         : decode_kernel_for<uint16_t, false>(small_m, packed, log != nullptr))
+                                   : (hf ? decode_kernel_for<int32_t, true>(small_m, packed, log != nullptr)
+                                         : decode_kernel_for<int32_t, false>(small_m, packed, log != nullptr));
     if ((rc = launch(kern, L.bytes))) return rc;
     void* kargs[] = {&a};
     VRP_HIP(hipLaunchKernel(kern, dim3((unsigned)B), dim3(64), kargs, (size_t)L.bytes, st));
