@@ -79,6 +79,27 @@ def test_decode_parity_without_sequences(orc, P, case):
         assert tuple(got[b]) == (r["fitness"], r["makespan"], r["unscheduled"], r["status"]), b
 
 
+@pytest.mark.parametrize("case", [c for c in DECODE_CASES if c[1] <= 16], ids=lambda c: f"n{c[0]}m{c[1]}lm{c[5]}")
+def test_decode_without_sequences_all_rules(orc, P, case):
+    """The launch without op sequences (the BRKGA generations' form) on every
+    m <= 16 case: a batch that is not a multiple of four, both vehicle rules,
+    with and without hints, a bad key in the last chromosome."""
+    n, m, k, R, rule, lm, B = case
+    B = min(B, 64) + 3
+    inst = synth.make_instance(n, m, k, R, rule, seed=7300 + n, load_model=lm)
+    prio, hint = synth.random_keys(B, n, seed=n + m + 1, special=B >= 8)
+    S = P.InstanceSet([inst])
+    for use_hint, flags in ((True, 0), (False, 0), (True, P.DECODE_HINT_FIRST), (False, P.DECODE_HINT_FIRST)):
+        out = P.brkga_decode_eval(S, dev(prio), dev(hint) if use_hint else None, flags=flags)
+        torch.cuda.synchronize()
+        got = np.stack([out["fitness"].cpu().numpy(), out["makespan"].cpu().numpy(),
+                        out["unscheduled"].cpu().numpy(), out["status"].cpu().numpy().view(np.uint32)], axis=1)
+        for b in range(B):
+            r = orc.decode(inst, prio[b], hint[b] if use_hint else None, flags=flags)
+            assert tuple(got[b]) == (r["fitness"], r["makespan"], r["unscheduled"], r["status"]), \
+                (b, use_hint, flags)
+
+
 def test_decode_parity_wide_distances(orc, P):
     """Travel times above 65535 keep the int32 distance layout in the decoder."""
     inst = synth.make_instance(80, 5, 4, 20, "2x", seed=7201)
