@@ -579,7 +579,8 @@ def small_configs(P, torch, reps=10):
     """Throughput at the two smaller workloads (HIP events on the launch
     stream, median of `reps`):
       depot + 16 customers (m = 2, k = 2, R = 4, base rule): vrprpd_eval on
-        4,096 random feasible solutions;
+        4,096 random feasible solutions, then 2,000 ALNS iterations of 32
+        chains from the paper's start (wall time);
       100 customers (m = 4, k = 5, R = 20, 2x rule): 65,536 ALNS neighbours of
         one solution as insertion tuples (vrprpd_insert_scan against a
         feasible solution with 5 customers removed), the same number of explicit
@@ -624,6 +625,21 @@ def small_configs(P, torch, reps=10):
                "eval_hbm_frac": (4 * n + 2 * m + 8) * B / (t * 1e-3) / HBM_PEAK,
                "eval_l2_gather_frac": B / (t * 1e-3) / (rate / (2 * n + 2 * m)),
                "l2_reads_per_s": rate}
+        if n == 16:
+            # 2,000 ALNS iterations of 32 chains from the paper's start (every
+            # slot pair priced at this size), as one timed region
+            st_, _ = paper_start_gpu(P, S, 32, P.alns_params(), 77)
+            ev0 = st_.state()["evals"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st_.step(2000)
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+            ev = st_.state()["evals"] - ev0
+            row.update({"alns_chains": 32, "alns_iterations": 2000, "alns_seconds": ta,
+                        "alns_iterations_per_s": 2000 / ta, "alns_evals_per_s": ev / ta,
+                        "alns_best": int(st_.state()["zb"].min())})
+            st_.close()
         if n == 100:
             g = synth.rng(n + 3)
             removed = sorted(int(c) for c in g.choice(np.arange(1, n + 1), size=5, replace=False))
