@@ -238,6 +238,14 @@ def test_insert_scan_matches_hand_built_solutions(orc):
         keys = sorted((int(mk[i]) << 32) | i for i in range(lo, hi) if st[i] == 0)
         keys = (keys + [INT64_MAX] * 3)[:3]
         assert list(top[s]) == keys
+    # a customer the base already serves cannot be inserted again, whatever
+    # the positions (a tuple error, not a cover error of the result)
+    served = sorted({x[0] for r in base for x in r})
+    extra = np.zeros(len(served), dtype=tuples.dtype)
+    for i, c in enumerate(served):
+        extra[i]["c"], extra[i]["vD"], extra[i]["pD"], extra[i]["vP"], extra[i]["pP"] = c, 0, 0, 0, 1
+    mk2, st2, _ = orc.insert_scan(inst, bops, brt[0], extra, np.array([0, len(extra)], np.int64))
+    assert np.all(st2 == BAD_TUPLE) and np.all(mk2 == INT32_MAX)
 
 
 def test_insert_position_semantics(orc):

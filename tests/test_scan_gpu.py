@@ -101,6 +101,25 @@ def test_scan_deadlock_tuples_and_reuse(orc, P):
     assert (ost & 8).any()
 
 
+def test_scan_served_customer_tuples(orc, P):
+    """Tuples that re-insert a customer the base already serves are tuple
+    errors (valid positions or not), mixed with ordinary tuples."""
+    inst = synth.make_instance(40, 3, 4, 12, "2x", seed=13)
+    bops, brt = make_base(inst, 7, 4)
+    ok = synth.random_tuples(bops, brt, 40, 3, 300, seed=8)
+    served = sorted({int(x) >> 1 for x in bops[:int(brt[-1])]})
+    bad = np.zeros(len(served), dtype=ok.dtype)
+    for i, c in enumerate(served):
+        bad[i]["c"], bad[i]["vD"], bad[i]["pD"], bad[i]["vP"], bad[i]["pP"] = c, 0, 0, 0, 1
+    tuples = np.concatenate([ok, bad])[synth.rng(9).permutation(len(ok) + len(bad))]
+    seg_off = np.array([0, 150, len(tuples)], np.int64)
+    S = P.InstanceSet([inst])
+    mk, st, top = run_scan(P, S, bops, brt, tuples, seg_off)
+    omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg_off)
+    assert np.array_equal(mk, omk) and np.array_equal(st, ost) and np.array_equal(top, otop)
+    assert (ost == 32).sum() >= len(served)
+
+
 def test_scan_bad_base(orc, P):
     inst = synth.make_instance(20, 2, 3, 6, "base", seed=12)
     bops, brt = make_base(inst, 5, 3)
