@@ -91,6 +91,22 @@ def test_sectors_hand_example(orc):
     assert list(s1[1:]) == [0, 1, 1, 1] and moves == 1
 
 
+def test_balancing_moves_the_customer_closest_to_half_the_gap(orc):
+    """Worked by hand: c1 at distance 100 (angle 0), c2..c6 at distance 10 at
+    90, 135, 225, 270, 315 degrees; p = (0, 40, 110, 0, 0, 0); w = 2 d + p =
+    200, 60, 130, 20, 20, 20.  Cut {1,2,3} | {4,5,6}: W = 390 | 60, gap 330.
+    |gap - 2w|: c1 70, c2 210, c3 70 -> tie, lower index: c1 moves (190 | 260).
+    Gap 70 from sector 1: c4, c5, c6 all at |70 - 40| = 30 -> c4 (210 | 240).
+    Gap 30: c5, c6 at 10 -> c5 (230 | 220).  Gap 10, 10 x 10 < 230: stop."""
+    pts = [(0, 0), (100, 0), (0, 10), (-7, 7), (-7, -7), (0, -10), (7, -7)]
+    inst = coords_instance(pts, p=[0, 40, 110, 0, 0, 0], m=2, k=3, R=6)
+    assert list(orc.cons_angle_order(inst)) == [1, 2, 3, 4, 5, 6]
+    assert [int(inst.d[0][c]) for c in range(1, 7)] == [100, 10, 10, 10, 10, 10]
+    s0, s1, moves = orc.cons_sectors(inst)
+    assert list(s0[1:]) == [0, 0, 0, 1, 1, 1]
+    assert list(s1[1:]) == [1, 0, 0, 0, 0, 1] and moves == 3
+
+
 def workloads(inst, sector, mv):
     w = 2 * inst.d[0, 1:].astype(np.int64) + inst.p[1:]
     W = np.zeros(mv, np.int64)
