@@ -38,6 +38,11 @@ def test_hand_worked_schedules():
     # c2: v1's next op after D2 is at 30 < 120: interleaved
     inst = line_instance([0, 100], m=2)
     assert solution_stats(inst, *pack([[(1, D), (2, P_)], [(2, D), (1, P_)]])) == (2, 1)
+    # the boundary: p1 = 10, p2 = 0; v0 = D1 (10), D2 (20); v1 = P1 (arrives
+    # 10, waits to 10 + 10 = 20), P2 (30).  v0's op after D1 is at 20, the same
+    # time as P1: not before it, so c1 is not interleaved; D2 is v0's last op
+    inst = line_instance([10, 0], m=2)
+    assert solution_stats(inst, *pack([[(1, D), (2, D)], [(1, P_), (2, P_)]])) == (2, 0)
 
 
 def test_unschedulable_solutions_have_no_statistics():

@@ -51,6 +51,27 @@ def test_stats_parity(orc, P, case):
     assert np.array_equal(got, expect(orc, inst, ops, rt))
 
 
+def test_stats_hand_worked_boundaries(orc, P):
+    """The oracle's hand-worked line schedules on the GPU, the time-equality
+    boundary of Interleaved among them (p1 = 10: the drop vehicle's next op
+    and the pickup both at time 20, not interleaved)."""
+    D, Pk = 0, 1
+    cases = [([100, 100], [[(1, D), (1, Pk)], [(2, D), (2, Pk)]], (0, 0)),
+             ([100, 100], [[(1, D), (2, D), (2, Pk), (1, Pk)], []], (0, 1)),
+             ([100, 100], [[(1, D), (2, D)], [(1, Pk), (2, Pk)]], (2, 1)),
+             ([0, 100], [[(1, D), (2, Pk)], [(2, D), (1, Pk)]], (2, 1)),
+             ([10, 0], [[(1, D), (2, D)], [(1, Pk), (2, Pk)]], (2, 0))]
+    for p, routes, want in cases:
+        x = np.arange(3) * 10
+        d = np.abs(x[:, None] - x[None, :]).astype(np.int32)
+        inst = synth.instance_from_matrix(d, np.array([0] + p, np.int32), 2, k=2, R=4)
+        ops = np.array([[(c << 1) | t for r in routes for c, t in r]], np.uint16)
+        rt = np.array([np.cumsum([len(r) for r in routes])], np.uint16)
+        cross, inter = P.vrprpd_solution_stats(P.InstanceSet([inst]), dev(ops), dev(rt))
+        got = (int(cross[0]), int(inter[0]))
+        assert got == want == orc.solution_stats(inst, ops[0], rt[0]), (p, routes)
+
+
 def test_stats_of_constructions_and_bad_inputs(orc, P):
     insts = [synth.make_instance(60, 5, 4, 20, "2x", seed=8101), synth.make_instance(30, 3, 3, 9, "5x", seed=8102)]
     S = P.InstanceSet(insts)
