@@ -13,16 +13,23 @@ of the path once on inputs already resident in HBM:
   3. brkga_decode_eval   a population of 4,096 chromosomes (2n keys + 2n hints)
      brkga_evolve        one generation (614 elites, 614 mutants, rho_e = 0.7)
   4. alns_step           one ALNS iteration of 32 chains (budget 16,384 tuples)
-`value` counts every exact schedule evaluation of the step (explicit
-candidates, tuples, decoded chromosomes and the ALNS iteration's tuples and
-removal gains) per second of step wall time.  In the timed steps the ALNS
-iteration runs on a second stream, concurrently with stages 1, 2 and 3 on the
-first (the stages share no data; the streams join at the end of each step);
-`components_ms` times the stages one after another in as many further steps.
+`value` is the evaluator's rate: complete n = 1000 candidates evaluated per
+second by the vrprpd_eval launches of the timed steps (HIP events on their
+stream); `all_evals_per_s` counts every exact schedule evaluation of the step
+(explicit candidates, tuples, decoded chromosomes and the ALNS iteration's
+tuples and removal gains) per second of step wall time.  In the timed steps
+the ALNS iteration runs on a second stream, concurrently with stages 1, 2 and
+3 on the first (the stages share no data; the streams join at the end of each
+step); `components_ms` times the stages one after another in as many further
+steps.  `roofline` is the evaluation kernel's (HBM bytes, with the measured
+L2 random-read ceiling as the secondary bound), `roofline_components` the
+scan's (LDS) and the decoder's (HBM).
 
-Also reported: the wall time for GPU ALNS to reach the best makespan the CPU
-oracle's ALNS finds in 2000 iterations on the depot + 16 customer instance,
-and the CPU baseline (the oracle, single-threaded, on a bounded sample).
+Also reported, each as its own phase (--phases): races of the two-stage method
+to the oracle's best makespans (16, 100 and 1000 customers), the smaller
+workloads (16 and 100 customers), the construction heuristics, the batched and
+learned forms, the processing-time hypothesis sweep, and the CPU baseline (the
+oracle on one core and on the process's share of cores, on a bounded sample).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -1055,30 +1062,34 @@ def main():
             phases -= {"construction", "batched", "hypothesis", "learned"}
         if args.no_cpu_baseline:
             phases.discard("cpu")
+    def phase(key, msg, fn):
+        """One reported phase after the timed steps: a Python error in it is
+        recorded in its place, so the line is still printed."""
+        if msg:
+            log(msg)
+        try:
+            out[key] = fn()
+        except Exception as exc:   # noqa: BLE001 -- reported, not hidden
+            log(f"{key} failed: {exc!r}")
+            out[key] = {"error": repr(exc)}
+
     if "race" in phases:
-        log("time to oracle-best (n=16)")
-        out["time_to_oracle_best"] = time_to_oracle_best(P, torch)
-        log("time to oracle-best (n=100, n=1000)")
-        out["time_to_oracle_best_large"] = race_to_oracle(P, torch)
+        phase("time_to_oracle_best", "time to oracle-best (n=16)", lambda: time_to_oracle_best(P, torch))
+        phase("time_to_oracle_best_large", "time to oracle-best (n=100, n=1000)", lambda: race_to_oracle(P, torch))
     if "small" in phases:
-        log("smaller workloads (16 and 100 customers)")
-        out["small_configs"] = small_configs(P, torch)
+        phase("small_configs", "smaller workloads (16 and 100 customers)", lambda: small_configs(P, torch))
     if "construction" in phases:
-        log("construction heuristics")
-        out["construction"] = construction(P, torch)
+        phase("construction", "construction heuristics", lambda: construction(P, torch))
     if "batched" in phases:
-        out["batched_form"] = batched_form(P, torch)
+        phase("batched_form", None, lambda: batched_form(P, torch))
     if "hypothesis" in phases:
-        log("processing-time hypothesis")
-        out["hypothesis"] = hypothesis(P, torch)
+        phase("hypothesis", "processing-time hypothesis", lambda: hypothesis(P, torch))
     if "learned" in phases:
-        out["learned_form"] = learned_form(P, torch)
+        phase("learned_form", None, lambda: learned_form(P, torch))
     elif "mlp" in phases:   # the network's GEMM rate alone (the learned form reports it too)
-        log("network GEMM rate")
-        out["mlp_roofline"] = mlp_roofline(P, torch)
+        phase("mlp_roofline", "network GEMM rate", lambda: mlp_roofline(P, torch))
     if "cpu" in phases:
-        log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds)
+        phase("cpu_baseline", "cpu baseline", lambda: cpu_baseline(inst, w["ops"], w["rt"], args.cpu_seconds))
     print(json.dumps(out), flush=True)
 
 
