@@ -593,8 +593,10 @@ def small_configs(P, torch, reps=10):
         feasible solution with 5 customers removed), the same number of explicit
         random candidates (vrprpd_eval), and one BRKGA generation of 1,024
         chromosomes (brkga_decode_eval + brkga_evolve).
-    With the evaluation's rooflines: HBM bytes 4n + 2m + 8 per candidate and
-    the measured L2 random-read ceiling at 2n + 2m reads per candidate."""
+    With the evaluation's rooflines (HBM bytes 4n + 2m + 8 per candidate; the
+    measured L2 random-read ceiling at 2n + 2m reads per candidate), the
+    scan's (20 B of LDS per customer of base + tuple) and the generation's
+    (16n + 20 B of HBM per chromosome, keys read and outputs written)."""
     import synth
     stream = torch.cuda.current_stream()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -660,7 +662,9 @@ def small_configs(P, torch, reps=10):
             seg_off = np.concatenate([[0], np.nonzero(np.diff(cs))[0] + 1, [T]]).astype(np.int64)
             d_b, d_br, d_seg, d_t = dev(fo), dev(frt[0]), dev(seg_off), dev(tuples.view(np.uint8))
             ts = timed(lambda: P.vrprpd_insert_scan(S, d_b, d_br, d_seg, d_t))
-            row.update({"neighbours": T, "scan_ms": ts, "scan_per_s": T / (ts * 1e-3)})
+            base_c = int(frt[0][-1]) // 2   # customers in the base
+            row.update({"neighbours": T, "scan_ms": ts, "scan_per_s": T / (ts * 1e-3),
+                        "scan_lds_frac": 20 * (base_c + 1) * T / (ts * 1e-3) / LDS_PEAK})
             Np = 1024
             prio, hint = synth.random_keys(Np, n, seed=n + 5)
             d_p, d_h = dev(prio), dev(hint)
@@ -674,7 +678,8 @@ def small_configs(P, torch, reps=10):
                 P.brkga_evolve(d_p, d_h, out_["fitness"], ne, nm, 0.7, 5, 0, prio_out=p2, hint_out=h2,
                                rank_out=rk)
             tg = timed(gen)
-            row.update({"population": Np, "generation_ms": tg, "chromosomes_per_s": Np / (tg * 1e-3)})
+            row.update({"population": Np, "generation_ms": tg, "chromosomes_per_s": Np / (tg * 1e-3),
+                        "generation_hbm_frac": (16 * n + 20) * Np / (tg * 1e-3) / HBM_PEAK})
         out[name] = row
     return out
 
