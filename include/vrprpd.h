@@ -121,7 +121,13 @@ int vrprpd_set_info(const vrprpd_set* set, int32_t* num_inst, int32_t* n_max, in
  *   makespan  [B] int32 out
  *   status    [B] uint32 out
  * op_off/rt_off NULL with inst non-NULL requires every instance to share n, m.
- * Errors: EINVAL (NULL set or buffers with B > 0, B < 0, bad flags), EHIP.
+ * The launch shape (kernel form, candidates per wave, ops per sweep step) is
+ * the one vrprpd_autotune_eval kept or vrprpd_eval_set_shape pinned for this
+ * (n, m), else a default (see vrprpd_autotune_eval); every shape gives the
+ * same results bit for bit.
+ * Errors: EINVAL (NULL set or buffers with B > 0, B < 0, bad flags, or a
+ * shape whose LDS does not fit: n above about 6,700 for the staged form and
+ * 9,900 for the live-leg form with 16-lane groups), EHIP.
  */
 int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                 const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
