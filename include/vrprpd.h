@@ -127,7 +127,7 @@ int vrprpd_set_info(const vrprpd_set* set, int32_t* num_inst, int32_t* n_max, in
  * same results bit for bit.
  * Errors: EINVAL (NULL set or buffers with B > 0, B < 0, bad flags, or a
  * shape whose LDS does not fit: n above about 6,700 for the staged form and
- * 9,900 for the live-leg form with 16-lane groups), EHIP.
+ * 10,200 for the live-leg form with 16-lane groups), EHIP.
  */
 int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int64_t* op_off,
                 const uint16_t* ops, const int64_t* rt_off, const uint16_t* rt_end, int32_t flags,
@@ -139,7 +139,8 @@ int vrprpd_eval(const vrprpd_set* set, int64_t B, const int32_t* inst, const int
  * for more resident waves) x ops per lane per sweep step (2 or 4).  The two
  * forms compute the same thing: "staged" gathers every travel time of a
  * candidate into LDS before its timing sweep, "live legs" keeps only the op
- * codes in LDS (a third less at n = 1000, so more candidates stay resident)
+ * codes in LDS (packed 12 bits each below n = 2048: 7.0 instead of 12.3 KB per
+ * candidate at n = 1000, so more candidates stay resident)
  * and reads each travel time from the matrix as the sweep takes the op.
  * Without tuning, vrprpd_eval uses live legs when the staged layout of a
  * candidate exceeds 8 KB (about n > 650 with 16-bit travel times).  Runs

@@ -9,8 +9,8 @@
 // by the autotuner: "staged" (eval_kernel) gathers every travel time
 // d[prev][c] into LDS in phase 1, so the sweep reads only LDS; "live legs"
 // (eval_live_kernel) keeps only the op codes in LDS and reads each travel
-// time from the L2-resident matrix as the sweep takes its op -- a third less
-// LDS per candidate at n = 1000, so more candidates stay resident.
+// time from the L2-resident matrix as the sweep takes its op -- 7.0 instead of
+// 12.3 KB of LDS per candidate at n = 1000, so more candidates stay resident.
 #include "common.h"
 #include "sweep.h"
 
@@ -255,22 +255,99 @@ __global__ __launch_bounds__(64) void eval_kernel(EvalArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Live-leg form: phase 1 stages only the op codes (2 B per op) and the cover
-// bits; the sweep gathers each op's travel time d[prev][c] from the L2 in the
-// same round trip as its ready[] read.  8.3 KB of LDS per candidate at
-// n = 1000 instead of 12.3 KB, and the gathers spread over the sweep instead
-// of a burst before it.
+// Live-leg form: phase 1 stages only the op codes and the cover bits; the
+// sweep gathers each op's travel time d[prev][c] from the L2 in the same
+// round trip as its ready[] read.  The cover bits share ready[]'s space (the
+// cover check is done before ready[] is written), and when every code fits
+// 12 bits (n < 2048) the codes are packed 12 bits each: 7.0 KB of LDS per
+// candidate at n = 1000 (12.3 KB staged), which is what sets how many
+// candidates stay resident.
 
-__host__ __device__ inline GroupLayout live_layout(int n_max)
+constexpr int kC12MaxN = 2047;   // codes (c << 1 | isP) below 4096
+
+__host__ __device__ inline int live_code_entries(int n_max) { return 2 * n_max + kStepOps + 8; }
+
+__host__ __device__ inline GroupLayout live_layout(int n_max, bool c12)
 {
     GroupLayout g;
     g.ready_off = 0;
-    g.bits_off = align16(4 * (n_max + 1));
-    g.ops_off = g.bits_off + align16(4 * ((2 * (n_max + 1) + 31) / 32));
-    // codes start up to 7 entries in, so that the vector stores are aligned
-    g.bytes = g.ops_off + align16(2 * (2 * n_max + kStepOps + 8));
+    g.bits_off = 0;
+    g.ops_off = align16(4 * (n_max + 1));
+    // 12-bit codes: a read of up to four codes from position p <= 2n + 6
+    // (the last op, shifted by up to 7) takes the words up to
+    // 12 (p + 2) / 32 + 1, and the writes stay below that
+    g.bytes = g.ops_off + (c12 ? align16(4 * ((12 * (2 * n_max + 8)) / 32 + 2))
+                               : align16(2 * live_code_entries(n_max)));
     return g;
 }
+
+// Op codes of one candidate in LDS, entry j at position j + sh (sh aligns
+// the vector stores of phase 1).
+template <bool kC12>
+struct LiveCodes;
+
+template <>
+struct LiveCodes<false> {
+    uint16_t* c;
+    __device__ __forceinline__ void init(unsigned char* base, int sh) { c = reinterpret_cast<uint16_t*>(base) + sh; }
+    __device__ __forceinline__ uint32_t get(int j) const { return c[j]; }
+    template <int K>
+    __device__ __forceinline__ void get_k(int j, uint32_t* cd) const
+    {
+#pragma unroll
+        for (int u = 0; u < K; ++u) cd[u] = c[j + u];
+    }
+    __device__ __forceinline__ void put(int j, uint32_t cd) { c[j] = (uint16_t)cd; }
+    // eight codes at j (j + sh a multiple of 8): 16-byte store
+    __device__ __forceinline__ void put8(int j, const uint32_t* cd)
+    {
+        *reinterpret_cast<uint4*>(c + j) = make_uint4(cd[0] | cd[1] << 16, cd[2] | cd[3] << 16, cd[4] | cd[5] << 16,
+                                                      cd[6] | cd[7] << 16);
+    }
+};
+
+template <>
+struct LiveCodes<true> {
+    uint32_t* w;
+    int sh;
+    __device__ __forceinline__ void init(unsigned char* base, int s) { w = reinterpret_cast<uint32_t*>(base); sh = s; }
+    // the 32 bits from bit b of the packed array
+    __device__ __forceinline__ uint32_t bits_at(int b) const
+    {
+        const uint32_t lo = w[b >> 5], hi = w[(b >> 5) + 1];
+        return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b & 31));
+    }
+    __device__ __forceinline__ uint32_t get(int j) const { return bits_at(12 * (j + sh)) & 0xFFFu; }
+    template <int K>
+    __device__ __forceinline__ void get_k(int j, uint32_t* cd) const
+    {
+        static_assert(K == 2 || K == 4, "two or four codes per read");
+        const int b = 12 * (j + sh);
+        const uint32_t y0 = bits_at(b);
+        cd[0] = y0 & 0xFFFu;
+        cd[1] = (y0 >> 12) & 0xFFFu;
+        if constexpr (K == 4) {
+            const uint32_t y1 = bits_at(b + 24);
+            cd[2] = y1 & 0xFFFu;
+            cd[3] = (y1 >> 12) & 0xFFFu;
+        }
+    }
+    // one code into a cleared field (it may straddle two words)
+    __device__ __forceinline__ void put(int j, uint32_t cd)
+    {
+        const int b = 12 * (j + sh), o = b & 31;
+        atomicOr(&w[b >> 5], cd << o);
+        if (o > 20) atomicOr(&w[(b >> 5) + 1], cd >> (32 - o));
+    }
+    // eight codes at j (j + sh a multiple of 8): three whole words
+    __device__ __forceinline__ void put8(int j, const uint32_t* cd)
+    {
+        uint32_t* q = w + 3 * ((j + sh) >> 3);
+        q[0] = cd[0] | cd[1] << 12 | cd[2] << 24;
+        q[1] = cd[2] >> 8 | cd[3] << 4 | cd[4] << 16 | cd[5] << 28;
+        q[2] = cd[5] >> 4 | cd[6] << 8 | cd[7] << 20;
+    }
+};
 
 // Cover bit of one code; returns the code, or 0 for a code outside [1, n].
 __device__ __forceinline__ uint32_t cover_code(uint32_t* bits, uint32_t cd, int n, bool live, bool& bad)
@@ -295,11 +372,10 @@ __device__ __forceinline__ int leg_at(const DT* D, uint32_t entry)
 // matrix as the ops are taken: lane v keeps the matrix row of its route's
 // last stop (the depot's at the start) for the next op's leg, so a step
 // reads its K codes from LDS, then their ready[] entries (LDS) and legs (L2)
-// together.  The codes array holds valid codes for K entries past the last
-// route.
-template <int GL, int K, typename DT>
-__device__ __forceinline__ SweepOut sweep_live(const uint16_t* codes, const DT* D, uint32_t N1, int* ready, int s,
-                                               int e)
+// together.  The code store holds valid codes (0) for K entries past the
+// last route.
+template <int GL, int K, typename DT, typename Codes>
+__device__ __forceinline__ SweepOut sweep_live(const Codes& C, const DT* D, uint32_t N1, int* ready, int s, int e)
 {
     SweepOut o{0, 0, 0, 0, false};
     int ptr = s;
@@ -309,8 +385,7 @@ __device__ __forceinline__ SweepOut sweep_live(const uint16_t* codes, const DT* 
         if (ptr < e) {
             uint32_t cd[K], row[K];
             int leg[K], r[K];
-#pragma unroll
-            for (int u = 0; u < K; ++u) cd[u] = codes[ptr + u];
+            C.template get_k<K>(ptr, cd);
 #pragma unroll
             for (int u = 0; u < K; ++u) {
                 // codes are 16-bit, so customers and n + 1 are below 2^16
@@ -335,14 +410,14 @@ __device__ __forceinline__ SweepOut sweep_live(const uint16_t* codes, const DT* 
     }
     // A deadlock stops the clocks but the load check covers whole routes.
     for (; ptr < e; ++ptr) {
-        o.w += (codes[ptr] & 1u) ? -1 : 1;
+        o.w += (C.get(ptr) & 1u) ? -1 : 1;
         o.wmax = o.w > o.wmax ? o.w : o.wmax;
         o.wmin = o.w < o.wmin ? o.w : o.wmin;
     }
     return o;
 }
 
-template <typename DT, int GL, int NG, int K, bool kOneInst>
+template <typename DT, int GL, int NG, int K, bool kOneInst, bool kC12>
 __global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
 {
     static_assert(NG * GL <= 64, "groups per wave");
@@ -355,7 +430,7 @@ __global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
     const int64_t b = (int64_t)blk * NG + grp;
     const bool live = b < a.B;
 
-    const GroupLayout L = live_layout(a.n_max);
+    const GroupLayout L = live_layout(a.n_max, kC12);
     unsigned char* gs = smem + (size_t)grp * a.group_bytes;
     int* ready = reinterpret_cast<int*>(gs + L.ready_off);
     uint32_t* bits = reinterpret_cast<uint32_t*>(gs + L.bits_off);
@@ -380,45 +455,31 @@ __global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
     if (total > 2 * n) bad = true;
     bool gbad = !live || group_ballot<GL>(bad) != 0;
 
-    // codes[j] = op j, placed so that codes + head is 16-byte aligned
+    // op j at position j + sh, so that the vector stores from `head` on align
     int head = (int)((8 - (((uintptr_t)ops >> 1) & 7)) & 7);
     head = head < total ? head : total;
-    uint16_t* codes = reinterpret_cast<uint16_t*>(gs + L.ops_off) + ((8 - head) & 7);
+    LiveCodes<kC12> C;
+    C.init(gs + L.ops_off, (8 - head) & 7);
 
-    // ---- phase 1: ready[], cover bits, op codes --------------------------
+    // ---- phase 1: cover bits and op codes, then ready[] ----------------------
     const int nwords = (2 * N1 + 31) / 32;
     for (int w = li; w < nwords; w += GL) bits[w] = 0u;
+    if constexpr (kC12) {   // the packed fields are or-ed into cleared words
+        uint4* z = reinterpret_cast<uint4*>(gs + L.ops_off);
+        const int nz = (L.bytes - L.ops_off) >> 4;
+        for (int q = li; q < nz; q += GL) z[q] = make_uint4(0u, 0u, 0u, 0u);
+    }
     wave_lds_fence();
     bool cbad = false;
     if (!gbad) {
-        {
-            const int4* P4 = reinterpret_cast<const int4*>(P);
-            int4* R4 = reinterpret_cast<int4*>(ready);
-            const int np4 = (N1 + 3) >> 2;
-            constexpr int VP = 8;
-            for (int q0 = li; q0 < np4; q0 += VP * GL) {
-                int4 x[VP];
-#pragma unroll
-                for (int v = 0; v < VP; ++v) {
-                    const int q = q0 + v * GL;
-                    x[v] = P4[q < np4 ? q : np4 - 1];
-                }
-#pragma unroll
-                for (int v = 0; v < VP; ++v) {
-                    const int q = q0 + v * GL;
-                    if (q < np4) R4[q] = make_int4(~x[v].x, ~x[v].y, ~x[v].z, ~x[v].w);
-                }
-            }
-        }
         const int nvec = (total - head) >> 3;
         const int tail0 = head + 8 * nvec;
         const int nscalar = head + (total - tail0);
         for (int t = li; t < nscalar; t += GL) {
             const int j = t < head ? t : tail0 + (t - head);
-            codes[j] = (uint16_t)cover_code(bits, ops[j], n, true, cbad);
+            C.put(j, cover_code(bits, ops[j], n, true, cbad));
         }
         const uint4* vec = reinterpret_cast<const uint4*>(ops + head);
-        uint4* cvec = reinterpret_cast<uint4*>(codes + head);
         constexpr int V = 8;
         for (int q0 = li; q0 < nvec; q0 += V * GL) {
             uint4 x[V];
@@ -431,20 +492,22 @@ __global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
             for (int v = 0; v < V; ++v) {
                 const int q = q0 + v * GL;
                 const bool in = q < nvec;
-                uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
+                const uint32_t w4[4] = {x[v].x, x[v].y, x[v].z, x[v].w};
+                uint32_t cd[8];
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    const uint32_t lo = cover_code(bits, w4[h] & 0xFFFFu, n, in, cbad);
-                    const uint32_t hi = cover_code(bits, w4[h] >> 16, n, in, cbad);
-                    w4[h] = lo | (hi << 16);
+                    cd[2 * h] = cover_code(bits, w4[h] & 0xFFFFu, n, in, cbad);
+                    cd[2 * h + 1] = cover_code(bits, w4[h] >> 16, n, in, cbad);
                 }
-                if (in) cvec[q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+                if (in) C.put8(head + 8 * q, cd);
             }
         }
     }
     // padding past the last route: the sweep reads its next K codes without
-    // testing the route's end
-    if (!gbad && li < K) codes[total + li] = 0;
+    // testing the route's end (the packed store was cleared)
+    if constexpr (!kC12) {
+        if (!gbad && li < K) C.put(total + li, 0u);
+    }
     wave_lds_fence();
     if (!gbad) {
         for (int c = 1 + li; c <= n; c += GL) {
@@ -453,18 +516,42 @@ __global__ __launch_bounds__(64) void eval_live_kernel(EvalArgs a)
         }
     }
     gbad = gbad || group_ballot<GL>(cbad) != 0;
+    wave_lds_fence();
+    // ready[c] = ~p_c ("not dropped yet"; the drop reads p_c back from it),
+    // over the cover bits.  The p row is 16-byte aligned and padded: int4
+    // loads, all of a lane's in flight together.
+    if (!gbad) {
+        const int4* P4 = reinterpret_cast<const int4*>(P);
+        int4* R4 = reinterpret_cast<int4*>(ready);
+        const int np4 = (N1 + 3) >> 2;
+        constexpr int VP = 8;
+        for (int q0 = li; q0 < np4; q0 += VP * GL) {
+            int4 x[VP];
+#pragma unroll
+            for (int v = 0; v < VP; ++v) {
+                const int q = q0 + v * GL;
+                x[v] = P4[q < np4 ? q : np4 - 1];
+            }
+#pragma unroll
+            for (int v = 0; v < VP; ++v) {
+                const int q = q0 + v * GL;
+                if (q < np4) R4[q] = make_int4(~x[v].x, ~x[v].y, ~x[v].z, ~x[v].w);
+            }
+        }
+    }
+    wave_lds_fence();
 
     // ---- phase 2: timing sweep ----------------------------------------------
     const bool veh = li < m;
     SweepOut o{0, 0, 0, 0, false};
-    if (!gbad) o = sweep_live<GL, K, DT>(codes, D, (uint32_t)N1, ready, veh ? s : 0, veh ? e : 0);
+    if (!gbad) o = sweep_live<GL, K, DT>(C, D, (uint32_t)N1, ready, veh ? s : 0, veh ? e : 0);
 
     uint32_t st = 0;
     int z = 0;
     if (!gbad) {
         st = load_status<GL>(o, veh, m, I.k, I.R, I.load_model);
         int ret = 0;
-        if (veh && e > s) ret = o.t + (int)D[(int64_t)(codes[e - 1] >> 1) * N1];
+        if (veh && e > s) ret = o.t + (int)D[(int64_t)(C.get(e - 1) >> 1) * N1];
         z = group_max<GL>(ret);
         if (o.dead) st |= VRPRPD_ST_DEADLOCK;
     }
@@ -487,7 +574,7 @@ struct LaunchShape {
 
 static int group_bytes_of(int n_max, int dist16, int live)
 {
-    if (live) return live_layout(n_max).bytes;
+    if (live) return live_layout(n_max, n_max <= kC12MaxN).bytes;
     return group_layout(n_max, dist16 ? OpStore<uint16_t>::kBytesPerOp : OpStore<int32_t>::kBytesPerOp).bytes;
 }
 
@@ -534,7 +621,11 @@ static LaunchShape eval_shape(int n_max, int m_max, int dist16, int ng, int step
 template <typename DT, int GL, int NG, int K>
 static int launch_eval(const EvalArgs& a, int lds, int live, hipStream_t stream)
 {
-    auto* k = live ? (a.inst ? eval_live_kernel<DT, GL, NG, K, false> : eval_live_kernel<DT, GL, NG, K, true>)
+    const bool c12 = a.n_max <= kC12MaxN;
+    auto* k = live ? (a.inst ? (c12 ? eval_live_kernel<DT, GL, NG, K, false, true>
+                                    : eval_live_kernel<DT, GL, NG, K, false, false>)
+                             : (c12 ? eval_live_kernel<DT, GL, NG, K, true, true>
+                                    : eval_live_kernel<DT, GL, NG, K, true, false>))
                    : (a.inst ? eval_kernel<DT, GL, NG, K, false> : eval_kernel<DT, GL, NG, K, true>);
     if (lds > 64 * 1024)
         VRP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),

@@ -20,8 +20,8 @@ def staged_bytes(n):   # one candidate of the staged evaluation, 16-bit times
     return a16(4 * (n + 1)) + a16(4 * ((2 * (n + 1) + 31) // 32)) + a16(4 * (2 * n + 8))
 
 
-def live_bytes(n):     # one candidate of the live-leg evaluation
-    return a16(4 * (n + 1)) + a16(4 * ((2 * (n + 1) + 31) // 32)) + a16(2 * (2 * n + 16))
+def live_bytes(n):     # one candidate of the live-leg evaluation (16-bit codes above n = 2047;
+    return a16(4 * (n + 1)) + a16(2 * (2 * n + 16))   # the cover bits share ready[]'s space)
 
 
 def scan_bytes(n):     # one scan block (4 waves of four 16-lane groups), 16-bit times
@@ -68,6 +68,31 @@ def test_eval_both_forms_at_the_staged_limit(orc, P):
     with pytest.raises(RuntimeError):
         P.vrprpd_eval_set_shape(S, n + 1, 16, 2, 4, 0)
     P.vrprpd_eval_set_shape(S, n + 1, 16, 2, 4, 1)      # the live form still fits
+
+
+@pytest.mark.parametrize("n", [2047, 2048])
+def test_eval_live_form_code_width_switch(orc, P, n):
+    """The live-leg form packs codes in 12 bits up to n = 2047 (the largest
+    code, 4095, fills the field) and keeps 16 bits from n = 2048; both against
+    the oracle, with partial solutions and cover errors in the batch."""
+    inst = synth.make_instance(n, 12, 6, 72, "2x", seed=9400 + n)
+    ops, rt = synth.random_candidates(inst, 40, seed=9401)
+    top = 2 * n + 1                                    # the pickup of customer n
+    assert (ops == top).any(axis=1).all()
+    bad = ops.copy()
+    bad[1, 5] = bad[1, 6]                              # a duplicate op
+    bad[2, 0] = (n + 1) << 1                           # a customer past n
+    ops2 = np.concatenate([ops, bad[1:3]])
+    rt2 = np.concatenate([rt, rt[1:3]])
+    S = P.InstanceSet([inst])
+    omk, ost = orc.eval_batch(inst, ops2, rt2)
+    assert (ost == 1).sum() == 2
+    for form in (0, 1):
+        P.vrprpd_eval_set_shape(S, n, 12, 0, 4, form)
+        mk, st = P.vrprpd_eval(S, dev(ops2), dev(rt2))
+        torch.cuda.synchronize()
+        assert np.array_equal(mk.cpu().numpy(), omk), form
+        assert np.array_equal(st.cpu().numpy().view(np.uint32), ost), form
 
 
 def test_eval_live_form_limit_is_refused(P):
