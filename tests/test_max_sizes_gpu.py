@@ -103,6 +103,28 @@ def test_eval_live_form_limit_is_refused(P):
         P.vrprpd_eval_set_shape(S, n + 1, 16, 2, 4, 1)
 
 
+def test_eval_live_form_at_the_largest_instance(orc, P):
+    """The largest instance the library accepts (n = 10,000, m = 64) in the
+    live-leg form (one 64-lane candidate per wave, 78 KB of LDS), against the
+    oracle, with cover errors in the batch."""
+    n, m = 10000, 64
+    assert 2 * live_bytes(n) <= LDS
+    inst = synth.make_instance(n, m, 8, 8 * m, "2x", seed=9500)
+    ops, rt = synth.random_candidates(inst, 6, seed=9501)
+    bad = ops.copy()
+    bad[0, 7] = bad[0, 8]                              # a duplicate op
+    bad[1, 3] = (n + 1) << 1                           # a customer past n
+    ops2, rt2 = np.concatenate([ops, bad[:2]]), np.concatenate([rt, rt[:2]])
+    S = P.InstanceSet([inst])
+    omk, ost = orc.eval_batch(inst, ops2, rt2)
+    assert (ost == 1).sum() == 2
+    P.vrprpd_eval_set_shape(S, n, m, 1, 4, 1)
+    mk, st = P.vrprpd_eval(S, dev(ops2), dev(rt2))
+    torch.cuda.synchronize()
+    assert np.array_equal(mk.cpu().numpy(), omk)
+    assert np.array_equal(st.cpu().numpy().view(np.uint32), ost)
+
+
 def test_decode_at_the_sort_limit(orc, P):
     """2n = 8,192 ops, the most one CU sorts; one customer more is refused."""
     n = 4096
