@@ -28,17 +28,21 @@ INT64_MAX = 2**63 - 1
 TUPLE_DTYPE = np.dtype([("c", "<u2"), ("vD", "u1"), ("vP", "u1"), ("pD", "<u2"), ("pP", "<u2")])
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle's C sources with gcc (plain -O2, no FP contraction)."""
+def build(verbose: bool = False, out: str | None = None, opt: str = "-O2", extra: tuple = ()) -> str:
+    """Compile the oracle's C sources with gcc (plain -O2, no FP contraction)
+    into ``out`` (default: the library :func:`lib` loads); ``opt`` and
+    ``extra`` change the optimisation level and add flags (the sanitizer
+    test builds a checked copy this way)."""
+    out = out or LIB_PATH
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+    tmp = out + ".tmp"
+    cmd = ["gcc", opt, "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", *extra,
            "-o", tmp] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class _Inst(C.Structure):
@@ -50,11 +54,14 @@ _lib = None
 
 
 def lib():
+    """The oracle's C core: ``liboracle.so`` (built on first use), or the
+    library named by VRPRPD_ORACLE_LIB (the sanitizer test's checked copy)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("VRPRPD_ORACLE_LIB") or LIB_PATH
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build()
-        _lib = C.CDLL(LIB_PATH)
+        _lib = C.CDLL(path)
         _declare(_lib)
     return _lib
 
