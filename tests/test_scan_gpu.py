@@ -158,3 +158,50 @@ def test_scan_split_segments(orc, P, bps):
     mk, st, top = run_scan(P, S, bops, brt, tuples, seg_off, blocks_per_seg=bps)
     omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg_off)
     assert np.array_equal(mk, omk) and np.array_equal(st, ost) and np.array_equal(top, otop)
+
+
+def test_scan_two_million_tuples_in_one_launch(orc, P):
+    """2^21 tuples in 2,048 segments over 8 bases of the 100-customer workload
+    (1 to 5 customers removed; each base admits feasible insertions) in one
+    launch.  The launch is 512 copies of the bases' tuple lists (4,096 tuples
+    in 4 uneven segments each) at random positions; every tuple's makespan
+    and status, and every segment's top-3 (keys carry the tuple's index in
+    the launch), against the oracle."""
+    inst = synth.make_instance(100, 4, 5, 20, "2x", seed=9650)
+    S = P.InstanceSet([inst])
+    picks = [(9660, 1), (9660, 3), (9661, 1), (9662, 1), (9663, 1), (9664, 1), (9665, 1), (9665, 5)]
+    nb, per = len(picks), 4096
+    bases, lists = [], []
+    for b, (seed, q) in enumerate(picks):
+        bops, brt = make_base(inst, seed, q)
+        tuples = synth.random_tuples(bops, brt, 100, 4, per, seed=9670 + b, invalid_frac=0.05)
+        cuts = np.sort(synth.rng(9680 + b).integers(1, per, size=3))
+        seg = np.concatenate([[0], cuts, [per]]).astype(np.int64)
+        omk, ost, otop = orc.insert_scan(inst, bops, brt, tuples, seg)
+        assert (ost == 0).sum() > 50 and (otop != INT64_MAX).any()
+        bases.append((bops, brt))
+        lists.append((tuples, seg, omk, ost, otop))
+    pick = synth.rng(9690).integers(0, nb, size=512)
+    T = per * len(pick)
+    tup = np.concatenate([lists[b][0] for b in pick])
+    seg_off = np.concatenate([[0]] + [lists[b][1][1:] + i * per for i, b in enumerate(pick)]).astype(np.int64)
+    seg_base = np.repeat(pick, 4).astype(np.int32)
+    b_off = np.concatenate([[0], np.cumsum([len(o) for o, _ in bases])[:-1]]).astype(np.int64)
+    b_ops = np.concatenate([o for o, _ in bases]).astype(np.uint16)
+    b_rt = np.concatenate([r for _, r in bases]).astype(np.uint16)
+    print(f"[scan large] T={T} segments={len(seg_off) - 1}", flush=True)
+    mk, st, top = P.vrprpd_insert_scan(S, dev(b_ops), dev(b_rt), dev(seg_off), dev(tup.view(np.uint8)),
+                                       num_bases=nb, base_inst=dev(np.zeros(nb, np.int32)),
+                                       base_op_off=dev(b_off), base_rt_off=dev(np.arange(nb, dtype=np.int64) * 4),
+                                       seg_base=dev(seg_base))
+    torch.cuda.synchronize()
+    mk, st, top = mk.cpu().numpy(), st.cpu().numpy().view(np.uint32), top.cpu().numpy()
+    emk = np.concatenate([lists[b][2] for b in pick])
+    est = np.concatenate([lists[b][3] for b in pick])
+    bad = np.nonzero((mk != emk) | (st != est))[0]
+    assert bad.size == 0, (bad.size, int(bad[0]))
+    for i, b in enumerate(pick):
+        otop = lists[b][4].copy()
+        real = otop != INT64_MAX
+        otop[real] += i * per           # the tuple index in the low 32 bits moves with the copy
+        assert np.array_equal(top[4 * i:4 * i + 4], otop), i
