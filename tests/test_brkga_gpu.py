@@ -253,3 +253,43 @@ def test_packed_and_plain_vehicle_minimum_agree_on_ties(orc, P, flags):
     f = a["fitness"].cpu().numpy()
     for i in range(0, B, 16):
         assert f[i] == orc.decode(inst, prio[i], hint[i], flags=flags)["fitness"], i
+
+
+def test_decode_a_quarter_million_chromosomes_in_one_launch(orc, P):
+    """2^18 chromosomes of the 100-customer workload (m = 4, k = 5, R = 20,
+    2x rule) in one launch per vehicle rule, each a copy of one of 1,024
+    oracle-decoded bases (special keys among them) at a random position:
+    fitness, makespan, unscheduled count, status and the op sequences of
+    every chromosome against the oracle."""
+    n, m = 100, 4
+    inst = synth.make_instance(n, m, 5, 20, "2x", seed=9750)
+    S = P.InstanceSet([inst])
+    prio, hint = synth.random_keys(1024, n, seed=9751, special=True)
+    B = 1 << 18
+    src = synth.rng(9752).integers(0, 1024, size=B)
+    d_prio, d_hint = dev(prio[src]), dev(hint[src])
+    pos = np.arange(2 * n)[None, :]
+    for flags in (0, P.DECODE_HINT_FIRST):
+        ref = [orc.decode(inst, prio[b], hint[b], want_ops=True, flags=flags) for b in range(1024)]
+        ef = np.array([r["fitness"] for r in ref])[src]
+        emk = np.array([r["makespan"] for r in ref])[src]
+        eun = np.array([r["unscheduled"] for r in ref])[src]
+        est = np.array([r["status"] for r in ref], np.uint32)[src]
+        ert = np.stack([np.zeros(m, np.uint16) if r["status"] & 16 else r["rt_end"] for r in ref])
+        eops = np.zeros((1024, 2 * n), np.uint16)
+        for b, r in enumerate(ref):
+            eops[b, :len(r["ops"])] = r["ops"]
+        assert (est == 0).sum() > B // 4 and (est == 16).any()
+        print(f"[decode large] B={B} flags={flags}", flush=True)
+        out = P.brkga_decode_eval(S, d_prio, d_hint, want_ops=True, flags=flags)
+        torch.cuda.synchronize()
+        assert np.array_equal(out["fitness"].cpu().numpy(), ef), flags
+        assert np.array_equal(out["makespan"].cpu().numpy(), emk), flags
+        assert np.array_equal(out["unscheduled"].cpu().numpy(), eun), flags
+        assert np.array_equal(out["status"].cpu().numpy().view(np.uint32), est), flags
+        rt = out["rt_end"].cpu().numpy()
+        assert np.array_equal(rt, ert[src]), flags
+        ops = out["ops"].cpu().numpy()
+        L = rt[:, -1].astype(np.int64)
+        live = pos < L[:, None]
+        assert np.array_equal(np.where(live, ops, 0), np.where(live, eops[src], 0)), flags
