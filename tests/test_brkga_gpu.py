@@ -121,7 +121,7 @@ def test_decode_parity_wide_distances(orc, P):
                 assert np.array_equal(out["ops"][b].cpu().numpy()[:L], r["ops"]), b
 
 
-@pytest.mark.parametrize("Np", [1024, 4096, 5000], ids=lambda x: f"Np{x}")
+@pytest.mark.parametrize("Np", [1024, 4096, 5000, 65536], ids=lambda x: f"Np{x}")
 def test_evolve_parity(orc, P, Np):
     """Ranking by the block-wide sort (Np <= 4096) and by counting (larger)."""
     n = 100
