@@ -293,3 +293,40 @@ def test_autotune_keeps_the_trajectory(orc, P):
     a.close()
     b.close()
     c.close()
+
+
+def test_batched_state_of_128_uneven_instances(orc, P):
+    """One ALNS state over 128 instances of uneven size (the batched form's
+    generator, n in [17, 300]; 4 chains each, best-solution import every 4
+    iterations) from the paper's sweep construction: every chain's trace,
+    final temperature and weights (fp64 bits) and best makespan equal the
+    oracle's run of that instance with the same chain ids."""
+    insts = synth.batched_instances(count=128, seed=9300, n_min=17, n_max=300)
+    S = P.InstanceSet(insts)
+    cpi, iters, seed = 4, 8, 321
+    kw = dict(tuple_budget=1024, import_interval=4)
+    N, Mx = S.n_max, S.m_max
+    starts = [orc.construct(x, 0) for x in insts]
+    ops = np.zeros((len(insts), 2 * N), np.uint16)
+    rts = np.zeros((len(insts), Mx), np.uint16)
+    for i, (o, r) in enumerate(starts):
+        assert orc.eval_one(insts[i], o, r)[1] == 0
+        ops[i, :len(o)] = o
+        rts[i, :len(r)] = r
+    print(f"[alns batched] {len(insts)} instances x {cpi} chains x {iters} iterations", flush=True)
+    st = P.AlnsState(S, list(range(len(insts))), cpi, P.alns_params(**kw), seed, torch.from_numpy(ops).cuda(),
+                     torch.from_numpy(rts).cuda())
+    tr = st.set_trace(iters)
+    st.step(iters)
+    torch.cuda.synchronize()
+    got, info = tr.cpu().numpy(), st.state()
+    for k, x in enumerate(insts):
+        ref = orc.alns_run(x, orc.alns_params(**kw), cpi, iters, seed, starts[k][0], starts[k][1], trace=True,
+                           chain0=k * cpi)
+        sl = slice(k * cpi, (k + 1) * cpi)
+        assert np.array_equal(got[sl], ref["trace"]), k
+        assert np.array_equal(info["zb"][sl], ref["best_mk"]), k
+        assert np.array_equal(info["z"][sl], ref["z"]), k
+        for key in ("T", "wD", "wR"):
+            assert np.array_equal(info[key][sl].view(np.uint64), ref[key].view(np.uint64)), (k, key)
+    st.close()
