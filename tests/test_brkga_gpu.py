@@ -215,6 +215,44 @@ def test_batched_populations_match_oracle(orc, P, graph, flags):
     st.close()
 
 
+def test_batched_populations_of_96_uneven_instances(orc, P):
+    """One batched BRKGA state over 96 instances of uneven size (the batched
+    form's generator, n in [17, 200]; Np = 64, 4 generations, hint-first rule,
+    graph replay): every population and best fitness equals the oracle's
+    single-population run of that instance with its seed."""
+    insts = synth.batched_instances(count=96, seed=9400, n_min=17, n_max=200)
+    S = P.InstanceSet(insts)
+    Np, gens, seed, flags = 64, 4, 4242, 1
+    ne, nm = orc.brkga_sizes(Np)
+    stride = 2 * S.n_max
+    g = np.random.Generator(np.random.Philox(key=78))
+    p0 = np.zeros((len(insts) * Np, stride), np.float32)
+    h0 = np.zeros((len(insts) * Np, stride), np.float32)
+    for p, inst in enumerate(insts):
+        p0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
+        h0[p * Np:(p + 1) * Np, :2 * inst.n] = g.random((Np, 2 * inst.n), dtype=np.float32)
+    print(f"[brkga batched] {len(insts)} instances x Np {Np} x {gens} generations", flush=True)
+    st = P.BrkgaState(S, list(range(len(insts))), Np, ne, nm, 0.7, seed, dev(p0), dev(h0), decode_flags=flags)
+    st.step(gens, graph=True)
+    torch.cuda.synchronize()
+    best, _, _ = st.best()
+    pop_p, pop_h = st.population()
+    pop_p, pop_h = pop_p.cpu().numpy(), pop_h.cpu().numpy()
+    for p, inst in enumerate(insts):
+        G = 2 * inst.n
+        op_ = p0[p * Np:(p + 1) * Np, :G].copy()
+        oh_ = h0[p * Np:(p + 1) * Np, :G].copy()
+        bf = np.iinfo(np.int64).max
+        for gen in range(gens):
+            fit = orc.decode_batch(inst, op_, oh_, flags=flags)[0]
+            bf = min(bf, int(fit.min()))
+            op_, oh_, _ = orc.brkga_evolve(op_, oh_, fit, ne, nm, orc.rho_threshold(0.7), P.pop_seed(seed, p), gen)
+        assert best[p] == bf, (p, best[p], bf)
+        assert np.array_equal(pop_p[p * Np:(p + 1) * Np, :G].view(np.uint32), op_.view(np.uint32)), p
+        assert np.array_equal(pop_h[p * Np:(p + 1) * Np, :G].view(np.uint32), oh_.view(np.uint32)), p
+    st.close()
+
+
 @pytest.mark.parametrize("flags", [0, 1], ids=["selectvehicle", "hintfirst"])
 def test_packed_and_plain_vehicle_minimum_agree_on_ties(orc, P, flags):
     """The decoder's two vehicle-minimum paths (packed time << 4 | rank keys
